@@ -1,0 +1,244 @@
+/*
+ * purimi.h -- C ABI of the MI355X (gfx950) library for the sparse radio
+ * interferometric imaging path of Pratley et al., "Distributed and parallel
+ * sparse convex optimization for radio interferometry with PURIFY".
+ *
+ * The library computes, on one GPU:
+ *   Phi = W G F Z S           measurement operator, eq. (matrix_equation)
+ *   Phi^dagger                its adjoint (dirty map), same section
+ *   Psi, Psi^dagger           SARA dictionary: Dirac + Daubechies 1..8
+ *                             (Sections "Analysis and Synthesis" and
+ *                             "MPI Wavelet Operator Benchmarks")
+ *   S_lambda                  soft thresholding (Section "Promoting Sparsity")
+ *   P_B                       l2-ball projection (eq. l2ball_prox)
+ *   Algorithm 1               Dual Forward-Backward ADMM
+ *
+ * Conventions shared by every call
+ *   - Array arguments are DEVICE pointers owned by the caller, unless stated
+ *     as host. Element type follows the precision: PR_F32 -> float and
+ *     complex float (two floats, re then im); PR_F64 -> double and complex
+ *     double. Arrays are contiguous.
+ *   - Image x: real, n*n values, row-major x[iy*n + ix]; the centred pixel
+ *     offsets are p_x = ix - n/2 (pairs with u) and p_y = iy - n/2 (pairs
+ *     with v).
+ *   - Visibilities: complex, M values. Baselines uv: M pairs (u, v) of the
+ *     precision's real type, in radians per pixel, each in [-pi, pi).
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream). Every
+ *     call only enqueues work on it and returns, unless its comment says it
+ *     synchronises. Kernel faults surface at the caller's next
+ *     synchronisation and as PR_EHIP from the next call.
+ *   - Workspaces: the library allocates no device memory. Each plan reports
+ *     the bytes it needs (persistent: kept for the plan's life; scratch:
+ *     reused by every call on the plan) and the caller passes them in,
+ *     256-byte aligned. Calls on one plan must be ordered on one stream.
+ *   - Return value: PR_OK or an error code; pr_last_error() gives a message
+ *     (thread-local). On error nothing has been enqueued.
+ */
+#ifndef PURIMI_H
+#define PURIMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_OK 0
+#define PR_EINVAL 1        /* invalid argument (shape, null pointer, range)  */
+#define PR_EWORKSPACE 2    /* workspace pointer missing or misaligned         */
+#define PR_EHIP 3          /* a HIP runtime call failed                        */
+#define PR_EUNSUPPORTED 4  /* valid request outside what this build supports  */
+
+#define PR_F32 0
+#define PR_F64 1
+
+/* Text of the last error on this thread ("" if none). */
+const char* pr_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int pr_version(void);
+
+/* ------------------------------------------------------------------------
+ * Measurement operator Phi = W G F Z S (eq. matrix_equation).
+ *   S: gridding correction, divides pixel p by the Kaiser-Bessel kernel's
+ *      Fourier transform at p/K;
+ *   Z: zero padding of the n x n image to the K x K grid, K = oversample*n,
+ *      pixel p placed at grid index p mod K;
+ *   F: unnormalised 2-D FFT, sign e^{-2 pi i (.)} as in eq. (meas_eq);
+ *   G: interpolation off the grid with the Kaiser-Bessel kernel of support
+ *      J, pre-sampled at D samples per grid cell on 0 <= |t| <= J/2 and read
+ *      by nearest sample (Section "Kernel Pre-Sampling"). A visibility at
+ *      grid coordinate s = u K / (2 pi) (FP64) uses cells
+ *      floor(s) - J/2 + 1 + a, a = 0..J-1 (mod K), and for tap a the sample
+ *      nearest to |s - cell| * D, ties to the larger distance;
+ *   W: real per-visibility weights.
+ * Visibility arrays passed to phi_* calls are in PLAN ORDER: the plan sorts
+ * the visibilities by grid tile; pr_phi_plan_perm gives the permutation.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n;          /* image side; power of two, 8 <= n <= 4096           */
+  int32_t oversample; /* K = oversample * n; must be 2                      */
+  int32_t J;          /* kernel support: 2, 4, 6 or 8                       */
+  int32_t D;          /* table samples per grid cell, 1 <= D <= 1000000     */
+  int64_t M;          /* visibilities, 0 <= M < 2^31                        */
+  int32_t prec;       /* PR_F32 or PR_F64                                    */
+  int32_t tile;       /* tile side in grid cells: 0 = default, else 8/16/32  */
+} pr_phi_desc;
+
+typedef struct pr_phi_plan_t* pr_phi_plan;
+
+/* Workspace bytes a plan for *desc needs. Host only, no GPU call. */
+int pr_phi_plan_sizes(const pr_phi_desc* desc, size_t* persistent_bytes,
+                      size_t* scratch_bytes);
+
+/* Build a plan: the kernel table, correction and FFT twiddles (computed on
+ * the GPU in FP64), the tile sort of the visibilities and the gridding work
+ * list. uv: M (u,v) pairs in user order; w: M real weights or NULL for 1.
+ * Synchronises the stream once (to read the work-list length). The plan
+ * keeps its own sorted copy of uv and w in the persistent workspace. */
+int pr_phi_plan_create(const pr_phi_desc* desc, const void* uv, const void* w,
+                       void* persistent_ws, void* scratch_ws, void* stream,
+                       pr_phi_plan* out);
+
+/* Release the host-side plan object (the caller frees the workspaces). */
+int pr_phi_plan_destroy(pr_phi_plan plan);
+
+/* Device pointer to int32 perm[M]: plan position k holds user visibility
+ * perm[k] (y_plan[k] = y_user[perm[k]]). Valid for the plan's lifetime. */
+int pr_phi_plan_perm(pr_phi_plan plan, const int32_t** perm);
+
+/* Copy the permutation into the caller's device buffer dst (int32[M]),
+ * enqueued on stream. */
+int pr_phi_plan_perm_copy(pr_phi_plan plan, int32_t* dst, void* stream);
+
+/* Number of gridding work items (tile chunks) the plan built. Host only. */
+int pr_phi_plan_items(pr_phi_plan plan, int64_t* items);
+
+/* y = Phi x. x: real[n*n]; y: complex[M] in plan order. */
+int pr_phi_apply(pr_phi_plan plan, const void* x, void* y, void* stream);
+
+/* x = Re(Phi^dagger y), the adjoint of Phi on real images (dirty map for
+ * weighted data y). y: complex[M] in plan order; x: real[n*n]. */
+int pr_phi_adjoint(pr_phi_plan plan, const void* y, void* x, void* stream);
+
+/* The two factors of Phi, for timing and for callers that keep the grid:
+ * pr_phi_fzs:         plan grid = F Z S x
+ * pr_phi_gw:          y = W G (plan grid)
+ * pr_phi_gw_adjoint:  plan grid = G^T W y   (deterministic binned gridding)
+ * pr_phi_fzs_adjoint: x = Re(S Z^T F^H plan grid)
+ * pr_phi_apply == fzs then gw; pr_phi_adjoint == gw_adjoint then fzs_adjoint. */
+int pr_phi_fzs(pr_phi_plan plan, const void* x, void* stream);
+int pr_phi_gw(pr_phi_plan plan, void* y, void* stream);
+int pr_phi_gw_adjoint(pr_phi_plan plan, const void* y, void* stream);
+int pr_phi_fzs_adjoint(pr_phi_plan plan, void* x, void* stream);
+
+/* Operator norm ||Phi|| by the power method on Re Phi^dagger Phi (Section
+ * "Distributed Images"): x0 = constant image of unit norm, x <- A x / ||A x||
+ * (norms in FP64), iters steps, result sqrt(||A x||) written to *norm (host).
+ * vis_ws: device scratch of M complex values. Synchronises the stream. */
+int pr_phi_norm(pr_phi_plan plan, int32_t iters, void* vis_ws, double* norm,
+                void* stream);
+
+/* ------------------------------------------------------------------------
+ * SARA dictionary (Sections "Analysis and Synthesis", "Distributed Wavelet
+ * Operator"): bases selected by basis_mask (bit 0 Dirac, bit k = Daubechies
+ * k, k = 1..8); each Daubechies basis is the periodic, orthonormal 2-D
+ * separable transform to `levels` levels (Mallat layout: rows then columns
+ * of the current low-low block, low half first), with the minimum-phase dbk
+ * filter. The dictionary is scaled by 1/sqrt(nb) (nb = bases selected) so
+ * Psi Psi^dagger = I.
+ *   alpha: real[nb][n*n], bases in increasing bit order.
+ * ---------------------------------------------------------------------- */
+typedef struct pr_psi_plan_t* pr_psi_plan;
+
+int pr_psi_plan_sizes(int32_t n, int32_t levels, uint32_t basis_mask, int32_t prec,
+                      size_t* persistent_bytes, size_t* scratch_bytes);
+/* Derives the Daubechies filters (host, FP64 spectral factorisation) and
+ * uploads them. Does not synchronise. */
+int pr_psi_plan_create(int32_t n, int32_t levels, uint32_t basis_mask, int32_t prec,
+                       void* persistent_ws, void* scratch_ws, void* stream,
+                       pr_psi_plan* out);
+int pr_psi_plan_destroy(pr_psi_plan plan);
+/* Number of bases nb selected by the plan's mask. Host only. */
+int pr_psi_plan_bases(pr_psi_plan plan, int32_t* nb);
+/* Filter taps of Daubechies basis k (1..8), 2k values, host FP64 copy. */
+int pr_psi_filter(pr_psi_plan plan, int32_t k, double* taps);
+
+/* x = Psi alpha (synthesis). */
+int pr_psi_apply(pr_psi_plan plan, const void* alpha, void* x, void* stream);
+/* alpha = Psi^dagger x (analysis). */
+int pr_psi_adjoint(pr_psi_plan plan, const void* x, void* alpha, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Proximal operators (Section "Proximal Operators").
+ * ---------------------------------------------------------------------- */
+/* out = S_lambda(in): 0 where |in_i| <= lambda, else in_i (|in_i| - lambda)
+ * / |in_i|. len elements, real or complex (is_complex != 0). in == out is
+ * allowed. */
+int pr_prox_l1(const void* in, void* out, int64_t len, int32_t is_complex,
+               int32_t prec, double lambda, void* stream);
+
+/* Device scratch bytes pr_proj_l2ball needs for len complex elements. */
+size_t pr_proj_l2ball_scratch_bytes(int64_t len);
+
+/* out = P_B(in) for the closed ball of radius eps centred at center
+ * (eq. l2ball_prox): in if ||in - center|| <= eps, else
+ * center + eps (in - center) / ||in - center||. len complex elements; the
+ * norm is reduced in FP64 in a fixed order (bitwise reproducible). dist: if
+ * not NULL, ||in - center|| is written to this HOST pointer and the call
+ * synchronises the stream. in == out is allowed. */
+int pr_proj_l2ball(const void* in, const void* center, void* out, int64_t len,
+                   int32_t prec, double eps, void* scratch, double* dist,
+                   void* stream);
+
+/* ------------------------------------------------------------------------
+ * Dual Forward-Backward ADMM (Algorithm 1) for
+ *   min ||Psi^dagger x||_1 + iota_{R+}(x) + iota_{||Phi x - y|| <= eps}
+ * with Phi normalised by op_norm: each outer iteration
+ *   v = Phi x / ||Phi||; r = P_B(v + s); s <- s + varrho (v - r);
+ *   xt = x - rho Phi^dagger (v - r + s) / ||Phi||; x = DualFB(xt, gamma),
+ * DualFB: zbar = max(xt, 0); repeat inner_iters times
+ *   d <- (1/eta) (I - S_gamma)(eta d + Psi^dagger zbar); zbar = max(xt - Psi d, 0).
+ * s and d start at 0 (d carried across outer iterations). The l2 norm of the
+ * ball test and the diagnostics are reduced in FP64.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t iters;       /* outer iterations (>= 0)                            */
+  int32_t inner_iters; /* DualFB iterations per outer iteration (>= 1)       */
+  double eps;          /* l2-ball radius                                     */
+  double gamma;        /* soft-threshold level (> 0)                         */
+  double rho;          /* gradient step                                      */
+  double varrho;       /* dual (Lagrange multiplier) step                    */
+  double eta;          /* DualFB step                                        */
+  double rel_tol;      /* > 0: stop when ||x_t - x_{t-1}|| / ||x_t|| < rel_tol
+                          (synchronises every iteration); 0: fixed count    */
+  double op_norm;      /* ||Phi||; <= 0: computed by pr_phi_norm, 100 steps  */
+} pr_admm_params;
+
+typedef struct {
+  int32_t iters_done;
+  double rel_var;      /* ||x_t - x_{t-1}|| / ||x_t|| of the last iteration  */
+  double resid_norm;   /* ||Phi x_{t-1} / ||Phi|| - y|| of the last iteration */
+  double l1_norm;      /* ||Psi^dagger x|| _1 of the returned x               */
+  double op_norm;      /* the ||Phi|| used                                    */
+  int32_t nonfinite;   /* 1 if a NaN or Inf reached a reduction               */
+} pr_admm_report;
+
+/* Device workspace bytes for pr_admm_solve on these plans. */
+int pr_admm_workspace_size(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes);
+
+/* Run Algorithm 1. y: complex[M], plan order. x: real[n*n], in: x0, out:
+ * the last iterate (in units of the normalised operator: the physical image
+ * is x / ||Phi||). rep: if not NULL, filled on return and the call
+ * synchronises; if NULL and rel_tol == 0 and op_norm > 0 the call is fully
+ * asynchronous. The two plans must have the same n and precision. */
+int pr_admm_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
+                  const pr_admm_params* params, void* x, void* workspace,
+                  pr_admm_report* rep, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PURIMI_H */

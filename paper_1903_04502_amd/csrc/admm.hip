@@ -1,0 +1,158 @@
+// Algorithm 1 (Dual Forward-Backward ADMM) on one GPU. Each outer iteration
+// is a fixed sequence of launches on the caller's stream:
+//   F Z S x                                   (2 FFT passes)
+//   degrid + epilogue t = v + s - y, FP64 ||t||^2, ||v - y||^2
+//   ball scale kappa = min(1, eps / ||t||)    (one-block FP64 reduction)
+//   gridding with the prologue r = y + kappa t, s <- s + varrho (v - r),
+//     q = v - r + s, then the patch merge
+//   S Z^T F^H with the epilogue xt = x - rho Re(.), zbar = max(xt, 0)
+//   DualFB: d <- (1/eta) clip_gamma(eta d + Psi^dagger zbar) fused into the
+//     analysis stores; zbar = max(xt - Psi d, 0) fused into the synthesis sum
+// Phi enters divided by ||Phi|| (folded into the per-visibility weight scale).
+// Nothing is read back to the host unless a report or a tolerance asks for it.
+#include <cmath>
+#include <cstring>
+
+#include "admm.hpp"
+#include "ops.hpp"
+
+namespace pr {
+
+struct AdmmWs {
+  void *s, *t, *d, *alpha, *xt, *zbar, *xb;
+  double* partials;
+  double* sums;
+};
+
+namespace {
+
+constexpr int kSumBall = 0;      // 0: ||t||^2, 1: ||v-y||^2, 2: kappa, 3: nonfinite
+constexpr int kSumVar = 8;       // 8: ||x_t - x_{t-1}||^2, 9: ||x_t||^2
+constexpr int kSumL1 = 12;
+
+template <typename R>
+__global__ void zero_kernel(R* a, int64_t len) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = R(0);
+}
+
+__global__ void zero_f64_kernel(double* a, int len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) a[i] = 0.0;
+}
+
+int zero_real(void* a, int64_t len, int prec, hipStream_t s) {
+  const int G = grid_for(len, 256, 8192);
+  if (prec == PR_F32) zero_kernel<float><<<G, 256, 0, s>>>(static_cast<float*>(a), len);
+  else zero_kernel<double><<<G, 256, 0, s>>>(static_cast<double*>(a), len);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+}  // namespace
+
+int admm_check_plans(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi) {
+  if (phi->n != psi->n) { set_error("Phi plan n = %d but Psi plan n = %d", phi->n, psi->n); return PR_EINVAL; }
+  if (phi->prec != psi->prec) { set_error("Phi and Psi plans differ in precision"); return PR_EINVAL; }
+  if (phi->M < 1) { set_error("ADMM needs M >= 1"); return PR_EINVAL; }
+  return PR_OK;
+}
+
+int admm_check_params(const pr_admm_params* p) {
+  if (p->iters < 0) { set_error("iters < 0"); return PR_EINVAL; }
+  if (p->inner_iters < 1) { set_error("inner_iters < 1"); return PR_EINVAL; }
+  if (!(p->eps >= 0)) { set_error("eps must be >= 0"); return PR_EINVAL; }
+  if (!(p->gamma > 0)) { set_error("gamma must be > 0"); return PR_EINVAL; }
+  if (!(p->rho > 0) || !(p->varrho > 0) || !(p->eta > 0)) { set_error("rho, varrho, eta must be > 0"); return PR_EINVAL; }
+  if (!(p->rel_tol >= 0)) { set_error("rel_tol must be >= 0"); return PR_EINVAL; }
+  return PR_OK;
+}
+
+size_t admm_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws, AdmmWs* out) {
+  const size_t rs = phi->prec == PR_F32 ? 4 : 8;
+  const int64_t n2 = static_cast<int64_t>(phi->n) * phi->n;
+  Carver c(ws);
+  AdmmWs w{};
+  w.s = c.take<char>(phi->M * 2 * rs);
+  w.t = c.take<char>(phi->M * 2 * rs);
+  w.d = c.take<char>(psi->nb * n2 * rs);
+  w.alpha = c.take<char>(psi->nb * n2 * rs);
+  w.xt = c.take<char>(n2 * rs);
+  w.zbar = c.take<char>(n2 * rs);
+  w.xb = c.take<char>(n2 * rs);
+  w.partials = c.take<double>(2 * kPartialsMax);
+  w.sums = c.take<double>(32);
+  if (out) *out = w;
+  return c.bytes();
+}
+
+int admm_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x, void* ws,
+               pr_admm_report* rep, hipStream_t s) {
+  AdmmWs w;
+  admm_layout(phi, psi, ws, &w);
+  const int prec = phi->prec;
+  const size_t rs = prec == PR_F32 ? 4 : 8;
+  const int64_t n2 = static_cast<int64_t>(phi->n) * phi->n;
+
+  double op_norm = prm.op_norm;
+  if (!(op_norm > 0)) PR_TRY(phi_norm(phi, 100, w.t, &op_norm, s));
+  const double scale = 1.0 / op_norm;
+
+  PR_TRY(zero_real(w.s, 2 * phi->M, prec, s));
+  PR_TRY(zero_real(w.d, psi->nb * n2, prec, s));
+  zero_f64_kernel<<<1, 32, 0, s>>>(w.sums, 32);
+  PR_TRY_LAUNCH();
+
+  AdmmVis av{};
+  av.y = y;
+  av.s = w.s;
+  av.t = w.t;
+  av.sums = w.sums + kSumBall;
+  av.eps = prm.eps;
+  av.varrho = prm.varrho;
+
+  void* xcur = x;        // current iterate
+  void* xnext = w.xb;    // receives the next iterate
+  int done = 0;
+  double host_sums[16] = {0};
+  for (int it = 0; it < prm.iters; ++it) {
+    PR_TRY(phi_fzs(phi, xcur, s));
+    PR_TRY(phi_gw_admm(phi, av, scale, s));
+    PR_TRY(phi_gw_adjoint_admm(phi, av, scale, s));
+    PR_TRY(phi_fzs_adjoint_step(phi, xcur, prm.rho, w.xt, w.zbar, s));
+    for (int k = 0; k < prm.inner_iters; ++k) {
+      PR_TRY(psi_dual_update(psi, w.zbar, 0, w.d, prm.gamma, prm.eta, s));
+      const bool last = k == prm.inner_iters - 1;
+      void* out = last ? xnext : w.zbar;
+      PR_TRY(psi_synthesis_step(psi, w.d, w.xt, out, last ? xcur : nullptr, w.partials, w.sums + kSumVar, s));
+    }
+    std::swap(xcur, xnext);
+    ++done;
+    if (prm.rel_tol > 0) {
+      PR_TRY_HIP(hipMemcpyAsync(host_sums, w.sums, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PR_TRY_HIP(hipStreamSynchronize(s));
+      const double rv = host_sums[kSumVar + 1] > 0 ? std::sqrt(host_sums[kSumVar] / host_sums[kSumVar + 1]) : INFINITY;
+      if (rv < prm.rel_tol) break;
+    }
+  }
+  if (xcur != x) PR_TRY_HIP(hipMemcpyAsync(x, xcur, n2 * rs, hipMemcpyDeviceToDevice, s));
+  if (rep) {
+    PR_TRY(psi_analysis(psi, x, w.alpha, s));
+    PR_TRY(reduce_abssum(w.alpha, psi->nb * n2, prec, w.partials, w.sums + kSumL1, s));
+    PR_TRY_HIP(hipMemcpyAsync(host_sums, w.sums, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+    PR_TRY_HIP(hipStreamSynchronize(s));
+    rep->iters_done = done;
+    rep->rel_var = host_sums[kSumVar + 1] > 0 ? std::sqrt(host_sums[kSumVar] / host_sums[kSumVar + 1]) : INFINITY;
+    rep->resid_norm = std::sqrt(host_sums[kSumBall + 1]);
+    rep->l1_norm = host_sums[kSumL1];
+    rep->op_norm = op_norm;
+    rep->nonfinite = (host_sums[kSumBall + 3] != 0 || !std::isfinite(rep->rel_var) || !std::isfinite(rep->l1_norm) ||
+                      !std::isfinite(rep->resid_norm))
+                         ? 1
+                         : 0;
+  }
+  return PR_OK;
+}
+
+}  // namespace pr

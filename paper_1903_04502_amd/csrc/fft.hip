@@ -1,0 +1,294 @@
+// F Z S and its adjoint (eq. matrix_equation): gridding correction, zero
+// padding to the oversampled K x K grid and the unnormalised 2-D FFT, as two
+// passes of in-LDS Stockham FFTs (radix 4, one radix-2 stage when log2 K is
+// odd). The zero padding is pruned: the forward row pass transforms only the
+// n image rows, and the adjoint column pass keeps only the n rows the crop
+// Z^T needs.
+//
+// Layouts: image x[iy*n + ix]; intermediate A[iy*K + kx] (n rows of K);
+// grid[ky*K + kx], ky = v cell, kx = u cell. Pixel offset p = i - n/2 sits at
+// grid index p mod K.
+#include "phi.hpp"
+
+namespace pr {
+
+namespace {
+
+constexpr int kFftThreads = 256;
+
+// Lines of length K held in LDS at stride LS (complex elements). All threads
+// of the block cooperate on the W lines; each stage reads every butterfly's
+// inputs into registers, synchronises, then writes (in place).
+template <typename R, bool INV, int PB4>
+__device__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t<R>* __restrict__ tw) {
+  using C = cx_t<R>;
+  const int tid = threadIdx.x;
+  int Ns = 1;
+  if (logK & 1) {
+    const int half = K >> 1, nbf = W * half;
+    C a[2 * PB4], b[2 * PB4];
+#pragma unroll
+    for (int i = 0; i < 2 * PB4; ++i) {
+      const int bf = tid + i * kFftThreads;
+      if (bf < nbf) {
+        const int line = bf / half, j = bf - line * half;
+        const C* L = buf + line * LS;
+        a[i] = L[j];
+        b[i] = L[j + half];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2 * PB4; ++i) {
+      const int bf = tid + i * kFftThreads;
+      if (bf < nbf) {
+        const int line = bf / half, j = bf - line * half;
+        C* L = buf + line * LS;
+        L[2 * j] = cadd(a[i], b[i]);
+        L[2 * j + 1] = csub(a[i], b[i]);
+      }
+    }
+    __syncthreads();
+    Ns = 2;
+  }
+  const int q = K >> 2, nbf = W * q;
+  for (; Ns < K; Ns <<= 2) {
+    const int stride = K / (4 * Ns);
+    C v[PB4][4];
+#pragma unroll
+    for (int i = 0; i < PB4; ++i) {
+      const int bf = tid + i * kFftThreads;
+      if (bf < nbf) {
+        const int line = bf / q, j = bf - line * q;
+        const C* L = buf + line * LS;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[i][r] = L[j + r * q];
+        const int k = j & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          C w = tw[k * r * stride];
+          if (INV) w = cconj(w);
+          v[i][r] = cmul(v[i][r], w);
+        }
+        // 4-point DFT; the rotation by -i (forward) or +i (inverse)
+        const C s0 = cadd(v[i][0], v[i][2]), d0 = csub(v[i][0], v[i][2]);
+        const C s1 = cadd(v[i][1], v[i][3]), d1 = csub(v[i][1], v[i][3]);
+        const C rd1 = INV ? cmk<C>(-d1.y, d1.x) : cmk<C>(d1.y, -d1.x);
+        v[i][0] = cadd(s0, s1);
+        v[i][2] = csub(s0, s1);
+        v[i][1] = cadd(d0, rd1);
+        v[i][3] = csub(d0, rd1);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PB4; ++i) {
+      const int bf = tid + i * kFftThreads;
+      if (bf < nbf) {
+        const int line = bf / q, j = bf - line * q;
+        const int k = j & (Ns - 1);
+        C* L = buf + line * LS;
+        const int idxD = (j - k) * 4 + k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) L[idxD + r * Ns] = v[i][r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Butterflies per thread per radix-4 stage: W * K / 4 <= kFftThreads * PB4.
+template <typename R> struct FftCfg;
+template <> struct FftCfg<float> { static constexpr int PB4 = 8; };
+template <> struct FftCfg<double> { static constexpr int PB4 = 4; };
+
+inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
+
+// Lines per block: the largest power of two whose lines fit 64 KB of LDS at
+// stride K + 1 (the pad spreads column loads over banks); a single line uses
+// stride K. This also keeps W * K within kFftThreads * 4 * PB4.
+template <typename R>
+inline void lines_per_block(int K, int cap, int* W, int* LS) {
+  const size_t per = static_cast<size_t>(K + 1) * sizeof(cx_t<R>);
+  int w = 1;
+  while (static_cast<size_t>(2 * w) * per <= 65536 && 2 * w <= cap) w *= 2;
+  *W = w;
+  *LS = w > 1 ? K + 1 : K;
+}
+
+// Forward row pass: image rows -> S Z -> FFT along u -> A.
+template <typename R>
+__global__ __launch_bounds__(kFftThreads) void fzs_rows_kernel(const R* __restrict__ x, const R* __restrict__ corr,
+                                                             const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ A,
+                                                             int n, int K, int logK, int W, int LS) {
+  using C = cx_t<R>;
+  extern __shared__ char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int row0 = blockIdx.x * W;
+  const int lines = min(W, n - row0);
+  for (int i = threadIdx.x; i < lines * LS; i += kFftThreads) buf[i] = cmk<C>(R(0), R(0));
+  __syncthreads();
+  for (int i = threadIdx.x; i < lines * n; i += kFftThreads) {
+    const int l = i / n, ix = i - l * n;
+    const int iy = row0 + l;
+    const int gx = (ix - n / 2) & (K - 1);
+    buf[l * LS + gx] = cmk<C>(x[static_cast<int64_t>(iy) * n + ix] * corr[ix] * corr[iy], R(0));
+  }
+  __syncthreads();
+  fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
+  for (int i = threadIdx.x; i < lines * K; i += kFftThreads) {
+    const int l = i / K, k = i - l * K;
+    A[static_cast<int64_t>(row0 + l) * K + k] = buf[l * LS + k];
+  }
+}
+
+// Column groups are laid out so that blocks on one XCD (blockIdx mod 8) take
+// neighbouring columns and share L2 lines.
+__device__ inline int xcd_group(int b, int nb) {
+  if (nb % kXcds) return b;
+  return (b % kXcds) * (nb / kXcds) + b / kXcds;
+}
+
+// Forward column pass: A (n nonzero rows at p mod K) -> FFT along v -> grid.
+template <typename R>
+__global__ __launch_bounds__(kFftThreads) void fzs_cols_kernel(const cx_t<R>* __restrict__ A,
+                                                             const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ grid,
+                                                             int n, int K, int logK, int W, int LS) {
+  using C = cx_t<R>;
+  extern __shared__ char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
+  for (int i = threadIdx.x; i < W * LS; i += kFftThreads) buf[i] = cmk<C>(R(0), R(0));
+  __syncthreads();
+  for (int i = threadIdx.x; i < n * W; i += kFftThreads) {
+    const int iy = i / W, l = i - iy * W;
+    const int gy = (iy - n / 2) & (K - 1);
+    buf[l * LS + gy] = A[static_cast<int64_t>(iy) * K + kx0 + l];
+  }
+  __syncthreads();
+  fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
+  for (int i = threadIdx.x; i < K * W; i += kFftThreads) {
+    const int ky = i / W, l = i - ky * W;
+    grid[static_cast<int64_t>(ky) * K + kx0 + l] = buf[l * LS + ky];
+  }
+}
+
+// Adjoint column pass: grid -> inverse FFT along v -> keep the n rows at p mod K -> A.
+template <typename R>
+__global__ __launch_bounds__(kFftThreads) void fzs_adj_cols_kernel(const cx_t<R>* __restrict__ grid,
+                                                                 const cx_t<R>* __restrict__ tw,
+                                                                 cx_t<R>* __restrict__ A, int n, int K, int logK,
+                                                                 int W, int LS) {
+  using C = cx_t<R>;
+  extern __shared__ char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
+  for (int i = threadIdx.x; i < K * W; i += kFftThreads) {
+    const int ky = i / W, l = i - ky * W;
+    buf[l * LS + ky] = grid[static_cast<int64_t>(ky) * K + kx0 + l];
+  }
+  __syncthreads();
+  fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
+  for (int i = threadIdx.x; i < n * W; i += kFftThreads) {
+    const int iy = i / W, l = i - iy * W;
+    const int gy = (iy - n / 2) & (K - 1);
+    A[static_cast<int64_t>(iy) * K + kx0 + l] = buf[l * LS + gy];
+  }
+}
+
+// Adjoint row pass: A rows -> inverse FFT along u -> crop, correct, real part.
+// MODE 0: x = Re(.). MODE 1 (gradient step of Algorithm 1):
+// x_out = x_in - rho Re(.), zbar = max(x_out, 0).
+template <typename R, int MODE>
+__global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>* __restrict__ A,
+                                                                 const R* __restrict__ corr,
+                                                                 const cx_t<R>* __restrict__ tw, R* __restrict__ x_out,
+                                                                 const R* __restrict__ x_in, R* __restrict__ zbar,
+                                                                 R rho, int n, int K, int logK, int W, int LS) {
+  using C = cx_t<R>;
+  extern __shared__ char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int row0 = blockIdx.x * W;
+  const int lines = min(W, n - row0);
+  for (int i = threadIdx.x; i < lines * K; i += kFftThreads) {
+    const int l = i / K, k = i - l * K;
+    buf[l * LS + k] = A[static_cast<int64_t>(row0 + l) * K + k];
+  }
+  __syncthreads();
+  fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
+  for (int i = threadIdx.x; i < lines * n; i += kFftThreads) {
+    const int l = i / n, ix = i - l * n;
+    const int iy = row0 + l;
+    const int gx = (ix - n / 2) & (K - 1);
+    const R val = buf[l * LS + gx].x * corr[ix] * corr[iy];
+    const int64_t o = static_cast<int64_t>(iy) * n + ix;
+    if (MODE == 0) {
+      x_out[o] = val;
+    } else {
+      const R xo = x_in[o] - rho * val;
+      x_out[o] = xo;
+      zbar[o] = xo > R(0) ? xo : R(0);
+    }
+  }
+}
+
+template <typename R>
+int fzs_impl(pr_phi_plan_t* p, const R* x, hipStream_t s) {
+  using C = cx_t<R>;
+  const int n = p->n, K = p->K, logK = ilog2(K);
+  int Wr, LSr, Wc, LSc;
+  lines_per_block<R>(K, n, &Wr, &LSr);
+  lines_per_block<R>(K, K, &Wc, &LSc);
+  const size_t lds_r = static_cast<size_t>(Wr) * LSr * sizeof(C);
+  const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
+  fzs_rows_kernel<R><<<(n + Wr - 1) / Wr, kFftThreads, lds_r, s>>>(
+      x, static_cast<const R*>(p->corr), static_cast<const C*>(p->tw), static_cast<C*>(p->fft_tmp), n, K, logK, Wr, LSr);
+  PR_TRY_LAUNCH();
+  fzs_cols_kernel<R><<<K / Wc, kFftThreads, lds_c, s>>>(static_cast<const C*>(p->fft_tmp),
+                                                       static_cast<const C*>(p->tw), static_cast<C*>(p->grid), n, K,
+                                                       logK, Wc, LSc);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+template <typename R, int MODE>
+int fzs_adjoint_impl(pr_phi_plan_t* p, R* x_out, const R* x_in, R* zbar, double rho, hipStream_t s) {
+  using C = cx_t<R>;
+  const int n = p->n, K = p->K, logK = ilog2(K);
+  int Wr, LSr, Wc, LSc;
+  lines_per_block<R>(K, n, &Wr, &LSr);
+  lines_per_block<R>(K, K, &Wc, &LSc);
+  const size_t lds_r = static_cast<size_t>(Wr) * LSr * sizeof(C);
+  const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
+  fzs_adj_cols_kernel<R><<<K / Wc, kFftThreads, lds_c, s>>>(static_cast<const C*>(p->grid),
+                                                           static_cast<const C*>(p->tw), static_cast<C*>(p->fft_tmp),
+                                                           n, K, logK, Wc, LSc);
+  PR_TRY_LAUNCH();
+  fzs_adj_rows_kernel<R, MODE><<<(n + Wr - 1) / Wr, kFftThreads, lds_r, s>>>(
+      static_cast<const C*>(p->fft_tmp), static_cast<const R*>(p->corr), static_cast<const C*>(p->tw), x_out, x_in,
+      zbar, static_cast<R>(rho), n, K, logK, Wr, LSr);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+}  // namespace
+
+int phi_fzs(pr_phi_plan_t* p, const void* x, hipStream_t s) {
+  if (p->prec == PR_F32) return fzs_impl<float>(p, static_cast<const float*>(x), s);
+  return fzs_impl<double>(p, static_cast<const double*>(x), s);
+}
+
+int phi_fzs_adjoint(pr_phi_plan_t* p, void* x, hipStream_t s) {
+  if (p->prec == PR_F32) return fzs_adjoint_impl<float, 0>(p, static_cast<float*>(x), nullptr, nullptr, 0.0, s);
+  return fzs_adjoint_impl<double, 0>(p, static_cast<double*>(x), nullptr, nullptr, 0.0, s);
+}
+
+int phi_fzs_adjoint_step(pr_phi_plan_t* p, const void* x_in, double rho, void* x_out, void* zbar, hipStream_t s) {
+  if (p->prec == PR_F32)
+    return fzs_adjoint_impl<float, 1>(p, static_cast<float*>(x_out), static_cast<const float*>(x_in),
+                                      static_cast<float*>(zbar), rho, s);
+  return fzs_adjoint_impl<double, 1>(p, static_cast<double*>(x_out), static_cast<const double*>(x_in),
+                                     static_cast<double*>(zbar), rho, s);
+}
+
+}  // namespace pr

@@ -1,0 +1,606 @@
+// G W (degridding) and its adjoint W G^T (gridding) with the pre-sampled
+// Kaiser-Bessel kernel (eq. matrix_equation, Section "Kernel Pre-Sampling"),
+// on visibilities sorted by grid tile.
+//
+// Degridding: one work item = a run of one tile's visibilities. The block
+// stages the tile's (T+J-1)^2 grid patch in LDS and each thread interpolates
+// one visibility at a time from it.
+//
+// Gridding is deterministic (no float atomics anywhere): within an item the
+// visibilities are also sorted by their first tap cell ("base cell"). For each
+// base cell c and tap (a, b) the item accumulates the moment
+//   m[c][a][b] = sum_{k in c} g_a(u_k) g_b(v_k) w_k y_k
+// in a fixed order: streams of J lanes walk contiguous runs of staged
+// visibilities, lane a holding the J sums of column a in registers; a run that
+// starts inside a stream is stored directly, a run continued from the previous
+// stream is parked in a side slot and added after a barrier in stream order.
+// The item's patch value at cell q is sum_{a,b} m[q - (a,b)][a][b]. Patches are
+// written per item and a merge kernel adds the up to four overlapping tile
+// patches of each grid cell, items in order.
+#include "phi.hpp"
+#include "taps.hpp"
+
+namespace pr {
+
+constexpr int kSlotT2 = 0;      // ||t||^2 of the ADMM degridding epilogue
+constexpr int kSlotR2 = 1;      // ||v - y||^2
+constexpr int kSlotKappa = 2;   // ball scale min(1, eps / ||t||)
+constexpr int kSlotNonfinite = 3;
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 2048;   // <= kPartialsMax
+constexpr size_t kLdsSoft = 81920;    // two blocks per CU
+constexpr size_t kLdsHard = 163840;   // per-workgroup limit on gfx950
+
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+// ---------------------------------------------------------------------------
+// degridding
+// ---------------------------------------------------------------------------
+template <typename R>
+struct GwArgs {
+  const cx_t<R>* grid;
+  const R* table;
+  const R* uv;
+  const R* w;
+  const int4* items;
+  int64_t nItems;
+  int K, T, P, nT, D, tlen;
+  double kappa;
+  R scale;
+  cx_t<R>* y_out;          // MODE 0
+  const cx_t<R>* y_obs;    // MODE 1
+  const cx_t<R>* s_in;
+  cx_t<R>* t_out;
+  double* partials;
+};
+
+template <typename R, int J, int MODE, bool TAB_LDS>
+__global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
+  using C = cx_t<R>;
+  extern __shared__ char smem_raw[];
+  const int tid = threadIdx.x;
+  C* patch = reinterpret_cast<C*>(smem_raw);
+  const R* tab = a.table;
+  if (TAB_LDS) {
+    R* t = reinterpret_cast<R*>(smem_raw + align16(static_cast<size_t>(a.P) * a.P * sizeof(C)));
+    for (int i = tid; i < a.tlen; i += kThreads) t[i] = a.table[i];
+    tab = t;
+  }
+  const int P = a.P, T = a.T, K = a.K;
+  double sum_t = 0.0, sum_r = 0.0;
+  for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
+    const int4 it = a.items[item];
+    const int tv = it.x / a.nT, tu = it.x - tv * a.nT;
+    __syncthreads();
+    for (int i = tid; i < P * P; i += kThreads) {
+      const int pv = i / P, pu = i - pv * P;
+      const int gv = (tv * T + pv) & (K - 1), gu = (tu * T + pu) & (K - 1);
+      patch[i] = a.grid[static_cast<int64_t>(gv) * K + gu];
+    }
+    __syncthreads();
+    for (int k = it.y + tid; k < it.z; k += kThreads) {
+      const R u = a.uv[2 * static_cast<int64_t>(k)];
+      const R v = a.uv[2 * static_cast<int64_t>(k) + 1];
+      const AxisTaps xu = axis_taps(static_cast<double>(u), a.kappa, J, a.D);
+      const AxisTaps xv = axis_taps(static_cast<double>(v), a.kappa, J, a.D);
+      const int lu = mod_pos(xu.j0, K) - tu * T;
+      const int lv = mod_pos(xv.j0, K) - tv * T;
+      if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
+        // cannot happen for a plan's own sorted baselines; flag instead of reading out of the patch
+        const R nan = R(NAN);
+        if (MODE == 0) a.y_out[k] = cmk<C>(nan, nan);
+        else a.t_out[k] = cmk<C>(nan, nan);
+        continue;
+      }
+      R wu[J], wv[J];
+#pragma unroll
+      for (int q = 0; q < J; ++q) {
+        wu[q] = tab[tap_index(xu, q, J, a.D)];
+        wv[q] = tab[tap_index(xv, q, J, a.D)];
+      }
+      R accr = 0, acci = 0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        const C* row = patch + (lv + b) * P + lu;
+        R rr = 0, ri = 0;
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+          const C g = row[q];
+          rr += wu[q] * g.x;
+          ri += wu[q] * g.y;
+        }
+        accr += wv[b] * rr;
+        acci += wv[b] * ri;
+      }
+      const R ws = a.w[k] * a.scale;
+      const C yk = cmk<C>(accr * ws, acci * ws);
+      if (MODE == 0) {
+        a.y_out[k] = yk;
+      } else {
+        const C yo = a.y_obs[k], sk = a.s_in[k];
+        const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
+        a.t_out[k] = t;
+        const double tr = t.x, ti = t.y, rr = static_cast<double>(yk.x) - yo.x, ri = static_cast<double>(yk.y) - yo.y;
+        sum_t += tr * tr + ti * ti;
+        sum_r += rr * rr + ri * ri;
+      }
+    }
+  }
+  if (MODE == 1) {
+    __syncthreads();
+    double* sh = reinterpret_cast<double*>(smem_raw);
+    const double bt = block_sum_f64(sum_t, sh);
+    const double br = block_sum_f64(sum_r, sh);
+    if (tid == 0) {
+      a.partials[kSlotT2 * kPartialsMax + blockIdx.x] = bt;
+      a.partials[kSlotR2 * kPartialsMax + blockIdx.x] = br;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gridding
+// ---------------------------------------------------------------------------
+template <typename R>
+struct GwAdjArgs {
+  const R* table;
+  const R* uv;
+  const R* w;
+  const int4* items;
+  int64_t nItems;
+  int K, T, P, nT, D, tlen, B;
+  double kappa;
+  R scale;
+  const cx_t<R>* y_in;       // MODE 0
+  const cx_t<R>* t_in;       // MODE 1: t = v + s - y
+  cx_t<R>* s_io;             // MODE 1: multiplier, updated
+  const double* scalars;     // MODE 1: ball scale at kSlotKappa
+  R varrho;
+  cx_t<R>* patches;
+};
+
+template <typename R, int J>
+struct GridLds {
+  static constexpr int SPW = 64 / J;             // streams per wave
+  static constexpr int S = (kThreads / 64) * SPW;
+  size_t tab, cell, ywu, wv, mom, bits, side, side_cell, misc, total;
+  __host__ __device__ GridLds(int T, int B, int tlen, bool tab_lds) {
+    using C = cx_t<R>;
+    size_t o = 0;
+    tab = o;       o += tab_lds ? align16(static_cast<size_t>(tlen) * sizeof(R)) : 0;
+    cell = o;      o += align16(static_cast<size_t>(B) * sizeof(int));
+    ywu = o;       o += align16(static_cast<size_t>(B) * J * sizeof(C));
+    wv = o;        o += align16(static_cast<size_t>(B) * J * sizeof(R));
+    mom = o;       o += align16(static_cast<size_t>(T) * T * J * J * sizeof(C));
+    bits = o;      o += align16(static_cast<size_t>((T * T + 31) / 32) * sizeof(uint32_t));
+    side = o;      o += align16(static_cast<size_t>(S) * J * J * sizeof(C));
+    side_cell = o; o += align16(static_cast<size_t>(S) * sizeof(int));
+    misc = o;      o += 16;
+    total = o;
+  }
+};
+
+template <typename R, int J, int MODE, bool TAB_LDS>
+__global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
+  using C = cx_t<R>;
+  using L = GridLds<R, J>;
+  constexpr int SPW = L::SPW, S = L::S, JJ = J * J;
+  extern __shared__ char smem_raw[];
+  const L lay(a.T, a.B, a.tlen, TAB_LDS);
+  int* st_cell = reinterpret_cast<int*>(smem_raw + lay.cell);
+  C* st_ywu = reinterpret_cast<C*>(smem_raw + lay.ywu);
+  R* st_wv = reinterpret_cast<R*>(smem_raw + lay.wv);
+  C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem_raw + lay.bits);
+  C* side = reinterpret_cast<C*>(smem_raw + lay.side);
+  int* side_cell = reinterpret_cast<int*>(smem_raw + lay.side_cell);
+  int* prevlast = reinterpret_cast<int*>(smem_raw + lay.misc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const R* tab = a.table;
+  if (TAB_LDS) {
+    R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
+    for (int i = tid; i < a.tlen; i += kThreads) t[i] = a.table[i];
+    tab = t;
+  }
+  const int T = a.T, P = a.P, K = a.K, B = a.B;
+  const int sl = lane / J, aa = lane - sl * J;
+  const bool lane_on = sl < SPW;
+  const int sid = wave * SPW + sl;
+  R kappa_ball = 1;
+  if (MODE == 1) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
+  const int nbits = (T * T + 31) / 32;
+
+  for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
+    const int4 it = a.items[item];
+    const int tv = it.x / a.nT, tu = it.x - tv * a.nT;
+    const int begin = it.y, end = it.z;
+    __syncthreads();
+    for (int i = tid; i < nbits; i += kThreads) bits[i] = 0u;
+    for (int bs = begin; bs < end; bs += B) {
+      const int nb = min(B, end - bs);
+      // stage: taps, weights and the weighted value of each visibility
+      for (int i = tid; i < nb; i += kThreads) {
+        const int64_t k = bs + i;
+        const R u = a.uv[2 * k], v = a.uv[2 * k + 1];
+        const AxisTaps xu = axis_taps(static_cast<double>(u), a.kappa, J, a.D);
+        const AxisTaps xv = axis_taps(static_cast<double>(v), a.kappa, J, a.D);
+        int lu = mod_pos(xu.j0, K) - tu * T;
+        int lv = mod_pos(xv.j0, K) - tv * T;
+        const bool inside = static_cast<unsigned>(lu) < static_cast<unsigned>(T) &&
+                            static_cast<unsigned>(lv) < static_cast<unsigned>(T);
+        C val;
+        if (MODE == 0) {
+          val = a.y_in[k];
+        } else {
+          // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
+          // r = y + kappa t, s' = s + varrho (v - r), q = v - r + s'
+          const C t = a.t_in[k], s = a.s_io[k];
+          const R omk = R(1) - kappa_ball;
+          const C vr = cmk<C>(omk * t.x - s.x, omk * t.y - s.y);   // v - r
+          const C sn = cmk<C>(s.x + a.varrho * vr.x, s.y + a.varrho * vr.y);
+          a.s_io[k] = sn;
+          val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
+        }
+        const R ws = a.w[k] * a.scale;
+        val = cmk<C>(val.x * ws, val.y * ws);
+        if (!inside) {
+          // cannot happen for a plan's own sorted baselines; keep LDS indices in range, poison the value
+          lu = lv = 0;
+          val = cmk<C>(R(NAN), R(NAN));
+        }
+        st_cell[i] = lv * T + lu;
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+          const R gu = tab[tap_index(xu, q, J, a.D)];
+          st_ywu[i * J + q] = cmk<C>(val.x * gu, val.y * gu);
+          st_wv[i * J + q] = tab[tap_index(xv, q, J, a.D)];
+        }
+      }
+      __syncthreads();
+      // streams: lane aa of stream sid accumulates column aa of the moments
+      if (lane_on) {
+        const int p0 = static_cast<int>((static_cast<int64_t>(sid) * nb) / S);
+        const int p1 = static_cast<int>((static_cast<int64_t>(sid + 1) * nb) / S);
+        if (aa == 0) side_cell[sid] = -1;
+        if (p0 < p1) {
+          int cur = st_cell[p0];
+          bool began = p0 > 0 ? st_cell[p0 - 1] != cur : (bs == begin || *prevlast != cur);
+          R ar[J], ai[J];
+#pragma unroll
+          for (int b = 0; b < J; ++b) ar[b] = ai[b] = 0;
+          for (int p = p0; p <= p1; ++p) {
+            const int c = p < p1 ? st_cell[p] : -1;
+            if (c != cur) {
+              if (began) {
+#pragma unroll
+                for (int b = 0; b < J; ++b) mom[(cur * J + aa) * J + b] = cmk<C>(ar[b], ai[b]);
+                if (aa == 0) atomicOr(&bits[cur >> 5], 1u << (cur & 31));
+              } else {
+#pragma unroll
+                for (int b = 0; b < J; ++b) side[sid * JJ + aa * J + b] = cmk<C>(ar[b], ai[b]);
+                if (aa == 0) side_cell[sid] = cur;
+              }
+              if (p == p1) break;
+              began = true;
+              cur = c;
+#pragma unroll
+              for (int b = 0; b < J; ++b) ar[b] = ai[b] = 0;
+            }
+            const C x = st_ywu[p * J + aa];
+#pragma unroll
+            for (int b = 0; b < J; ++b) {
+              const R g = st_wv[p * J + b];
+              ar[b] += g * x.x;
+              ai[b] += g * x.y;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // continued runs, added in stream order
+      for (int e = tid; e < JJ; e += kThreads) {
+        for (int s2 = 0; s2 < S; ++s2) {
+          const int c = side_cell[s2];
+          if (c >= 0) {
+            C m = mom[c * JJ + e];
+            const C d = side[s2 * JJ + e];
+            mom[c * JJ + e] = cmk<C>(m.x + d.x, m.y + d.y);
+          }
+        }
+      }
+      if (tid == 0) *prevlast = st_cell[nb - 1];
+      __syncthreads();
+    }
+    // patch: cell q = c + (b, a) collects m[c][a][b]
+    C* out = a.patches + item * static_cast<int64_t>(P) * P;
+    for (int pc = tid; pc < P * P; pc += kThreads) {
+      const int pv = pc / P, pu = pc - pv * P;
+      R sr = 0, si = 0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        const int cv = pv - b;
+        if (cv < 0 || cv >= T) continue;
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+          const int cu = pu - q;
+          if (cu < 0 || cu >= T) continue;
+          const int c = cv * T + cu;
+          if (bits[c >> 5] >> (c & 31) & 1u) {
+            const C m = mom[(c * J + q) * J + b];
+            sr += m.x;
+            si += m.y;
+          }
+        }
+      }
+      out[pc] = cmk<C>(sr, si);
+    }
+  }
+}
+
+// Grid cell = sum of the patches of the (up to four) tiles whose patch covers
+// it, neighbour tiles first, items of a tile in order.
+template <typename R>
+__global__ void merge_patches_kernel(const cx_t<R>* __restrict__ patches, const int32_t* __restrict__ item_off,
+                                     cx_t<R>* __restrict__ grid, int K, int T, int P, int nT, int J) {
+  using C = cx_t<R>;
+  const int64_t K2 = static_cast<int64_t>(K) * K;
+  for (int64_t cell = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; cell < K2;
+       cell += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int cv = static_cast<int>(cell / K), cu = static_cast<int>(cell - static_cast<int64_t>(cv) * K);
+    const int tv = cv / T, tu = cu / T, lv = cv - tv * T, lu = cu - tu * T;
+    R sr = 0, si = 0;
+    for (int dv = 1; dv >= 0; --dv) {
+      if (dv == 1 && lv >= J - 1) continue;
+      const int tvv = (tv - dv + nT) % nT, pv = lv + dv * T;
+      for (int du = 1; du >= 0; --du) {
+        if (du == 1 && lu >= J - 1) continue;
+        const int tuu = (tu - du + nT) % nT, pu = lu + du * T;
+        const int t = tvv * nT + tuu;
+        for (int itm = item_off[t]; itm < item_off[t + 1]; ++itm) {
+          const C v = patches[static_cast<int64_t>(itm) * P * P + pv * P + pu];
+          sr += v.x;
+          si += v.y;
+        }
+      }
+    }
+    grid[cell] = cmk<C>(sr, si);
+  }
+}
+
+// Sum the ADMM degridding partials in a fixed order and form the ball scale.
+__global__ void ball_scale_kernel(const double* partials, int nblocks, double eps, double* scalars) {
+  __shared__ double sh[kThreads];
+  double t2 = 0, r2 = 0;
+  for (int i = threadIdx.x; i < nblocks; i += kThreads) {
+    t2 += partials[kSlotT2 * kPartialsMax + i];
+    r2 += partials[kSlotR2 * kPartialsMax + i];
+  }
+  t2 = block_sum_f64(t2, sh);
+  r2 = block_sum_f64(r2, sh);
+  if (threadIdx.x == 0) {
+    const double nt = sqrt(t2);
+    scalars[kSlotT2] = t2;
+    scalars[kSlotR2] = r2;
+    scalars[kSlotKappa] = nt <= eps ? 1.0 : eps / nt;
+    if (!isfinite(t2) || !isfinite(r2)) scalars[kSlotNonfinite] = 1.0;
+  }
+}
+
+int degrid_blocks(const pr_phi_plan_t* p) {
+  return static_cast<int>(p->nItems < kMaxBlocks ? p->nItems : kMaxBlocks);
+}
+
+template <typename K>
+int allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    PR_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)));
+  return PR_OK;
+}
+
+template <typename R, int J, int MODE>
+int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
+  using C = cx_t<R>;
+  const size_t patch = align16(static_cast<size_t>(p->P) * p->P * sizeof(C));
+  const size_t tabb = static_cast<size_t>(a.tlen) * sizeof(R);
+  size_t lds = patch;
+  if (MODE == 1 && lds < kThreads * sizeof(double)) lds = kThreads * sizeof(double);
+  const int G = degrid_blocks(p);
+  if (lds + tabb <= kLdsSoft) {
+    degrid_kernel<R, J, MODE, true><<<G, kThreads, lds + tabb, s>>>(a);
+  } else if (lds <= kLdsHard) {
+    PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false>, lds));
+    degrid_kernel<R, J, MODE, false><<<G, kThreads, lds, s>>>(a);
+  } else {
+    set_error("degridding patch of tile %d does not fit in LDS", p->T);
+    return PR_EUNSUPPORTED;
+  }
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+// Staging depth B and table placement: fit two blocks per CU if possible,
+// else use up to the whole 160 KB.
+template <typename R, int J>
+bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
+  const size_t limits[2] = {kLdsSoft, kLdsHard};
+  for (size_t lim : limits) {
+    for (int tl = 1; tl >= 0; --tl) {
+      for (int b = 256; b >= 32; b /= 2) {
+        GridLds<R, J> g(T, b, tlen, tl != 0);
+        if (g.total <= lim) {
+          *B = b;
+          *tab_lds = tl != 0;
+          *bytes = g.total;
+          return true;
+        }
+      }
+    }
+  }
+  return false;
+}
+
+template <typename R, int J, int MODE>
+int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s) {
+  using C = cx_t<R>;
+  const int G = degrid_blocks(p);
+  int B;
+  bool tab_lds;
+  size_t bytes;
+  if (!pick_grid_lds<R, J>(a.T, a.tlen, &B, &tab_lds, &bytes)) {
+    set_error("gridding tile %d with J=%d does not fit in LDS", a.T, J);
+    return PR_EUNSUPPORTED;
+  }
+  a.B = B;
+  if (tab_lds) {
+    PR_TRY(allow_lds(grid_kernel<R, J, MODE, true>, bytes));
+    grid_kernel<R, J, MODE, true><<<G, kThreads, bytes, s>>>(a);
+  } else {
+    PR_TRY(allow_lds(grid_kernel<R, J, MODE, false>, bytes));
+    grid_kernel<R, J, MODE, false><<<G, kThreads, bytes, s>>>(a);
+  }
+  PR_TRY_LAUNCH();
+  const int64_t K2 = static_cast<int64_t>(p->K) * p->K;
+  merge_patches_kernel<R><<<grid_for(K2, kThreads, 8192), kThreads, 0, s>>>(
+      static_cast<const C*>(p->patches), p->item_off, static_cast<C*>(p->grid), p->K, p->T, p->P, p->nT, p->J);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+template <typename R>
+GwArgs<R> gw_args(pr_phi_plan_t* p, double scale) {
+  GwArgs<R> a{};
+  a.grid = static_cast<const cx_t<R>*>(p->grid);
+  a.table = static_cast<const R*>(p->table);
+  a.uv = static_cast<const R*>(p->uv);
+  a.w = static_cast<const R*>(p->w);
+  a.items = p->items;
+  a.nItems = p->nItems;
+  a.K = p->K; a.T = p->T; a.P = p->P; a.nT = p->nT; a.D = p->D;
+  a.tlen = p->J * p->D / 2 + 1;
+  a.kappa = p->kappa;
+  a.scale = static_cast<R>(scale);
+  return a;
+}
+
+template <typename R>
+GwAdjArgs<R> gwadj_args(pr_phi_plan_t* p, double scale) {
+  GwAdjArgs<R> a{};
+  a.table = static_cast<const R*>(p->table);
+  a.uv = static_cast<const R*>(p->uv);
+  a.w = static_cast<const R*>(p->w);
+  a.items = p->items;
+  a.nItems = p->nItems;
+  a.K = p->K; a.T = p->T; a.P = p->P; a.nT = p->nT; a.D = p->D;
+  a.tlen = p->J * p->D / 2 + 1;
+  a.kappa = p->kappa;
+  a.scale = static_cast<R>(scale);
+  a.patches = static_cast<cx_t<R>*>(p->patches);
+  return a;
+}
+
+#define PR_DISPATCH_J(J, CALL) \
+  switch (J) {                 \
+    case 2: return CALL(2);    \
+    case 4: return CALL(4);    \
+    case 6: return CALL(6);    \
+    case 8: return CALL(8);    \
+    default: set_error("J = %d unsupported", J); return PR_EUNSUPPORTED; \
+  }
+
+template <typename R>
+int gw_plain(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {
+  GwArgs<R> a = gw_args<R>(p, scale);
+  a.y_out = static_cast<cx_t<R>*>(y);
+#define CALL(JJ) launch_degrid<R, JJ, 0>(p, a, s)
+  PR_DISPATCH_J(p->J, CALL)
+#undef CALL
+}
+
+template <typename R>
+int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
+  GwArgs<R> a = gw_args<R>(p, scale);
+  a.y_obs = static_cast<const cx_t<R>*>(v.y);
+  a.s_in = static_cast<const cx_t<R>*>(v.s);
+  a.t_out = static_cast<cx_t<R>*>(v.t);
+  a.partials = p->partials;
+  int rc;
+#define CALL(JJ) launch_degrid<R, JJ, 1>(p, a, s)
+  switch (p->J) {
+    case 2: rc = CALL(2); break;
+    case 4: rc = CALL(4); break;
+    case 6: rc = CALL(6); break;
+    case 8: rc = CALL(8); break;
+    default: set_error("J = %d unsupported", p->J); return PR_EUNSUPPORTED;
+  }
+#undef CALL
+  if (rc != PR_OK) return rc;
+  ball_scale_kernel<<<1, kThreads, 0, s>>>(p->partials, degrid_blocks(p), v.eps, v.sums);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+template <typename R>
+int gwadj_plain(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s) {
+  GwAdjArgs<R> a = gwadj_args<R>(p, scale);
+  a.y_in = static_cast<const cx_t<R>*>(y);
+#define CALL(JJ) launch_grid<R, JJ, 0>(p, a, s)
+  PR_DISPATCH_J(p->J, CALL)
+#undef CALL
+}
+
+template <typename R>
+int gwadj_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
+  GwAdjArgs<R> a = gwadj_args<R>(p, scale);
+  a.t_in = static_cast<const cx_t<R>*>(v.t);
+  a.s_io = static_cast<cx_t<R>*>(v.s);
+  a.scalars = v.sums;
+  a.varrho = static_cast<R>(v.varrho);
+#define CALL(JJ) launch_grid<R, JJ, 1>(p, a, s)
+  PR_DISPATCH_J(p->J, CALL)
+#undef CALL
+}
+
+template <typename R>
+__global__ void zero_cx_kernel(cx_t<R>* a, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = cmk<cx_t<R>>(R(0), R(0));
+}
+
+}  // namespace
+
+int phi_gw(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {
+  if (p->M == 0) return PR_OK;
+  return p->prec == PR_F32 ? gw_plain<float>(p, y, scale, s) : gw_plain<double>(p, y, scale, s);
+}
+
+int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s) {
+  if (p->nItems == 0) {
+    const int64_t K2 = static_cast<int64_t>(p->K) * p->K;
+    if (p->prec == PR_F32)
+      zero_cx_kernel<float><<<grid_for(K2, 256, 4096), 256, 0, s>>>(static_cast<float2*>(p->grid), K2);
+    else
+      zero_cx_kernel<double><<<grid_for(K2, 256, 4096), 256, 0, s>>>(static_cast<double2*>(p->grid), K2);
+    PR_TRY_LAUNCH();
+    return PR_OK;
+  }
+  return p->prec == PR_F32 ? gwadj_plain<float>(p, y, scale, s) : gwadj_plain<double>(p, y, scale, s);
+}
+
+int phi_gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
+  if (p->nItems == 0) {
+    set_error("ADMM needs at least one visibility");
+    return PR_EINVAL;
+  }
+  return p->prec == PR_F32 ? gw_admm<float>(p, v, scale, s) : gw_admm<double>(p, v, scale, s);
+}
+
+int phi_gw_adjoint_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
+  return p->prec == PR_F32 ? gwadj_admm<float>(p, v, scale, s) : gwadj_admm<double>(p, v, scale, s);
+}
+
+}  // namespace pr

@@ -1,0 +1,217 @@
+// Element-wise proximal operators (Section "Proximal Operators"), FP64
+// deterministic reductions and the power method for ||Phi|| (Section
+// "Distributed Images").
+#include "ops.hpp"
+
+namespace pr {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRedBlocks = 1024;   // fixed grid of the reduction first stage
+
+template <typename R>
+__global__ void soft_threshold_kernel(const R* in, R* out, int64_t len, R lam) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const R v = in[i];
+    const R m = fabs(v);
+    out[i] = m > lam ? v * ((m - lam) / m) : R(0);
+  }
+}
+
+template <typename R>
+__global__ void soft_threshold_cx_kernel(const cx_t<R>* in, cx_t<R>* out, int64_t len, R lam) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const cx_t<R> v = in[i];
+    const R m = hypot(v.x, v.y);
+    const R f = m > lam ? (m - lam) / m : R(0);
+    out[i] = cmk<cx_t<R>>(v.x * f, v.y * f);
+  }
+}
+
+// Stage 1: per-block FP64 sums of |a - b|^2 (b may be null) over a fixed
+// grid-stride partition; stage 2 sums the block results in index order.
+template <typename R>
+__global__ void sumsq_stage1(const R* a, const R* b, int64_t len, double* partials) {
+  __shared__ double sh[kThreads];
+  double acc = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double d = b ? static_cast<double>(a[i]) - static_cast<double>(b[i]) : static_cast<double>(a[i]);
+    acc += d * d;
+  }
+  acc = block_sum_f64(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+template <typename R>
+__global__ void abssum_stage1(const R* a, int64_t len, double* partials) {
+  __shared__ double sh[kThreads];
+  double acc = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    acc += fabs(static_cast<double>(a[i]));
+  acc = block_sum_f64(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ void sum_stage2(const double* partials, int n, double* out, double* nonfinite_flag) {
+  __shared__ double sh[kThreads];
+  double acc = 0;
+  for (int i = threadIdx.x; i < n; i += kThreads) acc += partials[i];
+  acc = block_sum_f64(acc, sh);
+  if (threadIdx.x == 0) {
+    *out = acc;
+    if (nonfinite_flag && !isfinite(acc)) *nonfinite_flag = 1.0;
+  }
+}
+
+// out = center + (in - center) * min(1, eps / sqrt(*d2)); closed ball.
+template <typename R>
+__global__ void ball_apply_kernel(const cx_t<R>* in, const cx_t<R>* center, cx_t<R>* out, int64_t len,
+                                  const double* d2, double eps) {
+  const double d = sqrt(*d2);
+  const R k = static_cast<R>(d <= eps ? 1.0 : eps / d);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const cx_t<R> v = in[i], c = center[i];
+    out[i] = cmk<cx_t<R>>(c.x + k * (v.x - c.x), c.y + k * (v.y - c.y));
+  }
+}
+
+template <typename R>
+__global__ void fill_kernel(R* a, int64_t len, R v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+
+// a = b / sqrt(*s2)
+template <typename R>
+__global__ void normalise_kernel(R* a, const R* b, int64_t len, const double* s2) {
+  const R inv = static_cast<R>(1.0 / sqrt(*s2));
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = b[i] * inv;
+}
+
+}  // namespace
+
+int reduce_sumsq(const void* a, const void* b, int64_t len, int prec, double* partials, double* out,
+                 hipStream_t s, double* nonfinite_flag) {
+  const int G = grid_for(len, kThreads, kRedBlocks);
+  if (prec == PR_F32)
+    sumsq_stage1<float><<<G, kThreads, 0, s>>>(static_cast<const float*>(a), static_cast<const float*>(b), len, partials);
+  else
+    sumsq_stage1<double><<<G, kThreads, 0, s>>>(static_cast<const double*>(a), static_cast<const double*>(b), len,
+                                                partials);
+  PR_TRY_LAUNCH();
+  sum_stage2<<<1, kThreads, 0, s>>>(partials, G, out, nonfinite_flag);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int reduce_abssum(const void* a, int64_t len, int prec, double* partials, double* out, hipStream_t s) {
+  const int G = grid_for(len, kThreads, kRedBlocks);
+  if (prec == PR_F32)
+    abssum_stage1<float><<<G, kThreads, 0, s>>>(static_cast<const float*>(a), len, partials);
+  else
+    abssum_stage1<double><<<G, kThreads, 0, s>>>(static_cast<const double*>(a), len, partials);
+  PR_TRY_LAUNCH();
+  sum_stage2<<<1, kThreads, 0, s>>>(partials, G, out, nullptr);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int soft_threshold(const void* in, void* out, int64_t len, int is_complex, int prec, double lam, hipStream_t s) {
+  if (len == 0) return PR_OK;
+  const int G = grid_for(len, kThreads, 8192);
+  if (prec == PR_F32) {
+    if (is_complex)
+      soft_threshold_cx_kernel<float><<<G, kThreads, 0, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out),
+                                                             len, static_cast<float>(lam));
+    else
+      soft_threshold_kernel<float><<<G, kThreads, 0, s>>>(static_cast<const float*>(in), static_cast<float*>(out), len,
+                                                          static_cast<float>(lam));
+  } else {
+    if (is_complex)
+      soft_threshold_cx_kernel<double><<<G, kThreads, 0, s>>>(static_cast<const double2*>(in),
+                                                              static_cast<double2*>(out), len, lam);
+    else
+      soft_threshold_kernel<double><<<G, kThreads, 0, s>>>(static_cast<const double*>(in), static_cast<double*>(out),
+                                                           len, lam);
+  }
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+size_t ball_scratch_bytes() { return (kRedBlocks + 8) * sizeof(double); }
+
+int proj_l2ball(const void* in, const void* center, void* out, int64_t len, int prec, double eps, void* scratch,
+                double* dist, hipStream_t s) {
+  double* partials = static_cast<double*>(scratch);
+  double* d2 = partials + kRedBlocks;
+  // ||in - center||^2 over the real and imaginary parts: 2 len real values
+  PR_TRY(reduce_sumsq(in, center, 2 * len, prec, partials, d2, s, nullptr));
+  if (len > 0) {
+    const int G = grid_for(len, kThreads, 8192);
+    if (prec == PR_F32)
+      ball_apply_kernel<float><<<G, kThreads, 0, s>>>(static_cast<const float2*>(in), static_cast<const float2*>(center),
+                                                      static_cast<float2*>(out), len, d2, eps);
+    else
+      ball_apply_kernel<double><<<G, kThreads, 0, s>>>(static_cast<const double2*>(in),
+                                                       static_cast<const double2*>(center), static_cast<double2*>(out),
+                                                       len, d2, eps);
+    PR_TRY_LAUNCH();
+  }
+  if (dist) {
+    double h = 0;
+    PR_TRY_HIP(hipMemcpyAsync(&h, d2, sizeof(double), hipMemcpyDeviceToHost, s));
+    PR_TRY_HIP(hipStreamSynchronize(s));
+    *dist = std::sqrt(h);
+  }
+  return PR_OK;
+}
+
+int fill_real(void* a, int64_t len, int prec, double v, hipStream_t s) {
+  const int G = grid_for(len, kThreads, 8192);
+  if (prec == PR_F32)
+    fill_kernel<float><<<G, kThreads, 0, s>>>(static_cast<float*>(a), len, static_cast<float>(v));
+  else
+    fill_kernel<double><<<G, kThreads, 0, s>>>(static_cast<double*>(a), len, v);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int normalise(void* a, const void* b, int64_t len, int prec, const double* s2, hipStream_t s) {
+  const int G = grid_for(len, kThreads, 8192);
+  if (prec == PR_F32)
+    normalise_kernel<float><<<G, kThreads, 0, s>>>(static_cast<float*>(a), static_cast<const float*>(b), len, s2);
+  else
+    normalise_kernel<double><<<G, kThreads, 0, s>>>(static_cast<double*>(a), static_cast<const double*>(b), len, s2);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int phi_norm(pr_phi_plan_t* p, int iters, void* vis, double* norm, hipStream_t s) {
+  const int64_t N = static_cast<int64_t>(p->n) * p->n;
+  double* s2 = p->scalars + 8;
+  PR_TRY(fill_real(p->img_a, N, p->prec, 1.0 / p->n, s));
+  for (int it = 0; it < iters; ++it) {
+    PR_TRY(phi_fzs(p, p->img_a, s));
+    PR_TRY(phi_gw(p, vis, 1.0, s));
+    PR_TRY(phi_gw_adjoint(p, vis, 1.0, s));
+    PR_TRY(phi_fzs_adjoint(p, p->img_b, s));
+    PR_TRY(reduce_sumsq(p->img_b, nullptr, N, p->prec, p->partials, s2, s, nullptr));
+    PR_TRY(normalise(p->img_a, p->img_b, N, p->prec, s2, s));
+  }
+  double h = 0;
+  PR_TRY_HIP(hipMemcpyAsync(&h, s2, sizeof(double), hipMemcpyDeviceToHost, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));
+  *norm = iters > 0 ? std::sqrt(std::sqrt(h)) : 0.0;
+  return PR_OK;
+}
+
+}  // namespace pr

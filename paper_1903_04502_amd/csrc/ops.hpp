@@ -1,0 +1,23 @@
+// Element-wise operators and reductions shared by the operator and solver code.
+#pragma once
+
+#include <cmath>
+
+#include "phi.hpp"
+
+namespace pr {
+
+// *out = sum |a - b|^2 over len real values (b may be null), FP64, fixed order.
+int reduce_sumsq(const void* a, const void* b, int64_t len, int prec, double* partials, double* out,
+                 hipStream_t s, double* nonfinite_flag);
+// *out = sum |a| over len real values, FP64, fixed order.
+int reduce_abssum(const void* a, int64_t len, int prec, double* partials, double* out, hipStream_t s);
+int soft_threshold(const void* in, void* out, int64_t len, int is_complex, int prec, double lam, hipStream_t s);
+size_t ball_scratch_bytes();
+int proj_l2ball(const void* in, const void* center, void* out, int64_t len, int prec, double eps, void* scratch,
+                double* dist, hipStream_t s);
+int fill_real(void* a, int64_t len, int prec, double v, hipStream_t s);
+// a = b / sqrt(*s2) (device scalar)
+int normalise(void* a, const void* b, int64_t len, int prec, const double* s2, hipStream_t s);
+
+}  // namespace pr

@@ -1,0 +1,79 @@
+// Internal state of a measurement-operator plan and the launchers that act on
+// it. The operator is Phi = W G F Z S of eq. (matrix_equation).
+#pragma once
+
+#include "common.hpp"
+
+struct pr_phi_plan_t {
+  pr_phi_desc desc;
+  int n = 0, K = 0, J = 0, D = 0, T = 0;
+  int P = 0;        // patch side of one tile: T + J - 1
+  int nT = 0;       // tiles per grid side
+  int nTiles = 0;
+  int prec = PR_F32;
+  int64_t M = 0;
+  int64_t nItems = 0, nItemsMax = 0;
+  int chunk = 0;    // max visibilities per gridding work item
+  double kappa = 0; // K / (2 pi)
+  double beta = 0;  // Kaiser-Bessel shape
+
+  // persistent workspace
+  void* uv = nullptr;          // sorted (u, v) pairs, Real[2M]
+  void* w = nullptr;           // sorted weights, Real[M]
+  int32_t* perm = nullptr;     // plan position -> user index
+  int32_t* item_off = nullptr; // per tile first work item, [nTiles + 1]
+  int4* items = nullptr;       // (tile, begin, end, 0)
+  void* table = nullptr;       // Real[J*D/2 + 1]
+  void* corr = nullptr;        // Real[n]
+  void* tw = nullptr;          // complex[K], e^{-2 pi i m / K}
+
+  // scratch workspace
+  void* grid = nullptr;        // complex[K*K], row = v cell, column = u cell
+  void* fft_tmp = nullptr;     // complex[n*K]
+  void* patches = nullptr;     // complex[nItemsMax * P * P]
+  double* partials = nullptr;  // FP64 per-block partial sums
+  double* scalars = nullptr;   // FP64 device scalars
+  void* img_a = nullptr;       // Real[n*n]
+  void* img_b = nullptr;       // Real[n*n]
+};
+
+namespace pr {
+
+constexpr int kPartialsMax = 4096;     // per-block partials, per quantity slot
+constexpr int kPartialSlots = 4;
+constexpr int kScalars = 64;
+
+// Sizes of the two workspaces for a descriptor (validated beforehand).
+int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch,
+               size_t* persistent_bytes, size_t* scratch_bytes);
+int phi_validate(const pr_phi_desc* d);
+// Geometry (sizes, tile, kernel shape) from a validated descriptor.
+int phi_prepare(pr_phi_plan_t* p, const pr_phi_desc* d);
+int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s);
+
+// Operator stages.
+int phi_fzs(pr_phi_plan_t* p, const void* x, hipStream_t s);
+int phi_fzs_adjoint(pr_phi_plan_t* p, void* x, hipStream_t s);
+int phi_gw(pr_phi_plan_t* p, void* y, double scale, hipStream_t s);
+int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s);
+int phi_norm(pr_phi_plan_t* p, int iters, void* vis, double* norm, hipStream_t s);
+
+// Fused ADMM stages (defined with the operator kernels).
+struct AdmmVis {
+  const void* y;   // observed visibilities
+  void* s;         // Lagrange multiplier, updated in place by the gridding stage
+  void* t;         // v + s - y, written by the degridding stage
+  double* sums;    // device: [0] ||t||^2, [1] ||v - y||^2 (FP64)
+  double eps, varrho;
+};
+int phi_gw_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);
+int phi_gw_adjoint_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);
+// x_out = x_in - rho * Re(S Z^T F^H grid), and zbar = max(x_out, 0).
+int phi_fzs_adjoint_step(pr_phi_plan_t* p, const void* x_in, double rho, void* x_out,
+                         void* zbar, hipStream_t s);
+
+// FP64 deterministic reductions over device arrays.
+int reduce_sq_f64(const void* a, const void* b, int64_t len, int prec, int is_complex,
+                  double* partials, double* out, hipStream_t s);
+
+}  // namespace pr

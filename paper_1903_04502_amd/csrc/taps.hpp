@@ -1,0 +1,50 @@
+// Interpolation taps of the pre-sampled Kaiser-Bessel kernel (Section "Kernel
+// Pre-Sampling": the kernel is sampled on 0 <= |t| <= J/2 and read by
+// zeroth-order interpolation, i.e. the nearest sample).
+//
+// For a baseline coordinate u (radians per pixel) the continuous grid
+// coordinate is s = u * K / (2 pi), formed in FP64. Tap a (a = 0..J-1) sits
+// on cell floor(s) - J/2 + 1 + a at distance t_a = |s - cell|; it uses table
+// sample round(t_a * D) with ties to the larger distance. With
+// f = (s - floor(s)) * D and m = J/2 - 1 - a this is m*D + round_half_up(f)
+// for m >= 0 and |m|*D - round_half_down(f) for m < 0. All of it is FP64 with
+// FMA contraction disabled, so every caller picks exactly the same samples.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pr {
+
+struct AxisTaps {
+  int j0;     // first tap cell, not reduced mod K
+  int up;     // round_half_up(f)
+  int dn;     // round_half_down(f)
+};
+
+__device__ __forceinline__ AxisTaps axis_taps(double u, double kappa, int J, int D) {
+#pragma clang fp contract(off)
+  const double s = u * kappa;
+  const double fl = floor(s);
+  const double fr = s - fl;
+  const double f = fr * static_cast<double>(D);
+  const double ff = floor(f);
+  const double r = f - ff;
+  AxisTaps t;
+  t.j0 = static_cast<int>(fl) - J / 2 + 1;
+  t.up = static_cast<int>(ff) + (r >= 0.5 ? 1 : 0);
+  t.dn = static_cast<int>(ff) + (r > 0.5 ? 1 : 0);
+  return t;
+}
+
+// Table index of tap a.
+__device__ __forceinline__ int tap_index(const AxisTaps& t, int a, int J, int D) {
+  const int m = J / 2 - 1 - a;
+  return m >= 0 ? m * D + t.up : (-m) * D - t.dn;
+}
+
+__device__ __forceinline__ int mod_pos(int a, int K) {
+  int r = a % K;
+  return r < 0 ? r + K : r;
+}
+
+}  // namespace pr

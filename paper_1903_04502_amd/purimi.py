@@ -1,0 +1,362 @@
+"""Thin Python binding of the gfx950 library (include/purimi.h).
+
+Functions named ``pr_*`` mirror the C entry points one to one and only
+marshal arguments: device tensors become pointers, and the stream is torch's
+current stream on the tensors' device. The plan classes at the bottom hold the
+caller-owned workspaces as torch tensors (torch is the device allocator).
+
+Nothing here computes any part of the method; if ``libpurimi.so`` is missing
+every call raises (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpurimi.so")
+
+PR_OK, PR_EINVAL, PR_EWORKSPACE, PR_EHIP, PR_EUNSUPPORTED = 0, 1, 2, 3, 4
+PR_F32, PR_F64 = 0, 1
+
+
+class PrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"purimi error {code}: {msg}")
+        self.code = code
+
+
+class pr_phi_desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("oversample", C.c_int32), ("J", C.c_int32), ("D", C.c_int32),
+                ("M", C.c_int64), ("prec", C.c_int32), ("tile", C.c_int32)]
+
+
+class pr_admm_params(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("inner_iters", C.c_int32), ("eps", C.c_double),
+                ("gamma", C.c_double), ("rho", C.c_double), ("varrho", C.c_double),
+                ("eta", C.c_double), ("rel_tol", C.c_double), ("op_norm", C.c_double)]
+
+
+class pr_admm_report(C.Structure):
+    _fields_ = [("iters_done", C.c_int32), ("rel_var", C.c_double), ("resid_norm", C.c_double),
+                ("l1_norm", C.c_double), ("op_norm", C.c_double), ("nonfinite", C.c_int32)]
+
+
+_VP, _I32, _I64, _U32, _D, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double, C.c_size_t
+_SIGS = {
+    "pr_last_error": (C.c_char_p, []),
+    "pr_version": (C.c_int, []),
+    "pr_phi_plan_sizes": (C.c_int, [C.POINTER(pr_phi_desc), C.POINTER(_SZ), C.POINTER(_SZ)]),
+    "pr_phi_plan_create": (C.c_int, [C.POINTER(pr_phi_desc), _VP, _VP, _VP, _VP, _VP, C.POINTER(_VP)]),
+    "pr_phi_plan_destroy": (C.c_int, [_VP]),
+    "pr_phi_plan_perm": (C.c_int, [_VP, C.POINTER(_VP)]),
+    "pr_phi_plan_perm_copy": (C.c_int, [_VP, _VP, _VP]),
+    "pr_phi_plan_items": (C.c_int, [_VP, C.POINTER(_I64)]),
+    "pr_phi_apply": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pr_phi_adjoint": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pr_phi_fzs": (C.c_int, [_VP, _VP, _VP]),
+    "pr_phi_gw": (C.c_int, [_VP, _VP, _VP]),
+    "pr_phi_gw_adjoint": (C.c_int, [_VP, _VP, _VP]),
+    "pr_phi_fzs_adjoint": (C.c_int, [_VP, _VP, _VP]),
+    "pr_phi_norm": (C.c_int, [_VP, _I32, _VP, C.POINTER(_D), _VP]),
+    "pr_psi_plan_sizes": (C.c_int, [_I32, _I32, _U32, _I32, C.POINTER(_SZ), C.POINTER(_SZ)]),
+    "pr_psi_plan_create": (C.c_int, [_I32, _I32, _U32, _I32, _VP, _VP, _VP, C.POINTER(_VP)]),
+    "pr_psi_plan_destroy": (C.c_int, [_VP]),
+    "pr_psi_plan_bases": (C.c_int, [_VP, C.POINTER(_I32)]),
+    "pr_psi_filter": (C.c_int, [_VP, _I32, C.POINTER(_D)]),
+    "pr_psi_apply": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pr_psi_adjoint": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "pr_prox_l1": (C.c_int, [_VP, _VP, _I64, _I32, _I32, _D, _VP]),
+    "pr_proj_l2ball_scratch_bytes": (_SZ, [_I64]),
+    "pr_proj_l2ball": (C.c_int, [_VP, _VP, _VP, _I64, _I32, _D, _VP, C.POINTER(_D), _VP]),
+    "pr_admm_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
+    "pr_admm_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_admm_params), _VP, _VP,
+                                C.POINTER(pr_admm_report), _VP]),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libpurimi.so (built in place by ``build()``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1903_04502_amd.build.build()")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int):
+    if rc != PR_OK:
+        raise PrError(rc, lib().pr_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(device=None):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _prec_of(dtype) -> int:
+    if dtype in (torch.float32, torch.complex64):
+        return PR_F32
+    if dtype in (torch.float64, torch.complex128):
+        return PR_F64
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+# --------------------------------------------------------------------------
+# one-to-one wrappers (same names as the C symbols)
+# --------------------------------------------------------------------------
+def pr_last_error() -> str:
+    return lib().pr_last_error().decode()
+
+
+def pr_version() -> int:
+    return lib().pr_version()
+
+
+def pr_phi_plan_sizes(desc: pr_phi_desc):
+    p, s = _SZ(), _SZ()
+    _check(lib().pr_phi_plan_sizes(C.byref(desc), C.byref(p), C.byref(s)))
+    return p.value, s.value
+
+
+def pr_phi_plan_create(desc, uv, w, persistent, scratch, stream=None):
+    h = _VP()
+    _check(lib().pr_phi_plan_create(C.byref(desc), _ptr(uv), _ptr(w), _ptr(persistent), _ptr(scratch),
+                                    stream if stream is not None else _stream(), C.byref(h)))
+    return h.value
+
+
+def pr_phi_plan_destroy(plan):
+    _check(lib().pr_phi_plan_destroy(plan))
+
+
+def pr_phi_plan_perm(plan) -> int:
+    p = _VP()
+    _check(lib().pr_phi_plan_perm(plan, C.byref(p)))
+    return p.value
+
+
+def pr_phi_plan_perm_copy(plan, dst, stream=None):
+    _check(lib().pr_phi_plan_perm_copy(plan, _ptr(dst), stream if stream is not None else _stream()))
+
+
+def pr_phi_plan_items(plan) -> int:
+    v = _I64()
+    _check(lib().pr_phi_plan_items(plan, C.byref(v)))
+    return v.value
+
+
+def pr_phi_apply(plan, x, y, stream=None):
+    _check(lib().pr_phi_apply(plan, _ptr(x), _ptr(y), stream if stream is not None else _stream()))
+
+
+def pr_phi_adjoint(plan, y, x, stream=None):
+    _check(lib().pr_phi_adjoint(plan, _ptr(y), _ptr(x), stream if stream is not None else _stream()))
+
+
+def pr_phi_fzs(plan, x, stream=None):
+    _check(lib().pr_phi_fzs(plan, _ptr(x), stream if stream is not None else _stream()))
+
+
+def pr_phi_gw(plan, y, stream=None):
+    _check(lib().pr_phi_gw(plan, _ptr(y), stream if stream is not None else _stream()))
+
+
+def pr_phi_gw_adjoint(plan, y, stream=None):
+    _check(lib().pr_phi_gw_adjoint(plan, _ptr(y), stream if stream is not None else _stream()))
+
+
+def pr_phi_fzs_adjoint(plan, x, stream=None):
+    _check(lib().pr_phi_fzs_adjoint(plan, _ptr(x), stream if stream is not None else _stream()))
+
+
+def pr_phi_norm(plan, iters, vis_ws, stream=None) -> float:
+    v = _D()
+    _check(lib().pr_phi_norm(plan, iters, _ptr(vis_ws), C.byref(v), stream if stream is not None else _stream()))
+    return v.value
+
+
+def pr_psi_plan_sizes(n, levels, mask, prec):
+    p, s = _SZ(), _SZ()
+    _check(lib().pr_psi_plan_sizes(n, levels, mask, prec, C.byref(p), C.byref(s)))
+    return p.value, s.value
+
+
+def pr_psi_plan_create(n, levels, mask, prec, persistent, scratch, stream=None):
+    h = _VP()
+    _check(lib().pr_psi_plan_create(n, levels, mask, prec, _ptr(persistent), _ptr(scratch),
+                                    stream if stream is not None else _stream(), C.byref(h)))
+    return h.value
+
+
+def pr_psi_plan_destroy(plan):
+    _check(lib().pr_psi_plan_destroy(plan))
+
+
+def pr_psi_plan_bases(plan) -> int:
+    v = _I32()
+    _check(lib().pr_psi_plan_bases(plan, C.byref(v)))
+    return v.value
+
+
+def pr_psi_filter(plan, k):
+    buf = (_D * (2 * k))()
+    _check(lib().pr_psi_filter(plan, k, buf))
+    return list(buf)
+
+
+def pr_psi_apply(plan, alpha, x, stream=None):
+    _check(lib().pr_psi_apply(plan, _ptr(alpha), _ptr(x), stream if stream is not None else _stream()))
+
+
+def pr_psi_adjoint(plan, x, alpha, stream=None):
+    _check(lib().pr_psi_adjoint(plan, _ptr(x), _ptr(alpha), stream if stream is not None else _stream()))
+
+
+def pr_prox_l1(inp, out, lam, stream=None):
+    is_c = 1 if inp.is_complex() else 0
+    _check(lib().pr_prox_l1(_ptr(inp), _ptr(out), inp.numel(), is_c, _prec_of(inp.dtype), float(lam),
+                            stream if stream is not None else _stream()))
+
+
+def pr_proj_l2ball_scratch_bytes(length: int) -> int:
+    return lib().pr_proj_l2ball_scratch_bytes(length)
+
+
+def pr_proj_l2ball(inp, center, out, eps, scratch, want_dist=False, stream=None):
+    d = _D()
+    _check(lib().pr_proj_l2ball(_ptr(inp), _ptr(center), _ptr(out), inp.numel(), _prec_of(inp.dtype), float(eps),
+                                _ptr(scratch), C.byref(d) if want_dist else None,
+                                stream if stream is not None else _stream()))
+    return d.value if want_dist else None
+
+
+def pr_admm_workspace_size(phi, psi) -> int:
+    v = _SZ()
+    _check(lib().pr_admm_workspace_size(phi, psi, C.byref(v)))
+    return v.value
+
+
+def pr_admm_solve(phi, psi, y, params: pr_admm_params, x, workspace, want_report=True, stream=None):
+    rep = pr_admm_report()
+    _check(lib().pr_admm_solve(phi, psi, _ptr(y), C.byref(params), _ptr(x), _ptr(workspace),
+                               C.byref(rep) if want_report else None, stream if stream is not None else _stream()))
+    return rep if want_report else None
+
+
+# --------------------------------------------------------------------------
+# plan holders: workspaces are torch tensors on the plan's device
+# --------------------------------------------------------------------------
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class PhiPlan:
+    """Measurement operator plan for one set of baselines (see pr_phi_plan_create)."""
+
+    def __init__(self, n, uv, w=None, J=4, D=2000, oversample=2, tile=0, prec=None):
+        dev = uv.device
+        self.prec = _prec_of(uv.dtype) if prec is None else prec
+        self.rdtype = torch.float32 if self.prec == PR_F32 else torch.float64
+        self.cdtype = torch.complex64 if self.prec == PR_F32 else torch.complex128
+        M = uv.shape[0]
+        self.desc = pr_phi_desc(n, oversample, J, D, M, self.prec, tile)
+        self.n, self.M, self.device = n, M, dev
+        pb, sb = pr_phi_plan_sizes(self.desc)
+        self.persistent = _workspace(pb, dev)
+        self.scratch = _workspace(sb, dev)
+        uv = uv.contiguous()
+        w = None if w is None else w.contiguous()
+        self.handle = pr_phi_plan_create(self.desc, uv, w, self.persistent, self.scratch, _stream(dev))
+        self.items = pr_phi_plan_items(self.handle)
+
+    def perm(self) -> torch.Tensor:
+        """plan position -> user index (int64 device tensor)."""
+        out = torch.empty(self.M, dtype=torch.int32, device=self.device)
+        pr_phi_plan_perm_copy(self.handle, out, _stream(self.device))
+        return out.to(torch.int64)
+
+    def apply(self, x, y=None):
+        y = torch.empty(self.M, dtype=self.cdtype, device=self.device) if y is None else y
+        pr_phi_apply(self.handle, x, y)
+        return y
+
+    def adjoint(self, y, x=None):
+        x = torch.empty((self.n, self.n), dtype=self.rdtype, device=self.device) if x is None else x
+        pr_phi_adjoint(self.handle, y, x)
+        return x
+
+    def norm(self, iters=100):
+        vis = torch.empty(max(self.M, 1), dtype=self.cdtype, device=self.device)
+        return pr_phi_norm(self.handle, iters, vis)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.pr_phi_plan_destroy(h)
+            self.handle = None
+
+
+class PsiPlan:
+    """SARA dictionary plan (see pr_psi_plan_create)."""
+
+    def __init__(self, n, levels, mask=0x1FF, prec=PR_F32, device="cuda"):
+        self.n, self.levels, self.mask, self.prec = n, levels, mask, prec
+        self.rdtype = torch.float32 if prec == PR_F32 else torch.float64
+        pb, sb = pr_psi_plan_sizes(n, levels, mask, prec)
+        self.device = torch.device(device)
+        self.persistent = _workspace(pb, self.device)
+        self.scratch = _workspace(sb, self.device)
+        self.handle = pr_psi_plan_create(n, levels, mask, prec, self.persistent, self.scratch, _stream(self.device))
+        self.nb = pr_psi_plan_bases(self.handle)
+
+    def adjoint(self, x, alpha=None):
+        alpha = torch.empty((self.nb, self.n, self.n), dtype=self.rdtype, device=self.device) if alpha is None else alpha
+        pr_psi_adjoint(self.handle, x, alpha)
+        return alpha
+
+    def apply(self, alpha, x=None):
+        x = torch.empty((self.n, self.n), dtype=self.rdtype, device=self.device) if x is None else x
+        pr_psi_apply(self.handle, alpha, x)
+        return x
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.pr_psi_plan_destroy(h)
+            self.handle = None
+
+
+def admm_params(eps, gamma, iters=50, inner_iters=1, rho=0.5, varrho=1.0, eta=1.0, rel_tol=0.0, op_norm=0.0):
+    return pr_admm_params(iters, inner_iters, eps, gamma, rho, varrho, eta, rel_tol, op_norm)
+
+
+def admm_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_admm_params, x0=None, want_report=True):
+    """Run Algorithm 1; returns (x, report). x is in normalised-operator units."""
+    ws = _workspace(pr_admm_workspace_size(phi.handle, psi.handle), phi.device)
+    x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
+    rep = pr_admm_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
+    return x, rep

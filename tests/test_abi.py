@@ -1,0 +1,114 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad
+arguments with the documented codes before touching a GPU (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "purimi.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1903_04502_amd import purimi
+    if not os.path.exists(purimi.LIB_PATH):
+        from paper_1903_04502_amd import build
+        build.build(verbose=False)
+    purimi.lib()
+    return purimi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound(P):
+    names = declared_functions()
+    assert len(names) >= 20
+    h = C.CDLL(P.LIB_PATH)
+    for name in names:
+        assert hasattr(h, name), name
+    assert sorted(P.exported_symbols()) == names
+
+
+def test_version_and_error_text(P):
+    assert P.pr_version() >= 10000
+    with pytest.raises(P.PrError) as e:
+        P.pr_phi_plan_sizes(P.pr_phi_desc(100, 2, 4, 2000, 10, 0, 0))
+    assert e.value.code == P.PR_EINVAL
+    assert "power of two" in P.pr_last_error()
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n", 4, 1), ("n", 8192, 1), ("oversample", 3, 4), ("J", 5, 1), ("J", 10, 1),
+    ("D", 0, 1), ("M", -1, 1), ("M", 1 << 31, 1), ("prec", 2, 1), ("tile", 12, 1),
+])
+def test_phi_descriptor_validation(P, field, value, code):
+    d = P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0)
+    setattr(d, field, value)
+    with pytest.raises(P.PrError) as e:
+        P.pr_phi_plan_sizes(d)
+    assert e.value.code == code
+
+
+def test_tiles_that_do_not_fit_lds_are_refused(P):
+    with pytest.raises(P.PrError) as e:
+        P.pr_phi_plan_sizes(P.pr_phi_desc(256, 2, 4, 2000, 1000, 1, 32))
+    assert e.value.code == P.PR_EUNSUPPORTED
+    with pytest.raises(P.PrError) as e:
+        P.pr_phi_plan_sizes(P.pr_phi_desc(256, 2, 6, 2000, 1000, 0, 32))
+    assert e.value.code == P.PR_EUNSUPPORTED
+    assert P.pr_phi_plan_sizes(P.pr_phi_desc(256, 2, 4, 2000, 1000, 0, 32))[0] > 0
+
+
+def test_phi_sizes_scale_with_the_problem(P):
+    small = P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 8192, 0, 0))
+    big = P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 81920, 0, 0))
+    f64 = P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 8192, 1, 0))
+    assert all(v > 0 and v % 256 == 0 for v in small + big + f64)
+    assert big[0] > small[0] and f64[0] > small[0]
+    # persistent part holds at least uv, w and the permutation (16 B per visibility in FP32)
+    assert big[0] >= 16 * 81920
+
+
+def test_workspace_and_null_checks(P):
+    L = P.lib()
+    d = P.pr_phi_desc(64, 2, 4, 2000, 10, 0, 0)
+    h = C.c_void_p()
+    assert L.pr_phi_plan_create(C.byref(d), 256, None, None, 256, None, C.byref(h)) == P.PR_EWORKSPACE
+    assert L.pr_phi_plan_create(C.byref(d), 256, None, 256 + 8, 512, None, C.byref(h)) == P.PR_EWORKSPACE
+    assert L.pr_phi_plan_create(C.byref(d), None, None, 256, 512, None, C.byref(h)) == P.PR_EINVAL
+    assert L.pr_phi_apply(None, 256, 256, None) == P.PR_EINVAL
+    assert L.pr_phi_adjoint(None, 256, 256, None) == P.PR_EINVAL
+    assert L.pr_phi_norm(None, 10, 256, None, None) == P.PR_EINVAL
+
+
+def test_prox_argument_checks(P):
+    L = P.lib()
+    assert L.pr_prox_l1(256, 256, -1, 0, 0, 0.1, None) == P.PR_EINVAL
+    assert L.pr_prox_l1(256, 256, 10, 0, 7, 0.1, None) == P.PR_EINVAL
+    assert L.pr_prox_l1(256, 256, 10, 0, 0, -0.1, None) == P.PR_EINVAL
+    assert L.pr_prox_l1(None, None, 10, 0, 0, 0.1, None) == P.PR_EINVAL
+    assert L.pr_proj_l2ball(256, 256, 256, 10, 0, 1.0, 256 + 4, None, None) == P.PR_EWORKSPACE
+    assert L.pr_proj_l2ball(256, 256, 256, 10, 0, -1.0, 256, None, None) == P.PR_EINVAL
+    assert P.pr_proj_l2ball_scratch_bytes(1000) >= 8 * 1024
+
+
+def test_psi_and_admm_checks(P):
+    L = P.lib()
+    with pytest.raises(P.PrError):
+        P.pr_psi_plan_sizes(96, 3, 0x1FF, 0)
+    with pytest.raises(P.PrError):
+        P.pr_psi_plan_sizes(64, 7, 0x1FF, 0)
+    with pytest.raises(P.PrError):
+        P.pr_psi_plan_sizes(64, 3, 0x200, 0)
+    pb, sb = P.pr_psi_plan_sizes(64, 3, 0x1FF, 0)
+    assert pb > 0 and sb >= 8 * 64 * 64 * 4
+    prm = P.admm_params(1.0, 0.1)
+    rep = P.pr_admm_report()
+    assert L.pr_admm_solve(None, None, None, C.byref(prm), None, None, C.byref(rep), None) == P.PR_EINVAL
+    assert L.pr_psi_apply(None, 256, 256, None) == P.PR_EINVAL
