@@ -22,14 +22,14 @@ constexpr int kFftThreads = 256;
 template <typename R, bool INV, int PB4>
 __device__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t<R>* __restrict__ tw) {
   using C = cx_t<R>;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nth = blockDim.x;
   int Ns = 1;
   if (logK & 1) {
     const int half = K >> 1, nbf = W * half;
     C a[2 * PB4], b[2 * PB4];
 #pragma unroll
     for (int i = 0; i < 2 * PB4; ++i) {
-      const int bf = tid + i * kFftThreads;
+      const int bf = tid + i * nth;
       if (bf < nbf) {
         const int line = bf / half, j = bf - line * half;
         const C* L = buf + line * LS;
@@ -40,7 +40,7 @@ __device__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2 * PB4; ++i) {
-      const int bf = tid + i * kFftThreads;
+      const int bf = tid + i * nth;
       if (bf < nbf) {
         const int line = bf / half, j = bf - line * half;
         C* L = buf + line * LS;
@@ -57,7 +57,7 @@ __device__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t
     C v[PB4][4];
 #pragma unroll
     for (int i = 0; i < PB4; ++i) {
-      const int bf = tid + i * kFftThreads;
+      const int bf = tid + i * nth;
       if (bf < nbf) {
         const int line = bf / q, j = bf - line * q;
         const C* L = buf + line * LS;
@@ -83,7 +83,7 @@ __device__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PB4; ++i) {
-      const int bf = tid + i * kFftThreads;
+      const int bf = tid + i * nth;
       if (bf < nbf) {
         const int line = bf / q, j = bf - line * q;
         const int k = j & (Ns - 1);
@@ -104,16 +104,21 @@ template <> struct FftCfg<double> { static constexpr int PB4 = 4; };
 
 inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
 
-// Lines per block: the largest power of two whose lines fit 64 KB of LDS at
-// stride K + 1 (the pad spreads column loads over banks); a single line uses
-// stride K. This also keeps W * K within kFftThreads * 4 * PB4.
+// Lines per block: a power of two that fits 64 KB of LDS at stride K + 1
+// (the pad spreads column accesses over banks; a single line uses stride K),
+// small enough to give at least 256 blocks when there are enough lines. The
+// block has W * K / 4 threads (one radix-4 butterfly each), clamped to
+// [64, 256]; this keeps W * K / 4 <= threads * PB4.
 template <typename R>
-inline void lines_per_block(int K, int cap, int* W, int* LS) {
+inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
   const size_t per = static_cast<size_t>(K + 1) * sizeof(cx_t<R>);
   int w = 1;
-  while (static_cast<size_t>(2 * w) * per <= 65536 && 2 * w <= cap) w *= 2;
+  while (static_cast<size_t>(2 * w) * per <= 65536 && 2 * w <= nlines && nlines / (2 * w) >= 256) w *= 2;
   *W = w;
   *LS = w > 1 ? K + 1 : K;
+  int t = w * K / 4;
+  t = t < 64 ? 64 : (t > kFftThreads ? kFftThreads : t);
+  *threads = t;
 }
 
 // Forward row pass: image rows -> S Z -> FFT along u -> A.
@@ -126,9 +131,9 @@ __global__ __launch_bounds__(kFftThreads) void fzs_rows_kernel(const R* __restri
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int row0 = blockIdx.x * W;
   const int lines = min(W, n - row0);
-  for (int i = threadIdx.x; i < lines * LS; i += kFftThreads) buf[i] = cmk<C>(R(0), R(0));
+  for (int i = threadIdx.x; i < lines * LS; i += blockDim.x) buf[i] = cmk<C>(R(0), R(0));
   __syncthreads();
-  for (int i = threadIdx.x; i < lines * n; i += kFftThreads) {
+  for (int i = threadIdx.x; i < lines * n; i += blockDim.x) {
     const int l = i / n, ix = i - l * n;
     const int iy = row0 + l;
     const int gx = (ix - n / 2) & (K - 1);
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(kFftThreads) void fzs_rows_kernel(const R* __restri
   }
   __syncthreads();
   fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
-  for (int i = threadIdx.x; i < lines * K; i += kFftThreads) {
+  for (int i = threadIdx.x; i < lines * K; i += blockDim.x) {
     const int l = i / K, k = i - l * K;
     A[static_cast<int64_t>(row0 + l) * K + k] = buf[l * LS + k];
   }
@@ -158,16 +163,16 @@ __global__ __launch_bounds__(kFftThreads) void fzs_cols_kernel(const cx_t<R>* __
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
-  for (int i = threadIdx.x; i < W * LS; i += kFftThreads) buf[i] = cmk<C>(R(0), R(0));
+  for (int i = threadIdx.x; i < W * LS; i += blockDim.x) buf[i] = cmk<C>(R(0), R(0));
   __syncthreads();
-  for (int i = threadIdx.x; i < n * W; i += kFftThreads) {
+  for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
     const int iy = i / W, l = i - iy * W;
     const int gy = (iy - n / 2) & (K - 1);
     buf[l * LS + gy] = A[static_cast<int64_t>(iy) * K + kx0 + l];
   }
   __syncthreads();
   fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
-  for (int i = threadIdx.x; i < K * W; i += kFftThreads) {
+  for (int i = threadIdx.x; i < K * W; i += blockDim.x) {
     const int ky = i / W, l = i - ky * W;
     grid[static_cast<int64_t>(ky) * K + kx0 + l] = buf[l * LS + ky];
   }
@@ -183,13 +188,13 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_cols_kernel(const cx_t<R>
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
-  for (int i = threadIdx.x; i < K * W; i += kFftThreads) {
+  for (int i = threadIdx.x; i < K * W; i += blockDim.x) {
     const int ky = i / W, l = i - ky * W;
     buf[l * LS + ky] = grid[static_cast<int64_t>(ky) * K + kx0 + l];
   }
   __syncthreads();
   fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
-  for (int i = threadIdx.x; i < n * W; i += kFftThreads) {
+  for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
     const int iy = i / W, l = i - iy * W;
     const int gy = (iy - n / 2) & (K - 1);
     A[static_cast<int64_t>(iy) * K + kx0 + l] = buf[l * LS + gy];
@@ -210,13 +215,13 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int row0 = blockIdx.x * W;
   const int lines = min(W, n - row0);
-  for (int i = threadIdx.x; i < lines * K; i += kFftThreads) {
+  for (int i = threadIdx.x; i < lines * K; i += blockDim.x) {
     const int l = i / K, k = i - l * K;
     buf[l * LS + k] = A[static_cast<int64_t>(row0 + l) * K + k];
   }
   __syncthreads();
   fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
-  for (int i = threadIdx.x; i < lines * n; i += kFftThreads) {
+  for (int i = threadIdx.x; i < lines * n; i += blockDim.x) {
     const int l = i / n, ix = i - l * n;
     const int iy = row0 + l;
     const int gx = (ix - n / 2) & (K - 1);
@@ -236,15 +241,15 @@ template <typename R>
 int fzs_impl(pr_phi_plan_t* p, const R* x, hipStream_t s) {
   using C = cx_t<R>;
   const int n = p->n, K = p->K, logK = ilog2(K);
-  int Wr, LSr, Wc, LSc;
-  lines_per_block<R>(K, n, &Wr, &LSr);
-  lines_per_block<R>(K, K, &Wc, &LSc);
+  int Wr, LSr, Wc, LSc, Tr, Tc;
+  lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
+  lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
   const size_t lds_r = static_cast<size_t>(Wr) * LSr * sizeof(C);
   const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
-  fzs_rows_kernel<R><<<(n + Wr - 1) / Wr, kFftThreads, lds_r, s>>>(
+  fzs_rows_kernel<R><<<(n + Wr - 1) / Wr, Tr, lds_r, s>>>(
       x, static_cast<const R*>(p->corr), static_cast<const C*>(p->tw), static_cast<C*>(p->fft_tmp), n, K, logK, Wr, LSr);
   PR_TRY_LAUNCH();
-  fzs_cols_kernel<R><<<K / Wc, kFftThreads, lds_c, s>>>(static_cast<const C*>(p->fft_tmp),
+  fzs_cols_kernel<R><<<K / Wc, Tc, lds_c, s>>>(static_cast<const C*>(p->fft_tmp),
                                                        static_cast<const C*>(p->tw), static_cast<C*>(p->grid), n, K,
                                                        logK, Wc, LSc);
   PR_TRY_LAUNCH();
@@ -255,16 +260,16 @@ template <typename R, int MODE>
 int fzs_adjoint_impl(pr_phi_plan_t* p, R* x_out, const R* x_in, R* zbar, double rho, hipStream_t s) {
   using C = cx_t<R>;
   const int n = p->n, K = p->K, logK = ilog2(K);
-  int Wr, LSr, Wc, LSc;
-  lines_per_block<R>(K, n, &Wr, &LSr);
-  lines_per_block<R>(K, K, &Wc, &LSc);
+  int Wr, LSr, Wc, LSc, Tr, Tc;
+  lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
+  lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
   const size_t lds_r = static_cast<size_t>(Wr) * LSr * sizeof(C);
   const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
-  fzs_adj_cols_kernel<R><<<K / Wc, kFftThreads, lds_c, s>>>(static_cast<const C*>(p->grid),
+  fzs_adj_cols_kernel<R><<<K / Wc, Tc, lds_c, s>>>(static_cast<const C*>(p->grid),
                                                            static_cast<const C*>(p->tw), static_cast<C*>(p->fft_tmp),
                                                            n, K, logK, Wc, LSc);
   PR_TRY_LAUNCH();
-  fzs_adj_rows_kernel<R, MODE><<<(n + Wr - 1) / Wr, kFftThreads, lds_r, s>>>(
+  fzs_adj_rows_kernel<R, MODE><<<(n + Wr - 1) / Wr, Tr, lds_r, s>>>(
       static_cast<const C*>(p->fft_tmp), static_cast<const R*>(p->corr), static_cast<const C*>(p->tw), x_out, x_in,
       zbar, static_cast<R>(rho), n, K, logK, Wr, LSr);
   PR_TRY_LAUNCH();

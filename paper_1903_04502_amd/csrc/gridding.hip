@@ -30,7 +30,7 @@ constexpr int kSlotNonfinite = 3;
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxBlocks = 2048;   // <= kPartialsMax
+constexpr int kMaxBlocks = 1024;   // persistent blocks (4 per CU); <= kPartialsMax
 constexpr size_t kLdsSoft = 81920;    // two blocks per CU
 constexpr size_t kLdsHard = 163840;   // per-workgroup limit on gfx950
 
@@ -47,7 +47,7 @@ struct GwArgs {
   const R* w;
   const int4* items;
   int64_t nItems;
-  int K, T, P, nT, D, tlen;
+  int K, T, P, nT, lognT, D, tlen;
   double kappa;
   R scale;
   cx_t<R>* y_out;          // MODE 0
@@ -57,9 +57,12 @@ struct GwArgs {
   double* partials;
 };
 
+constexpr int kDegridPer = 4;   // visibilities per thread per chunk
+
 template <typename R, int J, int MODE, bool TAB_LDS>
 __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   using C = cx_t<R>;
+  constexpr int CH = kThreads * kDegridPer;
   extern __shared__ char smem_raw[];
   const int tid = threadIdx.x;
   C* patch = reinterpret_cast<C*>(smem_raw);
@@ -71,61 +74,86 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   }
   const int P = a.P, T = a.T, K = a.K;
   double sum_t = 0.0, sum_r = 0.0;
+  // inputs of this thread's visibilities for the current and the next chunk
+  R cu_[kDegridPer], cv_[kDegridPer], cw_[kDegridPer], nu_[kDegridPer], nv_[kDegridPer], nw_[kDegridPer];
+  auto load = [&](int c0, int cend, R* u, R* v, R* w) {
+#pragma unroll
+    for (int j = 0; j < kDegridPer; ++j) {
+      const int64_t k = c0 + tid + j * kThreads;
+      if (k < cend) {
+        u[j] = a.uv[2 * k];
+        v[j] = a.uv[2 * k + 1];
+        w[j] = a.w[k];
+      }
+    }
+  };
   for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
     const int4 it = a.items[item];
-    const int tv = it.x / a.nT, tu = it.x - tv * a.nT;
+    const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
+    load(it.y, it.z, cu_, cv_, cw_);
     __syncthreads();
+    const float invP = 1.0f / P;
     for (int i = tid; i < P * P; i += kThreads) {
-      const int pv = i / P, pu = i - pv * P;
+      const int pv = small_div(i, P, invP), pu = i - pv * P;
       const int gv = (tv * T + pv) & (K - 1), gu = (tu * T + pu) & (K - 1);
       patch[i] = a.grid[static_cast<int64_t>(gv) * K + gu];
     }
     __syncthreads();
-    for (int k = it.y + tid; k < it.z; k += kThreads) {
-      const R u = a.uv[2 * static_cast<int64_t>(k)];
-      const R v = a.uv[2 * static_cast<int64_t>(k) + 1];
-      const AxisTaps xu = axis_taps(static_cast<double>(u), a.kappa, J, a.D);
-      const AxisTaps xv = axis_taps(static_cast<double>(v), a.kappa, J, a.D);
-      const int lu = mod_pos(xu.j0, K) - tu * T;
-      const int lv = mod_pos(xv.j0, K) - tv * T;
-      if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
-        // cannot happen for a plan's own sorted baselines; flag instead of reading out of the patch
-        const R nan = R(NAN);
-        if (MODE == 0) a.y_out[k] = cmk<C>(nan, nan);
-        else a.t_out[k] = cmk<C>(nan, nan);
-        continue;
-      }
-      R wu[J], wv[J];
+    for (int c0 = it.y; c0 < it.z; c0 += CH) {
+      if (c0 + CH < it.z) load(c0 + CH, it.z, nu_, nv_, nw_);
 #pragma unroll
-      for (int q = 0; q < J; ++q) {
-        wu[q] = tab[tap_index(xu, q, J, a.D)];
-        wv[q] = tab[tap_index(xv, q, J, a.D)];
-      }
-      R accr = 0, acci = 0;
-#pragma unroll
-      for (int b = 0; b < J; ++b) {
-        const C* row = patch + (lv + b) * P + lu;
-        R rr = 0, ri = 0;
+      for (int j = 0; j < kDegridPer; ++j) {
+        const int k = c0 + tid + j * kThreads;
+        if (k >= it.z) continue;
+        const AxisTaps xu = axis_taps(static_cast<double>(cu_[j]), a.kappa, J, a.D);
+        const AxisTaps xv = axis_taps(static_cast<double>(cv_[j]), a.kappa, J, a.D);
+        const int lu = mod_pow2(xu.j0, K) - tu * T;
+        const int lv = mod_pow2(xv.j0, K) - tv * T;
+        if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
+          // cannot happen for a plan's own sorted baselines; flag instead of reading out of the patch
+          const R nan = R(NAN);
+          if (MODE == 0) a.y_out[k] = cmk<C>(nan, nan);
+          else a.t_out[k] = cmk<C>(nan, nan);
+          continue;
+        }
+        R wu[J], wv[J];
 #pragma unroll
         for (int q = 0; q < J; ++q) {
-          const C g = row[q];
-          rr += wu[q] * g.x;
-          ri += wu[q] * g.y;
+          wu[q] = tab[tap_index(xu, q, J, a.D)];
+          wv[q] = tab[tap_index(xv, q, J, a.D)];
         }
-        accr += wv[b] * rr;
-        acci += wv[b] * ri;
+        R accr = 0, acci = 0;
+#pragma unroll
+        for (int b = 0; b < J; ++b) {
+          const C* row = patch + (lv + b) * P + lu;
+          R rr = 0, ri = 0;
+#pragma unroll
+          for (int q = 0; q < J; ++q) {
+            const C g = row[q];
+            rr += wu[q] * g.x;
+            ri += wu[q] * g.y;
+          }
+          accr += wv[b] * rr;
+          acci += wv[b] * ri;
+        }
+        const R ws = cw_[j] * a.scale;
+        const C yk = cmk<C>(accr * ws, acci * ws);
+        if (MODE == 0) {
+          a.y_out[k] = yk;
+        } else {
+          const C yo = a.y_obs[k], sk = a.s_in[k];
+          const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
+          a.t_out[k] = t;
+          const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
+          sum_t += tr * tr + ti * ti;
+          sum_r += dr * dr + di * di;
+        }
       }
-      const R ws = a.w[k] * a.scale;
-      const C yk = cmk<C>(accr * ws, acci * ws);
-      if (MODE == 0) {
-        a.y_out[k] = yk;
-      } else {
-        const C yo = a.y_obs[k], sk = a.s_in[k];
-        const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
-        a.t_out[k] = t;
-        const double tr = t.x, ti = t.y, rr = static_cast<double>(yk.x) - yo.x, ri = static_cast<double>(yk.y) - yo.y;
-        sum_t += tr * tr + ti * ti;
-        sum_r += rr * rr + ri * ri;
+#pragma unroll
+      for (int j = 0; j < kDegridPer; ++j) {
+        cu_[j] = nu_[j];
+        cv_[j] = nv_[j];
+        cw_[j] = nw_[j];
       }
     }
   }
@@ -151,7 +179,7 @@ struct GwAdjArgs {
   const R* w;
   const int4* items;
   int64_t nItems;
-  int K, T, P, nT, D, tlen, B;
+  int K, T, P, nT, lognT, D, tlen, B;
   double kappa;
   R scale;
   const cx_t<R>* y_in;       // MODE 0
@@ -162,43 +190,74 @@ struct GwAdjArgs {
   cx_t<R>* patches;
 };
 
-template <typename R, int J>
+// LDS layout of the gridding kernel. Staged visibilities are stored
+// segment-transposed (position p of a batch with L positions per segment lives
+// at (p mod L) * NS + p / L), per-tap weights as planes of B values, moments
+// and side slots entry-major: consecutive lanes touch consecutive words. The
+// side slots reuse the staged area when it is large enough: they are written
+// only after every thread has finished reading the staged batch.
+template <typename R, int J, int NS>
 struct GridLds {
-  static constexpr int SPW = 64 / J;             // streams per wave
-  static constexpr int S = (kThreads / 64) * SPW;
-  size_t tab, cell, ywu, wv, mom, bits, side, side_cell, misc, total;
+  size_t tab, cell, wu, wv, yw, side, side_cell, mom, bits, total;
   __host__ __device__ GridLds(int T, int B, int tlen, bool tab_lds) {
     using C = cx_t<R>;
     size_t o = 0;
-    tab = o;       o += tab_lds ? align16(static_cast<size_t>(tlen) * sizeof(R)) : 0;
-    cell = o;      o += align16(static_cast<size_t>(B) * sizeof(int));
-    ywu = o;       o += align16(static_cast<size_t>(B) * J * sizeof(C));
-    wv = o;        o += align16(static_cast<size_t>(B) * J * sizeof(R));
-    mom = o;       o += align16(static_cast<size_t>(T) * T * J * J * sizeof(C));
-    bits = o;      o += align16(static_cast<size_t>((T * T + 31) / 32) * sizeof(uint32_t));
-    side = o;      o += align16(static_cast<size_t>(S) * J * J * sizeof(C));
-    side_cell = o; o += align16(static_cast<size_t>(S) * sizeof(int));
-    misc = o;      o += 16;
+    tab = o;   o += tab_lds ? align16(static_cast<size_t>(tlen) * sizeof(R)) : 0;
+    bits = o;  o += align16(static_cast<size_t>((T * T + 31) / 32) * sizeof(uint32_t));
+    cell = o;  o += align16(static_cast<size_t>(B) * sizeof(int));
+    const size_t st0 = o;
+    wu = o;    o += align16(static_cast<size_t>(B) * J * sizeof(R));
+    wv = o;    o += align16(static_cast<size_t>(B) * J * sizeof(R));
+    yw = o;    o += align16(static_cast<size_t>(B) * sizeof(C));
+    const size_t staged = o - st0;
+    const size_t sb = align16(static_cast<size_t>(NS) * J * J * sizeof(C));
+    const size_t cb = align16(static_cast<size_t>(NS) * sizeof(int));
+    if (sb + cb <= staged) {
+      side = st0;
+      side_cell = st0 + sb;
+    } else {
+      side = o;      o += sb;
+      side_cell = o; o += cb;
+    }
+    mom = o;   o += align16(static_cast<size_t>(T) * T * J * J * sizeof(C));
     total = o;
   }
 };
 
-template <typename R, int J, int MODE, bool TAB_LDS>
+constexpr int kGridPer = 4;   // staged visibilities per thread: B <= kThreads * kGridPer
+
+// Gridding of one work item (a run of one tile's visibilities, sorted by base
+// cell). Per batch of nb <= B staged visibilities the block is split into NS
+// segments of L = ceil(nb / NS) contiguous positions; the threads of a segment
+// each hold JA columns (tap a) of the J^2 moments of the current base cell in
+// registers. A run that begins inside a segment is owned by it; the owner of a
+// run that continues into the following segments adds their parked partial
+// sums in segment order before adding the total to the cell's moments. Every
+// moment is therefore a sum in a fixed order: deterministic, no atomics. The
+// next batch's inputs are loaded into registers while the current one is
+// accumulated.
+template <typename R, int J, int JA, int MODE, bool TAB_LDS>
 __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
-  using L = GridLds<R, J>;
-  constexpr int SPW = L::SPW, S = L::S, JJ = J * J;
+  constexpr int JJ = J * J;
+  constexpr int TPC = (J + JA - 1) / JA;
+  constexpr int NS = kThreads / (TPC == 3 ? 4 : TPC);
+  constexpr int TPS = kThreads / NS;            // threads per segment (TPC rounded to a divisor)
+  constexpr int E = JA * J;                     // moments held per thread
   extern __shared__ char smem_raw[];
-  const L lay(a.T, a.B, a.tlen, TAB_LDS);
+  const GridLds<R, J, NS> lay(a.T, a.B, a.tlen, TAB_LDS);
   int* st_cell = reinterpret_cast<int*>(smem_raw + lay.cell);
-  C* st_ywu = reinterpret_cast<C*>(smem_raw + lay.ywu);
+  R* st_wu = reinterpret_cast<R*>(smem_raw + lay.wu);
   R* st_wv = reinterpret_cast<R*>(smem_raw + lay.wv);
-  C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
-  uint32_t* bits = reinterpret_cast<uint32_t*>(smem_raw + lay.bits);
+  C* st_yw = reinterpret_cast<C*>(smem_raw + lay.yw);
   C* side = reinterpret_cast<C*>(smem_raw + lay.side);
   int* side_cell = reinterpret_cast<int*>(smem_raw + lay.side_cell);
-  int* prevlast = reinterpret_cast<int*>(smem_raw + lay.misc);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem_raw + lay.bits);
+  const int tid = threadIdx.x;
+  const int sg = tid / TPS, pa = tid - sg * TPS;
+  const int q0 = pa * JA;                       // first column of this thread
+  const bool cols_on = q0 < J;
   const R* tab = a.table;
   if (TAB_LDS) {
     R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
@@ -206,119 +265,203 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
     tab = t;
   }
   const int T = a.T, P = a.P, K = a.K, B = a.B;
-  const int sl = lane / J, aa = lane - sl * J;
-  const bool lane_on = sl < SPW;
-  const int sid = wave * SPW + sl;
+  const int TT = T * T;
   R kappa_ball = 1;
   if (MODE == 1) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
-  const int nbits = (T * T + 31) / 32;
+
+  const int nbits = (TT + 31) / 32;
+  // Moment update of a run's total. An item of one batch has exactly one owner
+  // per base cell, so the owner stores and marks the cell; items of several
+  // batches accumulate into zeroed moments.
+  bool single = true;
+  auto flush = [&](int cell, const R* xr, const R* xi) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (q0 * J + e < JJ) {
+        C& m = mom[(q0 * J + e) * TT + cell];
+        m = single ? cmk<C>(xr[e], xi[e]) : cmk<C>(m.x + xr[e], m.y + xi[e]);
+      }
+    }
+    if (single && pa == 0) atomicOr(&bits[cell >> 5], 1u << (cell & 31));
+  };
+
+  // raw inputs of the visibilities this thread stages (prefetched a batch ahead)
+  R ru[kGridPer], rv[kGridPer], rw[kGridPer];
+  C ry[kGridPer], rs[kGridPer];
+  auto load_raw = [&](int b0, int n0) {
+#pragma unroll
+    for (int j = 0; j < kGridPer; ++j) {
+      const int i = tid + j * kThreads;
+      if (i < n0) {
+        const int64_t k = b0 + i;
+        ru[j] = a.uv[2 * k];
+        rv[j] = a.uv[2 * k + 1];
+        rw[j] = a.w[k];
+        if (MODE == 0) {
+          ry[j] = a.y_in[k];
+        } else {
+          ry[j] = a.t_in[k];
+          rs[j] = a.s_io[k];
+        }
+      }
+    }
+  };
 
   for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
     const int4 it = a.items[item];
-    const int tv = it.x / a.nT, tu = it.x - tv * a.nT;
+    const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
     const int begin = it.y, end = it.z;
+    load_raw(begin, min(B, end - begin));
+    single = end - begin <= B;
     __syncthreads();
-    for (int i = tid; i < nbits; i += kThreads) bits[i] = 0u;
+    if (single) {
+      for (int i = tid; i < nbits; i += kThreads) bits[i] = 0u;
+    } else {
+      for (int i = tid; i < TT * JJ; i += kThreads) mom[i] = cmk<C>(R(0), R(0));
+      for (int i = tid; i < nbits; i += kThreads) bits[i] = ~0u;
+    }
     for (int bs = begin; bs < end; bs += B) {
       const int nb = min(B, end - bs);
-      // stage: taps, weights and the weighted value of each visibility
-      for (int i = tid; i < nb; i += kThreads) {
+      // positions per segment: the smallest power of two with NS * L >= nb
+      int lgL = 0;
+      while ((NS << lgL) < nb) ++lgL;
+      const int L = 1 << lgL;
+      __syncthreads();
+      // stage: first tap cell, tap weights and the weighted value of each visibility
+#pragma unroll
+      for (int j = 0; j < kGridPer; ++j) {
+        const int i = tid + j * kThreads;
+        if (i >= nb) continue;
         const int64_t k = bs + i;
-        const R u = a.uv[2 * k], v = a.uv[2 * k + 1];
-        const AxisTaps xu = axis_taps(static_cast<double>(u), a.kappa, J, a.D);
-        const AxisTaps xv = axis_taps(static_cast<double>(v), a.kappa, J, a.D);
-        int lu = mod_pos(xu.j0, K) - tu * T;
-        int lv = mod_pos(xv.j0, K) - tv * T;
+        const AxisTaps xu = axis_taps(static_cast<double>(ru[j]), a.kappa, J, a.D);
+        const AxisTaps xv = axis_taps(static_cast<double>(rv[j]), a.kappa, J, a.D);
+        int lu = mod_pow2(xu.j0, K) - tu * T;
+        int lv = mod_pow2(xv.j0, K) - tv * T;
         const bool inside = static_cast<unsigned>(lu) < static_cast<unsigned>(T) &&
                             static_cast<unsigned>(lv) < static_cast<unsigned>(T);
         C val;
         if (MODE == 0) {
-          val = a.y_in[k];
+          val = ry[j];
         } else {
           // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
           // r = y + kappa t, s' = s + varrho (v - r), q = v - r + s'
-          const C t = a.t_in[k], s = a.s_io[k];
+          const C t = ry[j], sk = rs[j];
           const R omk = R(1) - kappa_ball;
-          const C vr = cmk<C>(omk * t.x - s.x, omk * t.y - s.y);   // v - r
-          const C sn = cmk<C>(s.x + a.varrho * vr.x, s.y + a.varrho * vr.y);
+          const C vr = cmk<C>(omk * t.x - sk.x, omk * t.y - sk.y);   // v - r
+          const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
           a.s_io[k] = sn;
           val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
         }
-        const R ws = a.w[k] * a.scale;
+        const R ws = rw[j] * a.scale;
         val = cmk<C>(val.x * ws, val.y * ws);
         if (!inside) {
           // cannot happen for a plan's own sorted baselines; keep LDS indices in range, poison the value
           lu = lv = 0;
           val = cmk<C>(R(NAN), R(NAN));
         }
-        st_cell[i] = lv * T + lu;
+        const int si = (i & (L - 1)) * NS + (i >> lgL);
+        st_cell[si] = lv * T + lu;
+        st_yw[si] = val;
 #pragma unroll
         for (int q = 0; q < J; ++q) {
-          const R gu = tab[tap_index(xu, q, J, a.D)];
-          st_ywu[i * J + q] = cmk<C>(val.x * gu, val.y * gu);
-          st_wv[i * J + q] = tab[tap_index(xv, q, J, a.D)];
+          st_wu[q * B + si] = tab[tap_index(xu, q, J, a.D)];
+          st_wv[q * B + si] = tab[tap_index(xv, q, J, a.D)];
         }
       }
       __syncthreads();
-      // streams: lane aa of stream sid accumulates column aa of the moments
-      if (lane_on) {
-        const int p0 = static_cast<int>((static_cast<int64_t>(sid) * nb) / S);
-        const int p1 = static_cast<int>((static_cast<int64_t>(sid + 1) * nb) / S);
-        if (aa == 0) side_cell[sid] = -1;
-        if (p0 < p1) {
-          int cur = st_cell[p0];
-          bool began = p0 > 0 ? st_cell[p0 - 1] != cur : (bs == begin || *prevlast != cur);
-          R ar[J], ai[J];
+      if (bs + B < end) load_raw(bs + B, min(B, end - bs - B));
+      // accumulate the segment: positions [p0, p1), position p at (p - p0) * NS + sg
+      const int p0 = sg * L;
+      const int p1 = min(p0 + L, nb);
+      R ar[E], ai[E], sr[E], si[E];
+      bool has_side = false, defer = false;
+      int cur = -1, side_c = -1;
+      if (p0 < p1) {
+        cur = st_cell[sg];
+        bool owner = p0 == 0 || st_cell[((p0 - 1) & (L - 1)) * NS + ((p0 - 1) >> lgL)] != cur;
 #pragma unroll
-          for (int b = 0; b < J; ++b) ar[b] = ai[b] = 0;
-          for (int p = p0; p <= p1; ++p) {
-            const int c = p < p1 ? st_cell[p] : -1;
-            if (c != cur) {
-              if (began) {
+        for (int e = 0; e < E; ++e) ar[e] = ai[e] = R(0);
+        for (int p = p0; p < p1; ++p) {
+          const int ix = (p - p0) * NS + sg;
+          const int c = st_cell[ix];
+          if (c != cur) {
+            if (owner) {
+              if (cols_on) flush(cur, ar, ai);
+            } else {
 #pragma unroll
-                for (int b = 0; b < J; ++b) mom[(cur * J + aa) * J + b] = cmk<C>(ar[b], ai[b]);
-                if (aa == 0) atomicOr(&bits[cur >> 5], 1u << (cur & 31));
-              } else {
+              for (int e = 0; e < E; ++e) { sr[e] = ar[e]; si[e] = ai[e]; }
+              has_side = true;
+              side_c = cur;
+            }
+            owner = true;
+            cur = c;
 #pragma unroll
-                for (int b = 0; b < J; ++b) side[sid * JJ + aa * J + b] = cmk<C>(ar[b], ai[b]);
-                if (aa == 0) side_cell[sid] = cur;
+            for (int e = 0; e < E; ++e) ar[e] = ai[e] = R(0);
+          }
+          if (cols_on) {
+            const C y = st_yw[ix];
+            R wv[J];
+#pragma unroll
+            for (int b = 0; b < J; ++b) wv[b] = st_wv[b * B + ix];
+#pragma unroll
+            for (int qq = 0; qq < JA; ++qq) {
+              if (q0 + qq < J) {
+                const R g = st_wu[(q0 + qq) * B + ix];
+                const R yr = y.x * g, yi = y.y * g;
+#pragma unroll
+                for (int b = 0; b < J; ++b) {
+                  ar[qq * J + b] += wv[b] * yr;
+                  ai[qq * J + b] += wv[b] * yi;
+                }
               }
-              if (p == p1) break;
-              began = true;
-              cur = c;
-#pragma unroll
-              for (int b = 0; b < J; ++b) ar[b] = ai[b] = 0;
-            }
-            const C x = st_ywu[p * J + aa];
-#pragma unroll
-            for (int b = 0; b < J; ++b) {
-              const R g = st_wv[p * J + b];
-              ar[b] += g * x.x;
-              ai[b] += g * x.y;
             }
           }
         }
+        const bool cont = p1 < nb && st_cell[(p1 & (L - 1)) * NS + (p1 >> lgL)] == cur;
+        if (!owner) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) { sr[e] = ar[e]; si[e] = ai[e]; }
+          has_side = true;
+          side_c = cur;
+        } else if (cont) {
+          defer = true;
+        } else if (cols_on) {
+          flush(cur, ar, ai);
+        }
+      }
+      __syncthreads();   // the staged batch is no longer read: park the side sums
+      if (pa == 0) side_cell[sg] = p0 < p1 ? (has_side ? side_c : -1) : -2;
+      if (has_side && cols_on) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (q0 * J + e < JJ) side[(q0 * J + e) * NS + sg] = cmk<C>(sr[e], si[e]);
       }
       __syncthreads();
-      // continued runs, added in stream order
-      for (int e = tid; e < JJ; e += kThreads) {
-        for (int s2 = 0; s2 < S; ++s2) {
+      if (defer && cols_on) {
+        // owner of a run that continues: add the following segments' parts in order
+        for (int s2 = sg + 1; s2 < NS; ++s2) {
           const int c = side_cell[s2];
-          if (c >= 0) {
-            C m = mom[c * JJ + e];
-            const C d = side[s2 * JJ + e];
-            mom[c * JJ + e] = cmk<C>(m.x + d.x, m.y + d.y);
+          if (c == -2) continue;        // empty segment
+          if (c != cur) break;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if (q0 * J + e < JJ) {
+              const C d = side[(q0 * J + e) * NS + s2];
+              ar[e] += d.x;
+              ai[e] += d.y;
+            }
           }
         }
+        flush(cur, ar, ai);
       }
-      if (tid == 0) *prevlast = st_cell[nb - 1];
-      __syncthreads();
     }
-    // patch: cell q = c + (b, a) collects m[c][a][b]
+    __syncthreads();
+    // patch: cell q = c + (b, a) collects moment [a][b] of base cell c
     C* out = a.patches + item * static_cast<int64_t>(P) * P;
+    const float invP = 1.0f / P;
     for (int pc = tid; pc < P * P; pc += kThreads) {
-      const int pv = pc / P, pu = pc - pv * P;
-      R sr = 0, si = 0;
+      const int pv = small_div(pc, P, invP), pu = pc - pv * P;
+      R sr2 = 0, si2 = 0;
 #pragma unroll
       for (int b = 0; b < J; ++b) {
         const int cv = pv - b;
@@ -328,45 +471,56 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
           const int cu = pu - q;
           if (cu < 0 || cu >= T) continue;
           const int c = cv * T + cu;
-          if (bits[c >> 5] >> (c & 31) & 1u) {
-            const C m = mom[(c * J + q) * J + b];
-            sr += m.x;
-            si += m.y;
+          if ((bits[c >> 5] >> (c & 31)) & 1u) {
+            const C m = mom[(q * J + b) * TT + c];
+            sr2 += m.x;
+            si2 += m.y;
           }
         }
       }
-      out[pc] = cmk<C>(sr, si);
+      out[pc] = cmk<C>(sr2, si2);
     }
   }
 }
 
+// Columns of the moments held per gridding thread (JA): FP32 keeps at most 8
+// complex accumulators per thread for J <= 4 (two threads per segment), FP64
+// at most 8.
+template <typename R, int J> struct GridSplit;
+template <int J> struct GridSplit<float, J> { static constexpr int JA = J <= 2 ? J : (J == 6 ? 3 : 2); };
+template <int J> struct GridSplit<double, J> { static constexpr int JA = J <= 2 ? J : 2; };
+
 // Grid cell = sum of the patches of the (up to four) tiles whose patch covers
-// it, neighbour tiles first, items of a tile in order.
+// it, neighbour tiles first, items of a tile in order. One block per output
+// tile, so the item ranges it walks are the same for all its threads.
 template <typename R>
 __global__ void merge_patches_kernel(const cx_t<R>* __restrict__ patches, const int32_t* __restrict__ item_off,
                                      cx_t<R>* __restrict__ grid, int K, int T, int P, int nT, int J) {
   using C = cx_t<R>;
-  const int64_t K2 = static_cast<int64_t>(K) * K;
-  for (int64_t cell = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; cell < K2;
-       cell += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int cv = static_cast<int>(cell / K), cu = static_cast<int>(cell - static_cast<int64_t>(cv) * K);
-    const int tv = cv / T, tu = cu / T, lv = cv - tv * T, lu = cu - tu * T;
+  const int t = blockIdx.x;
+  const int tv = t / nT, tu = t - tv * nT;
+  const int64_t P2 = static_cast<int64_t>(P) * P;
+  for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
+    const int lv = c / T, lu = c & (T - 1);
     R sr = 0, si = 0;
     for (int dv = 1; dv >= 0; --dv) {
       if (dv == 1 && lv >= J - 1) continue;
-      const int tvv = (tv - dv + nT) % nT, pv = lv + dv * T;
+      const int tvv = tv - dv < 0 ? tv - dv + nT : tv - dv;
+      const int pv = lv + dv * T;
       for (int du = 1; du >= 0; --du) {
         if (du == 1 && lu >= J - 1) continue;
-        const int tuu = (tu - du + nT) % nT, pu = lu + du * T;
-        const int t = tvv * nT + tuu;
-        for (int itm = item_off[t]; itm < item_off[t + 1]; ++itm) {
-          const C v = patches[static_cast<int64_t>(itm) * P * P + pv * P + pu];
+        const int tuu = tu - du < 0 ? tu - du + nT : tu - du;
+        const int pu = lu + du * T;
+        const int src = tvv * nT + tuu;
+        const int i0 = item_off[src], i1 = item_off[src + 1];
+        for (int itm = i0; itm < i1; ++itm) {
+          const C v = patches[itm * P2 + pv * P + pu];
           sr += v.x;
           si += v.y;
         }
       }
     }
-    grid[cell] = cmk<C>(sr, si);
+    grid[static_cast<int64_t>(tv * T + lv) * K + tu * T + lu] = cmk<C>(sr, si);
   }
 }
 
@@ -426,11 +580,14 @@ int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
 // else use up to the whole 160 KB.
 template <typename R, int J>
 bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
+  constexpr int JA = GridSplit<R, J>::JA;
+  constexpr int TPC = (J + JA - 1) / JA;
+  constexpr int NS = kThreads / (TPC == 3 ? 4 : TPC);
   const size_t limits[2] = {kLdsSoft, kLdsHard};
   for (size_t lim : limits) {
     for (int tl = 1; tl >= 0; --tl) {
-      for (int b = 256; b >= 32; b /= 2) {
-        GridLds<R, J> g(T, b, tlen, tl != 0);
+      for (int b = kThreads * kGridPer; b >= 64; b /= 2) {
+        GridLds<R, J, NS> g(T, b, tlen, tl != 0);
         if (g.total <= lim) {
           *B = b;
           *tab_lds = tl != 0;
@@ -446,6 +603,7 @@ bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
 template <typename R, int J, int MODE>
 int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s) {
   using C = cx_t<R>;
+  constexpr int JA = GridSplit<R, J>::JA;
   const int G = degrid_blocks(p);
   int B;
   bool tab_lds;
@@ -456,15 +614,14 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s) {
   }
   a.B = B;
   if (tab_lds) {
-    PR_TRY(allow_lds(grid_kernel<R, J, MODE, true>, bytes));
-    grid_kernel<R, J, MODE, true><<<G, kThreads, bytes, s>>>(a);
+    PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true>, bytes));
+    grid_kernel<R, J, JA, MODE, true><<<G, kThreads, bytes, s>>>(a);
   } else {
-    PR_TRY(allow_lds(grid_kernel<R, J, MODE, false>, bytes));
-    grid_kernel<R, J, MODE, false><<<G, kThreads, bytes, s>>>(a);
+    PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false>, bytes));
+    grid_kernel<R, J, JA, MODE, false><<<G, kThreads, bytes, s>>>(a);
   }
   PR_TRY_LAUNCH();
-  const int64_t K2 = static_cast<int64_t>(p->K) * p->K;
-  merge_patches_kernel<R><<<grid_for(K2, kThreads, 8192), kThreads, 0, s>>>(
+  merge_patches_kernel<R><<<p->nTiles, p->T * p->T < kThreads ? p->T * p->T : kThreads, 0, s>>>(
       static_cast<const C*>(p->patches), p->item_off, static_cast<C*>(p->grid), p->K, p->T, p->P, p->nT, p->J);
   PR_TRY_LAUNCH();
   return PR_OK;
@@ -480,6 +637,8 @@ GwArgs<R> gw_args(pr_phi_plan_t* p, double scale) {
   a.items = p->items;
   a.nItems = p->nItems;
   a.K = p->K; a.T = p->T; a.P = p->P; a.nT = p->nT; a.D = p->D;
+  a.lognT = 0;
+  while ((1 << a.lognT) < p->nT) ++a.lognT;
   a.tlen = p->J * p->D / 2 + 1;
   a.kappa = p->kappa;
   a.scale = static_cast<R>(scale);
@@ -495,6 +654,8 @@ GwAdjArgs<R> gwadj_args(pr_phi_plan_t* p, double scale) {
   a.items = p->items;
   a.nItems = p->nItems;
   a.K = p->K; a.T = p->T; a.P = p->P; a.nT = p->nT; a.D = p->D;
+  a.lognT = 0;
+  while ((1 << a.lognT) < p->nT) ++a.lognT;
   a.tlen = p->J * p->D / 2 + 1;
   a.kappa = p->kappa;
   a.scale = static_cast<R>(scale);

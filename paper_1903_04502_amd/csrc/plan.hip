@@ -72,7 +72,7 @@ __global__ void cell_keys_kernel(const R* uv, int64_t M, double kappa, int K, in
   if (k >= M) return;
   const AxisTaps tu = axis_taps(static_cast<double>(uv[2 * k]), kappa, J, 1);
   const AxisTaps tv = axis_taps(static_cast<double>(uv[2 * k + 1]), kappa, J, 1);
-  const int bu = mod_pos(tu.j0, K), bv = mod_pos(tv.j0, K);
+  const int bu = mod_pow2(tu.j0, K), bv = mod_pow2(tv.j0, K);
   const uint32_t tile = static_cast<uint32_t>((bv / T) * nT + bu / T);
   keys[k] = tile * static_cast<uint32_t>(T * T) + static_cast<uint32_t>((bv % T) * T + bu % T);
   vals[k] = static_cast<uint32_t>(k);
@@ -280,17 +280,28 @@ __global__ void gather_sorted_kernel(const R* uv, const R* w, const uint32_t* pe
 // ---------------------------------------------------------------------------
 static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Default tile side: 16 keeps the FP32 J <= 4 gridding moments at 32 KB of
-// LDS; wider kernels and FP64 use 8.
-static int default_tile(int J, int prec) { return (prec == PR_F32 && J <= 4) ? 16 : 8; }
+// Default tile side: aims at about a thousand visibilities per tile for the
+// gridding work items. FP32 with J <= 4 uses 16 (moments 32 KB of LDS) unless
+// the baselines are dense (8 or more per grid cell on average), then 8; wider
+// kernels and FP64 use 8.
+static int default_tile(int J, int prec, int64_t M, int K) {
+  if (prec == PR_F32 && J <= 4) return M < 8 * static_cast<int64_t>(K) * K ? 16 : 8;
+  return 8;
+}
 
-// Smallest LDS footprint of the gridding kernel for a tile (moments, side
-// slots and a 32-visibility staging batch, table in global memory).
+// Smallest LDS footprint of the gridding kernel for a tile: moments, one side
+// slot per segment and a 64-visibility staging batch, table in global memory
+// (segments: 256 / threads per segment, threads per segment = ceil(J / JA)
+// rounded up to a power of two, JA = moment columns per thread).
 static size_t grid_lds_min(int T, int J, int prec) {
   const size_t sr = prec == PR_F32 ? 4 : 8, sc = 2 * sr;
-  const size_t S = 4 * (64 / J);
-  return static_cast<size_t>(T) * T * J * J * sc + S * J * J * sc + 32 * (4 + J * sc + J * sr) +
-         (static_cast<size_t>(T) * T / 32 + 1) * 4 + 256;
+  int ja;
+  if (prec == PR_F32) ja = J <= 2 ? J : (J == 6 ? 3 : 2);
+  else ja = J <= 2 ? J : 2;
+  int tpc = (J + ja - 1) / ja;
+  if (tpc == 3) tpc = 4;
+  const size_t ns = 256 / tpc;
+  return static_cast<size_t>(T) * T * J * J * sc + ns * J * J * sc + ns * 4 + 64 * (4 + 2 * J * sr + sc) + 256;
 }
 
 int phi_validate(const pr_phi_desc* d) {
@@ -309,7 +320,7 @@ int phi_validate(const pr_phi_desc* d) {
     return PR_EINVAL;
   }
   const int K = d->oversample * d->n;
-  const int T = d->tile ? d->tile : default_tile(d->J, d->prec);
+  const int T = d->tile ? d->tile : default_tile(d->J, d->prec, d->M, K);
   if (T > K || T < d->J) { set_error("tile %d must satisfy J <= tile <= K (J=%d, K=%d)", T, d->J, K); return PR_EINVAL; }
   if (grid_lds_min(T, d->J, d->prec) > 163840) {
     set_error("tile %d with J=%d in %s needs more than 160 KB of LDS", T, d->J, d->prec == PR_F32 ? "FP32" : "FP64");
@@ -326,11 +337,18 @@ int phi_prepare(pr_phi_plan_t* p, const pr_phi_desc* d) {
   p->D = d->D;
   p->M = d->M;
   p->prec = d->prec;
-  p->T = d->tile ? d->tile : default_tile(d->J, d->prec);
+  p->T = d->tile ? d->tile : default_tile(d->J, d->prec, d->M, p->K);
   p->P = p->T + p->J - 1;
   p->nT = p->K / p->T;
   p->nTiles = p->nT * p->nT;
-  p->chunk = d->prec == PR_F32 ? 8192 : 4096;
+  // Work-item size: about M / 2048 visibilities (a power of two in [512, 8192])
+  // so that dense tiles split over many blocks while large inputs keep few
+  // patches to merge.
+  {
+    int64_t c = 512;
+    while (c < 8192 && c * 2048 < p->M) c *= 2;
+    p->chunk = static_cast<int>(c);
+  }
   p->nItemsMax = p->nTiles + (p->M + p->chunk - 1) / p->chunk;
   p->kappa = static_cast<double>(p->K) / (2.0 * M_PI);
   const double alpha = static_cast<double>(d->oversample);

@@ -47,4 +47,14 @@ __device__ __forceinline__ int mod_pos(int a, int K) {
   return r < 0 ? r + K : r;
 }
 
+// a mod K for K a power of two (two's complement keeps this right for a < 0).
+__device__ __forceinline__ int mod_pow2(int a, int K) { return a & (K - 1); }
+
+// i / d and i mod d for small non-negative i and d (i < 2^20, d < 2^12): the
+// float quotient of i + 1/2 is at least 1/(2d) away from an integer, far more
+// than its rounding error, so the truncation is exact.
+__device__ __forceinline__ int small_div(int i, int d, float inv_d) {
+  return static_cast<int>((static_cast<float>(i) + 0.5f) * inv_d);
+}
+
 }  // namespace pr

@@ -62,7 +62,8 @@ def test_tiles_that_do_not_fit_lds_are_refused(P):
     with pytest.raises(P.PrError) as e:
         P.pr_phi_plan_sizes(P.pr_phi_desc(256, 2, 6, 2000, 1000, 0, 32))
     assert e.value.code == P.PR_EUNSUPPORTED
-    assert P.pr_phi_plan_sizes(P.pr_phi_desc(256, 2, 4, 2000, 1000, 0, 32))[0] > 0
+    assert P.pr_phi_plan_sizes(P.pr_phi_desc(256, 2, 2, 2000, 1000, 0, 32))[0] > 0
+    assert P.pr_phi_plan_sizes(P.pr_phi_desc(256, 2, 8, 2000, 1000, 1, 8))[0] > 0
 
 
 def test_phi_sizes_scale_with_the_problem(P):

@@ -58,12 +58,12 @@ def test_phi_and_adjoint_parity(P, prec, n, M, J, tile, weights):
     assert rel_l2(x_gpu, x_ref) <= TOL[prec]
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_plan_order_is_the_stable_cell_sort(P, tile):
+@pytest.mark.parametrize("J,tile", [(4, 8), (4, 16), (2, 32)])
+def test_plan_order_is_the_stable_cell_sort(P, J, tile):
     n, M = 64, 20000
-    say(f"plan order tile={tile}")
-    x, uv, w, spec = problem(n, M, 4, 2000, seed=tile)
-    plan, perm = make_plan(P, n, uv, None, 4, 2000, "f32", tile)
+    say(f"plan order J={J} tile={tile}")
+    x, uv, w, spec = problem(n, M, J, 2000, seed=tile)
+    plan, perm = make_plan(P, n, uv, None, J, 2000, "f32", tile)
     keys = cell_keys(uv.astype(np.float64), spec, tile)
     ks = keys[perm]
     assert np.all(np.diff(ks) >= 0)
@@ -72,13 +72,21 @@ def test_plan_order_is_the_stable_cell_sort(P, tile):
     assert np.all(np.diff(perm)[same] > 0)
 
 
-def test_large_tile_fp32(P):
-    n, M = 128, 40000
-    say("phi parity tile 32 f32")
-    x, uv, w, spec = problem(n, M, 4, 2000, seed=77)
-    plan, perm = make_plan(P, n, uv, None, 4, 2000, "f32", 32)
-    y_gpu = plan.apply(to_dev(x, torch.float32)).cpu().numpy()
-    assert rel_l2(y_gpu, ms.phi(x, uv.astype(np.float64), None, spec)[perm]) <= 1e-5
+@pytest.mark.parametrize("prec,J,tile,M", [("f32", 2, 32, 40000), ("f32", 6, 16, 40000), ("f64", 6, 8, 30000),
+                                           ("f64", 8, 8, 30000), ("f32", 4, 8, 600000), ("f64", 4, 16, 50000)])
+def test_tile_and_support_variants(P, prec, J, tile, M):
+    # includes a dense case (~37 visibilities per grid cell) where runs span many segments
+    n = 64 if M > 100000 else 128
+    say(f"phi variants {prec} J={J} tile={tile} M={M}")
+    x, uv, w, spec = problem(n, M, J, 2000, seed=77 + J, prec=prec, weights=True)
+    plan, perm = make_plan(P, n, uv, w, J, 2000, prec, tile)
+    uv64, w64 = uv.astype(np.float64), w.astype(np.float64)
+    y_gpu = plan.apply(to_dev(x, _rdt(prec))).cpu().numpy()
+    assert rel_l2(y_gpu, ms.phi(x, uv64, w64, spec)[perm]) <= TOL[prec]
+    rng = np.random.default_rng(3)
+    yy = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    x_gpu = plan.adjoint(to_dev(yy[perm], _cdt(prec))).cpu().numpy()
+    assert rel_l2(x_gpu, ms.phi_adjoint(yy, uv64, w64, spec)) <= TOL[prec]
 
 
 def test_empty_visibility_set(P):

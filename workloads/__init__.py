@@ -195,3 +195,54 @@ def batch_channels(n_channels: int, rng: np.random.Generator,
     ns = rng.choice(np.asarray(sizes), n_channels)
     ms = np.exp(rng.uniform(math.log(m_lo), math.log(m_hi), n_channels)).astype(np.int64)
     return [(int(a), int(b)) for a, b in zip(ns, ms)]
+
+
+# --------------------------------------------------------------------------
+# device-side generators for the 5e8-visibility workload (torch RNG, seeded)
+# --------------------------------------------------------------------------
+def torch_generator(config_index: int, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(1000 + int(config_index))
+    return g
+
+
+def uv_ring_core_torch(M: int, gen, device, chunk: int = 1 << 26):
+    """Ring-plus-core baselines drawn on the device (same law as uv_ring_core)."""
+    import torch
+    out = torch.empty((M, 2), dtype=torch.float32, device=device)
+    filled = 0
+    while filled < M:
+        want = min(chunk, M - filled)
+        m = int(want * 1.05) + 16
+        core = torch.rand(m, generator=gen, device=device) < 0.6
+        r = torch.where(core, torch.randn(m, generator=gen, device=device).abs() * (math.pi / 6),
+                        0.55 * math.pi + 0.08 * math.pi * torch.randn(m, generator=gen, device=device))
+        th = torch.rand(m, generator=gen, device=device) * TWO_PI
+        u = (r * torch.cos(th)).float()
+        v = (r * torch.sin(th)).float()
+        ok = (u >= -math.pi) & (u < math.pi) & (v >= -math.pi) & (v < math.pi)
+        u, v = u[ok][:want], v[ok][:want]
+        out[filled:filled + u.numel(), 0] = u
+        out[filled:filled + u.numel(), 1] = v
+        filled += u.numel()
+    return out
+
+
+def unit_complex_noise_torch(M: int, gen, device, dtype=None):
+    import torch
+    dtype = torch.complex64 if dtype is None else dtype
+    re = torch.randn(M, generator=gen, device=device)
+    im = torch.randn(M, generator=gen, device=device)
+    return torch.complex(re, im).to(dtype) / math.sqrt(2.0)
+
+
+def add_noise_torch(y0, draws, snr_db: float = 30.0):
+    """Device version of add_noise: returns (y, sigma, epsilon)."""
+    import torch
+    M = y0.numel()
+    nrm = float(torch.linalg.vector_norm(y0.to(torch.complex128) if y0.numel() < (1 << 27) else y0).item())
+    sigma = nrm / math.sqrt(M) * 10.0 ** (-snr_db / 20.0)
+    y = y0 + sigma * draws
+    eps = sigma * math.sqrt(M + 2.0 * math.sqrt(M))
+    return y, sigma, eps
