@@ -483,6 +483,227 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// gridding, segment walk with chunked staging (J <= 4)
+// ---------------------------------------------------------------------------
+// LDS: kernel table (optional), moments [J*J][T*T] (entry-major), presence
+// bits, one region holding either a staged chunk (u, v and the weighted value
+// of kWalkChunk positions per thread, lane-transposed) or the side slots
+// [J*J][kThreads], and the first/last base cell per thread.
+constexpr int kWalkChunk = 8;   // positions per thread and staged chunk
+
+template <typename R, int J>
+struct WalkLds {
+  size_t tab, mom, bits, stage, fcell, lcell, total;
+  __host__ __device__ WalkLds(int T, int tlen, bool tab_lds) {
+    using C = cx_t<R>;
+    size_t o = 0;
+    tab = o;   o += tab_lds ? align16(static_cast<size_t>(tlen) * sizeof(R)) : 0;
+    mom = o;   o += align16(static_cast<size_t>(T) * T * J * J * sizeof(C));
+    bits = o;  o += align16(static_cast<size_t>((T * T + 31) / 32) * sizeof(uint32_t));
+    const size_t staged = align16(static_cast<size_t>(kThreads) * kWalkChunk * 2 * sizeof(C));
+    const size_t sides = align16(static_cast<size_t>(kThreads) * J * J * sizeof(C));
+    stage = o; o += staged > sides ? staged : sides;
+    fcell = o; o += align16(static_cast<size_t>(kThreads) * sizeof(int));
+    lcell = o; o += align16(static_cast<size_t>(kThreads) * sizeof(int));
+    total = o;
+  }
+};
+
+// Thread t owns the contiguous segment [t L, (t+1) L) of the item's
+// cell-sorted visibilities, L = ceil(n / 256). The block stages the segments
+// chunk by chunk (kWalkChunk positions per thread, loaded with consecutive
+// threads on consecutive visibilities, stored lane-transposed) and each thread
+// walks its positions in order, computing taps in FP64 and holding the J^2
+// moments of its current run in registers across chunks. A run that begins
+// and ends inside a segment is stored at once. At the end of the item a
+// barrier publishes each segment's first and last base cell; a segment whose
+// first run continues the previous segment's last run parks it in its side
+// slot; every other run is completed by the segment it begins in, which adds
+// the parked slots of the following segments in order. Each base cell's
+// moments are written exactly once per item: no zeroing, no value atomics.
+template <typename R, int J, int MODE, bool TAB_LDS>
+__global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
+  using C = cx_t<R>;
+  constexpr int JJ = J * J;
+  constexpr int CB = kThreads * kWalkChunk;
+  extern __shared__ char smem_raw[];
+  const WalkLds<R, J> lay(a.T, a.tlen, TAB_LDS);
+  C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem_raw + lay.bits);
+  C* st_uv = reinterpret_cast<C*>(smem_raw + lay.stage);        // (u, v)
+  C* st_val = st_uv + CB;                                         // weighted value
+  C* side = reinterpret_cast<C*>(smem_raw + lay.stage);          // after the walk
+  int* fcell = reinterpret_cast<int*>(smem_raw + lay.fcell);
+  int* lcell = reinterpret_cast<int*>(smem_raw + lay.lcell);
+  const int tid = threadIdx.x;
+  const R* tab = a.table;
+  if (TAB_LDS) {
+    R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
+    for (int i = tid; i < a.tlen; i += kThreads) t[i] = a.table[i];
+    tab = t;
+  }
+  const int T = a.T, P = a.P, K = a.K;
+  const int TT = T * T, nbits = (TT + 31) / 32;
+  R kappa_ball = 1;
+  if (MODE == 1) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
+
+  auto flush = [&](int cell, const R* xr, const R* xi) {
+#pragma unroll
+    for (int e = 0; e < JJ; ++e) mom[e * TT + cell] = cmk<C>(xr[e], xi[e]);
+    atomicOr(&bits[cell >> 5], 1u << (cell & 31));
+  };
+
+  for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
+    const int4 it = a.items[item];
+    const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
+    const int n = it.z - it.y;
+    const int L = (n + kThreads - 1) / kThreads;      // segment length
+    const int seg0 = it.y + tid * L;                   // this thread's first position
+    const int segn = max(0, min(L, it.z - seg0));      // its positions
+    __syncthreads();
+    for (int i = tid; i < nbits; i += kThreads) bits[i] = 0u;
+
+    R fr[JJ], fi[JJ], ar[JJ], ai[JJ];
+    int first = -1, cur = -1, nruns = 0;
+#pragma unroll
+    for (int e = 0; e < JJ; ++e) ar[e] = ai[e] = R(0);
+    for (int q0 = 0; q0 < L; q0 += kWalkChunk) {
+      __syncthreads();
+      // stage positions q0 .. q0 + kWalkChunk - 1 of every segment
+#pragma unroll
+      for (int r = 0; r < kWalkChunk; ++r) {
+        const int m = tid + r * kThreads;
+        const int t = m / kWalkChunk, i = m % kWalkChunk;
+        const int q = q0 + i;
+        const int pos = it.y + t * L + q;
+        if (q < L && pos < it.z) {
+          const int64_t k = pos;
+          C val;
+          if (MODE == 0) {
+            val = a.y_in[k];
+          } else {
+            // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
+            // r = y + kappa t, s' = s + varrho (v - r), q = v - r + s'
+            const C tt = a.t_in[k], sk = a.s_io[k];
+            const R omk = R(1) - kappa_ball;
+            const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
+            const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
+            a.s_io[k] = sn;
+            val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
+          }
+          const R ws = a.w[k] * a.scale;
+          st_uv[i * kThreads + t] = cmk<C>(a.uv[2 * k], a.uv[2 * k + 1]);
+          st_val[i * kThreads + t] = cmk<C>(val.x * ws, val.y * ws);
+        }
+      }
+      __syncthreads();
+      const int qn = min(kWalkChunk, segn - q0);
+      for (int i = 0; i < qn; ++i) {
+        const C uv = st_uv[i * kThreads + tid];
+        C val = st_val[i * kThreads + tid];
+        const AxisTaps xu = axis_taps(static_cast<double>(uv.x), a.kappa, J, a.D);
+        const AxisTaps xv = axis_taps(static_cast<double>(uv.y), a.kappa, J, a.D);
+        int lu = mod_pow2(xu.j0, K) - tu * T;
+        int lv = mod_pow2(xv.j0, K) - tv * T;
+        if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
+          // cannot happen for a plan's own sorted baselines: keep LDS indices in range, poison the value
+          lu = lv = 0;
+          val = cmk<C>(R(NAN), R(NAN));
+        }
+        const int c = lv * T + lu;
+        if (c != cur) {
+          if (nruns == 1) {
+#pragma unroll
+            for (int e = 0; e < JJ; ++e) { fr[e] = ar[e]; fi[e] = ai[e]; }
+          } else if (nruns > 1) {
+            flush(cur, ar, ai);                 // a run that began and ended in this segment
+          }
+          if (nruns == 0) first = c;
+          cur = c;
+          ++nruns;
+#pragma unroll
+          for (int e = 0; e < JJ; ++e) ar[e] = ai[e] = R(0);
+        }
+        R wv[J];
+#pragma unroll
+        for (int b = 0; b < J; ++b) wv[b] = tab[tap_index(xv, b, J, a.D)];
+#pragma unroll
+        for (int qq = 0; qq < J; ++qq) {
+          const R g = tab[tap_index(xu, qq, J, a.D)];
+          const R yr = val.x * g, yi = val.y * g;
+#pragma unroll
+          for (int b = 0; b < J; ++b) {
+            ar[qq * J + b] += wv[b] * yr;
+            ai[qq * J + b] += wv[b] * yi;
+          }
+        }
+      }
+    }
+    if (nruns == 1) {
+#pragma unroll
+      for (int e = 0; e < JJ; ++e) { fr[e] = ar[e]; fi[e] = ai[e]; }
+    }
+    fcell[tid] = first;
+    lcell[tid] = cur;
+    __syncthreads();   // staging consumed; first and last cells published
+    const bool cont_in = nruns > 0 && tid > 0 && lcell[tid - 1] == first;
+    bool pending = false;
+    if (nruns > 0) {
+      if (cont_in) {
+#pragma unroll
+        for (int e = 0; e < JJ; ++e) side[e * kThreads + tid] = cmk<C>(fr[e], fi[e]);
+        pending = nruns > 1;               // the last run began here
+      } else if (nruns == 1) {
+        pending = true;                    // first run = last run, begun here
+      } else {
+        flush(first, fr, fi);
+        pending = true;                    // the last run began here
+      }
+    }
+    __syncthreads();
+    if (pending) {
+      // complete the run with the parked parts of the following segments, in order
+      for (int j = tid + 1; j < kThreads; ++j) {
+        if (fcell[j] != cur) break;
+#pragma unroll
+        for (int e = 0; e < JJ; ++e) {
+          const C d = side[e * kThreads + j];
+          ar[e] += d.x;
+          ai[e] += d.y;
+        }
+        if (lcell[j] != cur) break;
+      }
+      flush(cur, ar, ai);
+    }
+    __syncthreads();
+    // patch: cell q = c + (b, a) collects moment [a][b] of base cell c
+    C* out = a.patches + item * static_cast<int64_t>(P) * P;
+    const float invP = 1.0f / P;
+    for (int pc = tid; pc < P * P; pc += kThreads) {
+      const int pv = small_div(pc, P, invP), pu = pc - pv * P;
+      R sr2 = 0, si2 = 0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        const int cv = pv - b;
+        if (cv < 0 || cv >= T) continue;
+#pragma unroll
+        for (int qq = 0; qq < J; ++qq) {
+          const int cu = pu - qq;
+          if (cu < 0 || cu >= T) continue;
+          const int c = cv * T + cu;
+          if ((bits[c >> 5] >> (c & 31)) & 1u) {
+            const C m = mom[(qq * J + b) * TT + c];
+            sr2 += m.x;
+            si2 += m.y;
+          }
+        }
+      }
+      out[pc] = cmk<C>(sr2, si2);
+    }
+  }
+}
+
 // Columns of the moments held per gridding thread (JA): FP32 keeps at most 8
 // complex accumulators per thread for J <= 4 (two threads per segment), FP64
 // at most 8.
@@ -605,20 +826,39 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s) {
   using C = cx_t<R>;
   constexpr int JA = GridSplit<R, J>::JA;
   const int G = degrid_blocks(p);
-  int B;
-  bool tab_lds;
-  size_t bytes;
-  if (!pick_grid_lds<R, J>(a.T, a.tlen, &B, &tab_lds, &bytes)) {
-    set_error("gridding tile %d with J=%d does not fit in LDS", a.T, J);
-    return PR_EUNSUPPORTED;
+  bool walked = false;
+  if (J <= 4) {
+    // segment walk: table in LDS if both fit the two-blocks-per-CU budget
+    const WalkLds<R, J> with(a.T, a.tlen, true), without(a.T, a.tlen, false);
+    const bool tl = with.total <= kLdsSoft;
+    const size_t bytes = tl ? with.total : without.total;
+    if (bytes <= kLdsHard) {
+      if (tl) {
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true>, bytes));
+        grid_walk_kernel<R, J, MODE, true><<<G, kThreads, bytes, s>>>(a);
+      } else {
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false>, bytes));
+        grid_walk_kernel<R, J, MODE, false><<<G, kThreads, bytes, s>>>(a);
+      }
+      walked = true;
+    }
   }
-  a.B = B;
-  if (tab_lds) {
-    PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true>, bytes));
-    grid_kernel<R, J, JA, MODE, true><<<G, kThreads, bytes, s>>>(a);
-  } else {
-    PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false>, bytes));
-    grid_kernel<R, J, JA, MODE, false><<<G, kThreads, bytes, s>>>(a);
+  if (!walked) {
+    int B;
+    bool tab_lds;
+    size_t bytes;
+    if (!pick_grid_lds<R, J>(a.T, a.tlen, &B, &tab_lds, &bytes)) {
+      set_error("gridding tile %d with J=%d does not fit in LDS", a.T, J);
+      return PR_EUNSUPPORTED;
+    }
+    a.B = B;
+    if (tab_lds) {
+      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true>, bytes));
+      grid_kernel<R, J, JA, MODE, true><<<G, kThreads, bytes, s>>>(a);
+    } else {
+      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false>, bytes));
+      grid_kernel<R, J, JA, MODE, false><<<G, kThreads, bytes, s>>>(a);
+    }
   }
   PR_TRY_LAUNCH();
   merge_patches_kernel<R><<<p->nTiles, p->T * p->T < kThreads ? p->T * p->T : kThreads, 0, s>>>(
