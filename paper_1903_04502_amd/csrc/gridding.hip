@@ -30,7 +30,8 @@ constexpr int kSlotNonfinite = 3;
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxBlocks = 1024;   // persistent blocks (4 per CU); <= kPartialsMax
+constexpr int kDegridBlocks = 2048;   // persistent degridding blocks (8 per CU); <= kPartialsMax
+constexpr int kGridBlocks = 512;      // persistent gridding blocks (2 per CU, bound by LDS)
 constexpr size_t kLdsSoft = 81920;    // two blocks per CU
 constexpr size_t kLdsHard = 163840;   // per-workgroup limit on gfx950
 
@@ -50,6 +51,7 @@ struct GwArgs {
   int K, T, P, nT, lognT, D, tlen;
   double kappa;
   R scale;
+  const double* scale_dev; // when set, the scale is read from device memory (MODE 1)
   cx_t<R>* y_out;          // MODE 0
   const cx_t<R>* y_obs;    // MODE 1
   const cx_t<R>* s_in;
@@ -62,6 +64,7 @@ constexpr int kDegridPer = 4;   // visibilities per thread per chunk
 template <typename R, int J, int MODE, bool TAB_LDS>
 __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   using C = cx_t<R>;
+  const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int CH = kThreads * kDegridPer;
   extern __shared__ char smem_raw[];
   const int tid = threadIdx.x;
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
           accr += wv[b] * rr;
           acci += wv[b] * ri;
         }
-        const R ws = cw_[j] * a.scale;
+        const R ws = cw_[j] * scale;
         const C yk = cmk<C>(accr * ws, acci * ws);
         if (MODE == 0) {
           a.y_out[k] = yk;
@@ -182,6 +185,7 @@ struct GwAdjArgs {
   int K, T, P, nT, lognT, D, tlen, B;
   double kappa;
   R scale;
+  const double* scale_dev;   // when set, the scale is read from device memory (MODE 1)
   const cx_t<R>* y_in;       // MODE 0
   const cx_t<R>* t_in;       // MODE 1: t = v + s - y
   cx_t<R>* s_io;             // MODE 1: multiplier, updated
@@ -239,6 +243,7 @@ constexpr int kGridPer = 4;   // staged visibilities per thread: B <= kThreads *
 template <typename R, int J, int JA, int MODE, bool TAB_LDS>
 __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
+  const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int TPC = (J + JA - 1) / JA;
   constexpr int NS = kThreads / (TPC == 3 ? 4 : TPC);
@@ -352,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
           a.s_io[k] = sn;
           val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
         }
-        const R ws = rw[j] * a.scale;
+        const R ws = rw[j] * scale;
         val = cmk<C>(val.x * ws, val.y * ws);
         if (!inside) {
           // cannot happen for a plan's own sorted baselines; keep LDS indices in range, poison the value
@@ -486,22 +491,24 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
 // ---------------------------------------------------------------------------
 // gridding, segment walk with chunked staging (J <= 4)
 // ---------------------------------------------------------------------------
-// LDS: kernel table (optional), moments [J*J][T*T] (entry-major), presence
-// bits, one region holding either a staged chunk (u, v and the weighted value
-// of kWalkChunk positions per thread, lane-transposed) or the side slots
-// [J*J][kThreads], and the first/last base cell per thread.
-constexpr int kWalkChunk = 8;   // positions per thread and staged chunk
+// LDS: kernel table (optional), moments [J*J][T*T] (entry-major), one region
+// holding either a staged chunk (u, v and the weighted value of WC positions
+// per thread, lane-transposed) or the side slots [J*J][kThreads], and the
+// first/last base cell per thread.
+// Positions per thread and staged chunk: FP32 8, FP64 4 (the prefetch
+// registers hold one chunk).
+template <typename R> struct WalkChunk { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
 
 template <typename R, int J>
 struct WalkLds {
-  size_t tab, mom, bits, stage, fcell, lcell, total;
+  size_t tab, mom, stage, fcell, lcell, total;
   __host__ __device__ WalkLds(int T, int tlen, bool tab_lds) {
     using C = cx_t<R>;
+    constexpr int WC = WalkChunk<R>::value;
     size_t o = 0;
     tab = o;   o += tab_lds ? align16(static_cast<size_t>(tlen) * sizeof(R)) : 0;
     mom = o;   o += align16(static_cast<size_t>(T) * T * J * J * sizeof(C));
-    bits = o;  o += align16(static_cast<size_t>((T * T + 31) / 32) * sizeof(uint32_t));
-    const size_t staged = align16(static_cast<size_t>(kThreads) * kWalkChunk * 2 * sizeof(C));
+    const size_t staged = align16(static_cast<size_t>(kThreads) * WC * 2 * sizeof(C));
     const size_t sides = align16(static_cast<size_t>(kThreads) * J * J * sizeof(C));
     stage = o; o += staged > sides ? staged : sides;
     fcell = o; o += align16(static_cast<size_t>(kThreads) * sizeof(int));
@@ -510,27 +517,50 @@ struct WalkLds {
   }
 };
 
+// Registers holding one chunk's inputs between the loads and the LDS stores,
+// so that the loads of the next chunk (or of the next item's first chunk) are
+// in flight while the current chunk is walked. Slot r of thread tid is
+// position (tid mod WC) of segment tid / WC + r * kThreads / WC.
+template <typename R, int MODE>
+struct WalkPrefetch {
+  using C = cx_t<R>;
+  static constexpr int WC = WalkChunk<R>::value;
+  C uv[WC];
+  C val[WC];                      // MODE 0: y; MODE 1: t = v + s - y
+  C s[MODE == 1 ? WC : 1];        // MODE 1: multiplier before the update
+  R w[WC];
+  unsigned ok;                    // bit r: slot r holds a position of the item
+};
+
 // Thread t owns the contiguous segment [t L, (t+1) L) of the item's
 // cell-sorted visibilities, L = ceil(n / 256). The block stages the segments
-// chunk by chunk (kWalkChunk positions per thread, loaded with consecutive
-// threads on consecutive visibilities, stored lane-transposed) and each thread
-// walks its positions in order, computing taps in FP64 and holding the J^2
-// moments of its current run in registers across chunks. A run that begins
-// and ends inside a segment is stored at once. At the end of the item a
-// barrier publishes each segment's first and last base cell; a segment whose
-// first run continues the previous segment's last run parks it in its side
-// slot; every other run is completed by the segment it begins in, which adds
-// the parked slots of the following segments in order. Each base cell's
-// moments are written exactly once per item: no zeroing, no value atomics.
+// chunk by chunk (WC positions per thread, loaded with consecutive threads on
+// consecutive visibilities, stored lane-transposed) and each thread walks its
+// positions in order, computing taps in FP64 and holding the J^2 moments of
+// its current run in registers across chunks. Moments start at zero; each
+// base cell's moments are stored once per item, plus at most one earlier
+// store of a continuation part (below). No value atomics.
+//
+// Runs and segments: because the item is cell-sorted, a run that crosses
+// segment boundaries covers the end of its owner segment (where it begins),
+// zero or more whole middle segments and possibly the start of a final
+// segment where it ends. A run that ends inside the segment where it begins is
+// stored as soon as it ends. The final segment stores its part (its first run)
+// in the cell's moments as soon as that run ends; a middle segment parks its
+// whole sum in its side slot after the walk; the owner then adds, in segment
+// order, the side slots of the middle segments and the final part already in
+// the moments, and stores the total.
 template <typename R, int J, int MODE, bool TAB_LDS>
 __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
+  const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
-  constexpr int CB = kThreads * kWalkChunk;
+  constexpr int WC = WalkChunk<R>::value;
+  constexpr int CB = kThreads * WC;
+  constexpr int kSegStride = kThreads / WC;
   extern __shared__ char smem_raw[];
   const WalkLds<R, J> lay(a.T, a.tlen, TAB_LDS);
   C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
-  uint32_t* bits = reinterpret_cast<uint32_t*>(smem_raw + lay.bits);
   C* st_uv = reinterpret_cast<C*>(smem_raw + lay.stage);        // (u, v)
   C* st_val = st_uv + CB;                                         // weighted value
   C* side = reinterpret_cast<C*>(smem_raw + lay.stage);          // after the walk
@@ -544,61 +574,88 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     tab = t;
   }
   const int T = a.T, P = a.P, K = a.K;
-  const int TT = T * T, nbits = (TT + 31) / 32;
+  const int TT = T * T;
   R kappa_ball = 1;
   if (MODE == 1) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
+  const C* uv2 = reinterpret_cast<const C*>(a.uv);
+  const int lane_q = tid & (WC - 1);      // position within the chunk this thread loads
+  const int lane_t = tid / WC;            // first segment this thread loads for
 
-  auto flush = [&](int cell, const R* xr, const R* xi) {
+  WalkPrefetch<R, MODE> pf;
+  // issue the loads of positions q0 .. q0 + WC - 1 of every segment of item it
+  auto issue = [&](const int4& it, int L, int q0) {
+    pf.ok = 0u;
 #pragma unroll
-    for (int e = 0; e < JJ; ++e) mom[e * TT + cell] = cmk<C>(xr[e], xi[e]);
-    atomicOr(&bits[cell >> 5], 1u << (cell & 31));
+    for (int r = 0; r < WC; ++r) {
+      const int q = q0 + lane_q;
+      const int pos = it.y + (lane_t + r * kSegStride) * L + q;
+      if (q < L && pos < it.z) {
+        pf.ok |= 1u << r;
+        pf.uv[r] = uv2[pos];
+        pf.w[r] = a.w[pos];
+        if (MODE == 0) {
+          pf.val[r] = a.y_in[pos];
+        } else {
+          pf.val[r] = a.t_in[pos];
+          pf.s[MODE == 1 ? r : 0] = a.s_io[pos];
+        }
+      }
+    }
   };
+  // store the prefetched chunk lane-transposed (ADMM prologue applied here)
+  auto commit = [&](const int4& it, int L, int q0) {
+#pragma unroll
+    for (int r = 0; r < WC; ++r) {
+      if (!((pf.ok >> r) & 1u)) continue;
+      C val;
+      if (MODE == 0) {
+        val = pf.val[r];
+      } else {
+        // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
+        // r = y + kappa t, s' = s + varrho (v - r), q = v - r + s'
+        const C tt = pf.val[r], sk = pf.s[MODE == 1 ? r : 0];
+        const R omk = R(1) - kappa_ball;
+        const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
+        const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
+        a.s_io[it.y + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
+        val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
+      }
+      const R ws = pf.w[r] * scale;
+      const int slot = lane_q * kThreads + lane_t + r * kSegStride;
+      st_uv[slot] = pf.uv[r];
+      st_val[slot] = cmk<C>(val.x * ws, val.y * ws);
+    }
+  };
+  auto seg_len = [](const int4& it) { return (it.z - it.y + kThreads - 1) / kThreads; };
 
-  for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
-    const int4 it = a.items[item];
+  int64_t item = blockIdx.x;
+  int4 it = make_int4(0, 0, 0, 0);
+  int L = 0;
+  if (item < a.nItems) {
+    it = a.items[item];
+    L = seg_len(it);
+    issue(it, L, 0);
+  }
+  for (; item < a.nItems; item += gridDim.x) {
+    const int64_t nxt = item + gridDim.x;
+    const int4 itn = nxt < a.nItems ? a.items[nxt] : make_int4(0, 0, 0, 0);
+    const int Ln = seg_len(itn);
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
-    const int n = it.z - it.y;
-    const int L = (n + kThreads - 1) / kThreads;      // segment length
-    const int seg0 = it.y + tid * L;                   // this thread's first position
-    const int segn = max(0, min(L, it.z - seg0));      // its positions
-    __syncthreads();
-    for (int i = tid; i < nbits; i += kThreads) bits[i] = 0u;
+    const int segn = max(0, min(L, it.z - (it.y + tid * L)));   // this thread's positions
+    __syncthreads();   // the previous item is done with the moments and side slots
+    for (int i = tid; i < TT * JJ; i += kThreads) mom[i] = cmk<C>(R(0), R(0));
 
-    R fr[JJ], fi[JJ], ar[JJ], ai[JJ];
+    R ar[JJ], ai[JJ];
     int first = -1, cur = -1, nruns = 0;
 #pragma unroll
     for (int e = 0; e < JJ; ++e) ar[e] = ai[e] = R(0);
-    for (int q0 = 0; q0 < L; q0 += kWalkChunk) {
+    for (int q0 = 0; q0 < L; q0 += WC) {
+      if (q0 > 0) __syncthreads();   // the previous chunk has been walked
+      commit(it, L, q0);
+      if (q0 + WC < L) issue(it, L, q0 + WC);
+      else if (nxt < a.nItems) issue(itn, Ln, 0);
       __syncthreads();
-      // stage positions q0 .. q0 + kWalkChunk - 1 of every segment
-#pragma unroll
-      for (int r = 0; r < kWalkChunk; ++r) {
-        const int m = tid + r * kThreads;
-        const int t = m / kWalkChunk, i = m % kWalkChunk;
-        const int q = q0 + i;
-        const int pos = it.y + t * L + q;
-        if (q < L && pos < it.z) {
-          const int64_t k = pos;
-          C val;
-          if (MODE == 0) {
-            val = a.y_in[k];
-          } else {
-            // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
-            // r = y + kappa t, s' = s + varrho (v - r), q = v - r + s'
-            const C tt = a.t_in[k], sk = a.s_io[k];
-            const R omk = R(1) - kappa_ball;
-            const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
-            const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
-            a.s_io[k] = sn;
-            val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
-          }
-          const R ws = a.w[k] * a.scale;
-          st_uv[i * kThreads + t] = cmk<C>(a.uv[2 * k], a.uv[2 * k + 1]);
-          st_val[i * kThreads + t] = cmk<C>(val.x * ws, val.y * ws);
-        }
-      }
-      __syncthreads();
-      const int qn = min(kWalkChunk, segn - q0);
+      const int qn = min(WC, segn - q0);
       for (int i = 0; i < qn; ++i) {
         const C uv = st_uv[i * kThreads + tid];
         C val = st_val[i * kThreads + tid];
@@ -613,13 +670,15 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         }
         const int c = lv * T + lu;
         if (c != cur) {
-          if (nruns == 1) {
+          if (nruns > 0) {
+            // the run on cur ended inside this segment: its sum is final
+            // unless it is the segment's first run and continues the previous
+            // segment, in which case the owner adds it later
 #pragma unroll
-            for (int e = 0; e < JJ; ++e) { fr[e] = ar[e]; fi[e] = ai[e]; }
-          } else if (nruns > 1) {
-            flush(cur, ar, ai);                 // a run that began and ended in this segment
+            for (int e = 0; e < JJ; ++e) mom[e * TT + cur] = cmk<C>(ar[e], ai[e]);
+          } else {
+            first = c;
           }
-          if (nruns == 0) first = c;
           cur = c;
           ++nruns;
 #pragma unroll
@@ -640,41 +699,39 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         }
       }
     }
-    if (nruns == 1) {
-#pragma unroll
-      for (int e = 0; e < JJ; ++e) { fr[e] = ar[e]; fi[e] = ai[e]; }
-    }
     fcell[tid] = first;
     lcell[tid] = cur;
     __syncthreads();   // staging consumed; first and last cells published
-    const bool cont_in = nruns > 0 && tid > 0 && lcell[tid - 1] == first;
-    bool pending = false;
-    if (nruns > 0) {
-      if (cont_in) {
+    // the last run (in registers) continues the previous segment only if the
+    // whole segment is one run: a middle segment, parked for its owner
+    const bool middle = nruns == 1 && tid > 0 && lcell[tid - 1] == first;
+    if (middle) {
 #pragma unroll
-        for (int e = 0; e < JJ; ++e) side[e * kThreads + tid] = cmk<C>(fr[e], fi[e]);
-        pending = nruns > 1;               // the last run began here
-      } else if (nruns == 1) {
-        pending = true;                    // first run = last run, begun here
-      } else {
-        flush(first, fr, fi);
-        pending = true;                    // the last run began here
-      }
+      for (int e = 0; e < JJ; ++e) side[e * kThreads + tid] = cmk<C>(ar[e], ai[e]);
     }
-    __syncthreads();
-    if (pending) {
-      // complete the run with the parked parts of the following segments, in order
-      for (int j = tid + 1; j < kThreads; ++j) {
-        if (fcell[j] != cur) break;
+    // owner of the last run: middle segments are [tid + 1, jend); a final
+    // segment, if any, has already stored its part in the moments of cur
+    int jend = tid + 1;
+    const bool owner = nruns > 0 && !middle;
+    if (owner) {
+      while (jend < kThreads && fcell[jend] == cur && lcell[jend] == cur) ++jend;
+    }
+    __syncthreads();   // side slots written
+    if (owner) {
+      for (int j = tid + 1; j < jend; ++j) {
 #pragma unroll
         for (int e = 0; e < JJ; ++e) {
           const C d = side[e * kThreads + j];
           ar[e] += d.x;
           ai[e] += d.y;
         }
-        if (lcell[j] != cur) break;
       }
-      flush(cur, ar, ai);
+#pragma unroll
+      for (int e = 0; e < JJ; ++e) {
+        C* m = &mom[e * TT + cur];
+        const C fin = *m;                // final segment's part, or zero
+        *m = cmk<C>(ar[e] + fin.x, ai[e] + fin.y);
+      }
     }
     __syncthreads();
     // patch: cell q = c + (b, a) collects moment [a][b] of base cell c
@@ -691,16 +748,15 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         for (int qq = 0; qq < J; ++qq) {
           const int cu = pu - qq;
           if (cu < 0 || cu >= T) continue;
-          const int c = cv * T + cu;
-          if ((bits[c >> 5] >> (c & 31)) & 1u) {
-            const C m = mom[(qq * J + b) * TT + c];
-            sr2 += m.x;
-            si2 += m.y;
-          }
+          const C m = mom[(qq * J + b) * TT + cv * T + cu];
+          sr2 += m.x;
+          si2 += m.y;
         }
       }
       out[pc] = cmk<C>(sr2, si2);
     }
+    it = itn;
+    L = Ln;
   }
 }
 
@@ -765,7 +821,11 @@ __global__ void ball_scale_kernel(const double* partials, int nblocks, double ep
 }
 
 int degrid_blocks(const pr_phi_plan_t* p) {
-  return static_cast<int>(p->nItems < kMaxBlocks ? p->nItems : kMaxBlocks);
+  return static_cast<int>(p->nItems < kDegridBlocks ? p->nItems : kDegridBlocks);
+}
+
+int grid_blocks(const pr_phi_plan_t* p) {
+  return static_cast<int>(p->nItems < kGridBlocks ? p->nItems : kGridBlocks);
 }
 
 template <typename K>
@@ -825,9 +885,9 @@ template <typename R, int J, int MODE>
 int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s) {
   using C = cx_t<R>;
   constexpr int JA = GridSplit<R, J>::JA;
-  const int G = degrid_blocks(p);
+  const int G = grid_blocks(p);
   bool walked = false;
-  if (J <= 4) {
+  if constexpr (J <= 4) {
     // segment walk: table in LDS if both fit the two-blocks-per-CU budget
     const WalkLds<R, J> with(a.T, a.tlen, true), without(a.T, a.tlen, false);
     const bool tl = with.total <= kLdsSoft;
@@ -925,6 +985,7 @@ template <typename R>
 int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
   GwArgs<R> a = gw_args<R>(p, scale);
   a.y_obs = static_cast<const cx_t<R>*>(v.y);
+  a.scale_dev = v.scale_dev;
   a.s_in = static_cast<const cx_t<R>*>(v.s);
   a.t_out = static_cast<cx_t<R>*>(v.t);
   a.partials = p->partials;
@@ -957,6 +1018,7 @@ template <typename R>
 int gwadj_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
   GwAdjArgs<R> a = gwadj_args<R>(p, scale);
   a.t_in = static_cast<const cx_t<R>*>(v.t);
+  a.scale_dev = v.scale_dev;
   a.s_io = static_cast<cx_t<R>*>(v.s);
   a.scalars = v.sums;
   a.varrho = static_cast<R>(v.varrho);

@@ -65,6 +65,7 @@ struct AdmmVis {
   void* t;         // v + s - y, written by the degridding stage
   double* sums;    // device: [0] ||t||^2, [1] ||v - y||^2 (FP64)
   double eps, varrho;
+  const double* scale_dev = nullptr;   // device 1 / ||Phi||; overrides the host scale when set
 };
 int phi_gw_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);
 int phi_gw_adjoint_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);

@@ -341,11 +341,11 @@ int phi_prepare(pr_phi_plan_t* p, const pr_phi_desc* d) {
   p->P = p->T + p->J - 1;
   p->nT = p->K / p->T;
   p->nTiles = p->nT * p->nT;
-  // Work-item size: about M / 2048 visibilities (a power of two in [512, 8192])
-  // so that dense tiles split over many blocks while large inputs keep few
-  // patches to merge.
+  // Work-item size: about M / 2048 visibilities (a power of two in [2048, 8192])
+  // so that dense tiles split over many blocks while the fixed cost of an item
+  // (patch load or assembly, carries between segments) stays small.
   {
-    int64_t c = 512;
+    int64_t c = 2048;
     while (c < 8192 && c * 2048 < p->M) c *= 2;
     p->chunk = static_cast<int>(c);
   }
