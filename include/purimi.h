@@ -132,6 +132,11 @@ int pr_phi_fzs(pr_phi_plan plan, const void* x, void* stream);
 int pr_phi_gw(pr_phi_plan plan, void* y, void* stream);
 int pr_phi_gw_adjoint(pr_phi_plan plan, const void* y, void* stream);
 int pr_phi_fzs_adjoint(pr_phi_plan plan, void* x, void* stream);
+/* pr_phi_gw_adjoint in its two launches: per-work-item grid patches from the
+ * visibilities (each patch written once, no atomics), then the fixed-order
+ * merge of the up to four overlapping patches of every grid cell. */
+int pr_phi_grid_patches(pr_phi_plan plan, const void* y, void* stream);
+int pr_phi_grid_merge(pr_phi_plan plan, void* stream);
 
 /* Operator norm ||Phi|| by the power method on Re Phi^dagger Phi (Section
  * "Distributed Images"): x0 = constant image of unit norm, x <- A x / ||A x||
@@ -139,6 +144,18 @@ int pr_phi_fzs_adjoint(pr_phi_plan plan, void* x, void* stream);
  * vis_ws: device scratch of M complex values. Synchronises the stream. */
 int pr_phi_norm(pr_phi_plan plan, int32_t iters, void* vis_ws, double* norm,
                 void* stream);
+
+/* Tile-side autotuner: for each admissible tile side (8, 16, 32; desc->tile
+ * is ignored) build the plan into the given workspaces and time `reps`
+ * (Phi, Phi^dagger) pairs with HIP events on `stream` after one untimed pair.
+ * *best_tile receives the fastest side, *best_ms (nullable) its time per pair.
+ * Workspaces must hold the largest candidate (pr_phi_plan_sizes per side);
+ * vis_ws: device complex[M]. Synchronises the stream; the workspaces hold no
+ * usable plan afterwards. */
+int pr_phi_tune(const pr_phi_desc* desc, const void* uv, const void* w,
+                void* persistent_ws, void* scratch_ws, void* vis_ws,
+                int32_t reps, void* stream, int32_t* best_tile,
+                double* best_ms);
 
 /* ------------------------------------------------------------------------
  * SARA dictionary (Sections "Analysis and Synthesis", "Distributed Wavelet
@@ -213,7 +230,11 @@ typedef struct {
   double eta;          /* DualFB step                                        */
   double rel_tol;      /* > 0: stop when ||x_t - x_{t-1}|| / ||x_t|| < rel_tol
                           (synchronises every iteration); 0: fixed count    */
-  double op_norm;      /* ||Phi||; <= 0: computed by pr_phi_norm, 100 steps  */
+  double op_norm;      /* ||Phi||; <= 0: power method on the device (below)  */
+  double gamma_factor; /* used when gamma <= 0: gamma = gamma_factor *
+                          ||Psi^dagger Re Phi^dagger y||_inf / ||Phi||, formed
+                          on the device (must then be > 0)                   */
+  int32_t norm_iters;  /* power-method steps when op_norm <= 0 (<= 0: 100)   */
 } pr_admm_params;
 
 typedef struct {
@@ -230,12 +251,109 @@ int pr_admm_workspace_size(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes);
 
 /* Run Algorithm 1. y: complex[M], plan order. x: real[n*n], in: x0, out:
  * the last iterate (in units of the normalised operator: the physical image
- * is x / ||Phi||). rep: if not NULL, filled on return and the call
- * synchronises; if NULL and rel_tol == 0 and op_norm > 0 the call is fully
- * asynchronous. The two plans must have the same n and precision. */
+ * is x / ||Phi||), updated in place. 1 / ||Phi|| and gamma are kept in the
+ * workspace on the device. rep: if not NULL, filled on return and the call
+ * synchronises; if NULL and rel_tol == 0 the call is fully asynchronous.
+ * The two plans must have the same n and precision. */
 int pr_admm_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
                   const pr_admm_params* params, void* x, void* workspace,
                   pr_admm_report* rep, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent solves of Algorithm 1 (frequency channels
+ * or imaging jobs of different n and M) stepped together, each one the
+ * problem above with its own data (the per-channel / per-node split of the
+ * paper's Section "Distributed Images", kept on one GPU). A step runs one
+ * outer iteration of every member; members run on the batch's own streams in
+ * longest-first order and are joined back to the caller's stream. With
+ * use_graph the step is captured once into a HIP graph and replayed (one
+ * launch per step) until the membership changes. Each member needs its own
+ * Phi and Psi plans and workspace; its kernels are those of pr_admm_solve,
+ * so results are bitwise identical to the member solved alone.
+ * Ownership: plans, data and workspaces stay the caller's and must outlive
+ * the membership. The batch holds only host objects (streams, events, graph).
+ * ---------------------------------------------------------------------- */
+typedef struct pr_batch_t* pr_batch;
+
+/* max_members in [1, 4096]; nstreams in [1, 64] streams of default priority. */
+int pr_batch_create(int32_t max_members, int32_t nstreams, pr_batch* out);
+/* Waits for the batch streams, then frees the host objects. */
+int pr_batch_destroy(pr_batch b);
+/* Add a member: y complex[M] in plan order, x real[n*n] (in: x0, out: the
+ * iterate, updated in place), workspace of pr_admm_workspace_size bytes.
+ * The member's state is cleared and 1 / ||Phi|| (and gamma when
+ * params->gamma <= 0) formed on the device, asynchronously on `stream`.
+ * params->iters and rel_tol are ignored (pr_batch_step sets the count).
+ * Fails with PR_EINVAL if either plan is already used by a member. */
+int pr_batch_add(pr_batch b, pr_phi_plan phi, pr_psi_plan psi, const void* y,
+                 void* x, const pr_admm_params* params, void* workspace,
+                 void* stream, int32_t* slot);
+int pr_batch_remove(pr_batch b, int32_t slot);
+int pr_batch_members(pr_batch b, int32_t* count);
+/* iters outer iterations of every member, asynchronous on `stream`. */
+int pr_batch_step(pr_batch b, int32_t iters, int32_t use_graph, void* stream);
+/* Batched operators over the members' plans: for each slot i with both
+ * pointers non-NULL, y[i] = Phi_i x[i] (plan order) or x[i] = Re Phi_i^dagger y[i].
+ * x, y: HOST arrays of device pointers indexed by slot (max_members long). */
+int pr_batch_phi_apply(pr_batch b, const void* const* x, void* const* y,
+                       void* stream);
+int pr_batch_phi_adjoint(pr_batch b, const void* const* y, void* const* x,
+                         void* stream);
+/* FP64 diagnostics of a member's current iterate (synchronises `stream`). */
+int pr_batch_report(pr_batch b, int32_t slot, pr_admm_report* rep, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over imaging solves with continuous batching.
+ * Requests are admitted in arrival order as the active-job limit and the
+ * caller's device arena allow (the footprint is exact: plans, workspace,
+ * plan-ordered visibilities and image, see pr_server_job_bytes); admitted
+ * jobs run one outer iteration per tick on a pool of streams, so jobs join
+ * and leave while others run. A job's kernels are those of a solve alone:
+ * its result is independent of the mix. The library allocates no device
+ * memory: everything lives in the arena. Calls on one server must come from
+ * one thread.
+ * ---------------------------------------------------------------------- */
+typedef struct pr_server_t* pr_server;
+
+typedef struct {
+  int32_t n;            /* image side (power of two)                          */
+  int32_t J;            /* kernel support                                     */
+  int32_t D;            /* table samples per grid cell; <= 0: 2000            */
+  int32_t tile;         /* 0: default                                         */
+  int32_t levels;       /* wavelet levels                                     */
+  uint32_t basis_mask;  /* SARA bases: bit 0 Dirac, bit k db k (0x1FF: all)    */
+  int32_t prec;         /* PR_F32 or PR_F64                                   */
+  int64_t M;            /* visibilities (>= 1)                                */
+  const void* uv;       /* device Real[M][2], user order                      */
+  const void* w;        /* device Real[M] or NULL (ones)                      */
+  const void* y;        /* device complex[M], user order                      */
+  pr_admm_params params;/* iters = outer iterations; rel_tol ignored; x0 = 0  */
+} pr_job_desc;
+/* uv, w and y must stay valid until the job is running (state >= 1). */
+
+/* Arena bytes the job occupies from admission until it is fetched. */
+int pr_server_job_bytes(const pr_job_desc* desc, size_t* bytes);
+/* arena: device memory of arena_bytes (256-byte aligned), owned by the
+ * caller, used by no one else while the server lives. */
+int pr_server_create(void* arena, size_t arena_bytes, int32_t max_active,
+                     int32_t nstreams, pr_server* out);
+int pr_server_destroy(pr_server s);
+/* Queue a request; fails with PR_EWORKSPACE if it can never fit the arena. */
+int pr_server_submit(pr_server s, const pr_job_desc* desc, int64_t* job_id);
+/* Retire finished jobs, admit queued ones, queue one outer iteration of each
+ * running job (at most two in flight per job). Blocks only while an admitted
+ * job's plan is built. Counts are optional. */
+int pr_server_tick(pr_server s, int32_t* queued, int32_t* running,
+                   int32_t* finished);
+/* state: 0 queued, 1 running, 2 finished, 3 failed. */
+int pr_server_job_state(pr_server s, int64_t job_id, int32_t* state,
+                        int32_t* iters_done);
+/* For a finished job: copy the image (real[n*n], normalised-operator units)
+ * to x_out (device, may be NULL), fill rep (may be NULL), synchronise
+ * `stream` and release the job's arena memory. */
+int pr_server_fetch(pr_server s, int64_t job_id, void* x_out,
+                    pr_admm_report* rep, void* stream);
+int pr_server_free_bytes(pr_server s, size_t* free_bytes, size_t* largest);
 
 #ifdef __cplusplus
 }

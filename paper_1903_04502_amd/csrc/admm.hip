@@ -9,7 +9,8 @@
 //   DualFB: d <- (1/eta) clip_gamma(eta d + Psi^dagger zbar) fused into the
 //     analysis stores; zbar = max(xt - Psi d, 0) fused into the synthesis sum
 // Phi enters divided by ||Phi|| (folded into the per-visibility weight scale).
-// Nothing is read back to the host unless a report or a tolerance asks for it.
+// The iterate is updated in place. Nothing is read back to the host unless a
+// report or a tolerance asks for it.
 #include <cmath>
 #include <cstring>
 
@@ -18,17 +19,7 @@
 
 namespace pr {
 
-struct AdmmWs {
-  void *s, *t, *d, *alpha, *xt, *zbar, *xb;
-  double* partials;
-  double* sums;
-};
-
 namespace {
-
-constexpr int kSumBall = 0;      // 0: ||t||^2, 1: ||v-y||^2, 2: kappa, 3: nonfinite
-constexpr int kSumVar = 8;       // 8: ||x_t - x_{t-1}||^2, 9: ||x_t||^2
-constexpr int kSumL1 = 12;
 
 template <typename R>
 __global__ void zero_kernel(R* a, int64_t len) {
@@ -36,6 +27,8 @@ __global__ void zero_kernel(R* a, int64_t len) {
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     a[i] = R(0);
 }
+
+__global__ void set_scalar_kernel(double* a, double v) { *a = v; }
 
 __global__ void zero_f64_kernel(double* a, int len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,7 +56,10 @@ int admm_check_params(const pr_admm_params* p) {
   if (p->iters < 0) { set_error("iters < 0"); return PR_EINVAL; }
   if (p->inner_iters < 1) { set_error("inner_iters < 1"); return PR_EINVAL; }
   if (!(p->eps >= 0)) { set_error("eps must be >= 0"); return PR_EINVAL; }
-  if (!(p->gamma > 0)) { set_error("gamma must be > 0"); return PR_EINVAL; }
+  if (!(p->gamma > 0) && !(p->gamma_factor > 0)) {
+    set_error("gamma must be > 0, or gamma <= 0 with gamma_factor > 0");
+    return PR_EINVAL;
+  }
   if (!(p->rho > 0) || !(p->varrho > 0) || !(p->eta > 0)) { set_error("rho, varrho, eta must be > 0"); return PR_EINVAL; }
   if (!(p->rel_tol >= 0)) { set_error("rel_tol must be >= 0"); return PR_EINVAL; }
   return PR_OK;
@@ -87,71 +83,115 @@ size_t admm_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws,
   return c.bytes();
 }
 
-int admm_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x, void* ws,
-               pr_admm_report* rep, hipStream_t s) {
-  AdmmWs w;
-  admm_layout(phi, psi, ws, &w);
-  const int prec = phi->prec;
-  const size_t rs = prec == PR_F32 ? 4 : 8;
+int admm_job_init(AdmmJob* j, pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, void* x, void* ws,
+                  const pr_admm_params& prm, hipStream_t s) {
+  j->phi = phi;
+  j->psi = psi;
+  j->y = y;
+  j->x = x;
+  j->prm = prm;
+  j->iters_done = 0;
+  j->device_scale = j->device_gamma = false;
+  j->scale = prm.op_norm > 0 ? 1.0 / prm.op_norm : 1.0;
+  admm_layout(phi, psi, ws, &j->w);
   const int64_t n2 = static_cast<int64_t>(phi->n) * phi->n;
-
-  double op_norm = prm.op_norm;
-  if (!(op_norm > 0)) PR_TRY(phi_norm(phi, 100, w.t, &op_norm, s));
-  const double scale = 1.0 / op_norm;
-
-  PR_TRY(zero_real(w.s, 2 * phi->M, prec, s));
-  PR_TRY(zero_real(w.d, psi->nb * n2, prec, s));
-  zero_f64_kernel<<<1, 32, 0, s>>>(w.sums, 32);
+  PR_TRY(zero_real(j->w.s, 2 * phi->M, phi->prec, s));
+  PR_TRY(zero_real(j->w.d, psi->nb * n2, phi->prec, s));
+  zero_f64_kernel<<<1, kSumSlots, 0, s>>>(j->w.sums, kSumSlots);
   PR_TRY_LAUNCH();
+  return PR_OK;
+}
 
+int admm_step(AdmmJob* j, hipStream_t s) {
+  pr_phi_plan_t* phi = j->phi;
+  pr_psi_plan_t* psi = j->psi;
+  const pr_admm_params& prm = j->prm;
+  AdmmWs& w = j->w;
   AdmmVis av{};
-  av.y = y;
+  av.y = j->y;
   av.s = w.s;
   av.t = w.t;
   av.sums = w.sums + kSumBall;
   av.eps = prm.eps;
   av.varrho = prm.varrho;
+  av.scale_dev = j->device_scale ? w.sums + kSumScale : nullptr;
+  const double* gamma_dev = j->device_gamma ? w.sums + kSumGamma : nullptr;
+  PR_TRY(phi_fzs(phi, j->x, s));
+  PR_TRY(phi_gw_admm(phi, av, j->scale, s));
+  PR_TRY(phi_gw_adjoint_admm(phi, av, j->scale, s));
+  PR_TRY(phi_fzs_adjoint_step(phi, j->x, prm.rho, w.xt, w.zbar, s));
+  for (int k = 0; k < prm.inner_iters; ++k) {
+    PR_TRY(psi_dual_update(psi, w.zbar, 0, w.d, prm.gamma, prm.eta, s, gamma_dev));
+    const bool last = k == prm.inner_iters - 1;
+    // the last synthesis writes the new iterate over x (read before written)
+    void* out = last ? j->x : w.zbar;
+    PR_TRY(psi_synthesis_step(psi, w.d, w.xt, out, last ? j->x : nullptr, w.partials, w.sums + kSumVar, s));
+  }
+  ++j->iters_done;
+  return PR_OK;
+}
 
-  void* xcur = x;        // current iterate
-  void* xnext = w.xb;    // receives the next iterate
-  int done = 0;
+int admm_report(AdmmJob* j, pr_admm_report* rep, hipStream_t s) {
+  pr_phi_plan_t* phi = j->phi;
+  pr_psi_plan_t* psi = j->psi;
+  const int64_t n2 = static_cast<int64_t>(phi->n) * phi->n;
+  double host_sums[kSumSlots] = {0};
+  PR_TRY(psi_analysis(psi, j->x, j->w.alpha, s));
+  PR_TRY(reduce_abssum(j->w.alpha, psi->nb * n2, phi->prec, j->w.partials, j->w.sums + kSumL1, s));
+  PR_TRY_HIP(hipMemcpyAsync(host_sums, j->w.sums, kSumSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));
+  rep->iters_done = j->iters_done;
+  rep->rel_var = host_sums[kSumVar + 1] > 0 ? std::sqrt(host_sums[kSumVar] / host_sums[kSumVar + 1]) : INFINITY;
+  rep->resid_norm = std::sqrt(host_sums[kSumBall + 1]);
+  rep->l1_norm = host_sums[kSumL1];
+  rep->op_norm = j->device_scale ? 1.0 / host_sums[kSumScale] : 1.0 / j->scale;
+  rep->nonfinite = (host_sums[kSumBall + 3] != 0 || !std::isfinite(rep->rel_var) || !std::isfinite(rep->l1_norm) ||
+                    !std::isfinite(rep->resid_norm))
+                       ? 1
+                       : 0;
+  return PR_OK;
+}
+
+int admm_device_setup(AdmmJob* j, hipStream_t s) {
+  pr_phi_plan_t* phi = j->phi;
+  const pr_admm_params& prm = j->prm;
+  const int64_t n2 = static_cast<int64_t>(phi->n) * phi->n;
+  double* inv = j->w.sums + kSumScale;
+  if (prm.op_norm > 0) {
+    set_scalar_kernel<<<1, 1, 0, s>>>(inv, 1.0 / prm.op_norm);
+    PR_TRY_LAUNCH();
+  } else {
+    PR_TRY(phi_norm_device(phi, prm.norm_iters > 0 ? prm.norm_iters : 100, j->w.t, inv, s));
+  }
+  j->device_scale = true;
+  if (!(prm.gamma > 0)) {
+    // gamma = factor * ||Psi^dagger Re Phi^dagger y||_inf / ||Phi|| (dirty image of the normalised operator)
+    PR_TRY(phi_gw_adjoint(phi, j->y, 1.0, s));
+    PR_TRY(phi_fzs_adjoint(phi, j->w.xt, s));
+    PR_TRY(psi_analysis(j->psi, j->w.xt, j->w.alpha, s));
+    PR_TRY(reduce_absmax_scaled(j->w.alpha, j->psi->nb * n2, phi->prec, prm.gamma_factor, inv, j->w.partials,
+                                j->w.sums + kSumGamma, s));
+    j->device_gamma = true;
+  }
+  return PR_OK;
+}
+
+int admm_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x, void* ws,
+               pr_admm_report* rep, hipStream_t s) {
+  AdmmJob j;
+  PR_TRY(admm_job_init(&j, phi, psi, y, x, ws, prm, s));
+  PR_TRY(admm_device_setup(&j, s));
   double host_sums[16] = {0};
   for (int it = 0; it < prm.iters; ++it) {
-    PR_TRY(phi_fzs(phi, xcur, s));
-    PR_TRY(phi_gw_admm(phi, av, scale, s));
-    PR_TRY(phi_gw_adjoint_admm(phi, av, scale, s));
-    PR_TRY(phi_fzs_adjoint_step(phi, xcur, prm.rho, w.xt, w.zbar, s));
-    for (int k = 0; k < prm.inner_iters; ++k) {
-      PR_TRY(psi_dual_update(psi, w.zbar, 0, w.d, prm.gamma, prm.eta, s));
-      const bool last = k == prm.inner_iters - 1;
-      void* out = last ? xnext : w.zbar;
-      PR_TRY(psi_synthesis_step(psi, w.d, w.xt, out, last ? xcur : nullptr, w.partials, w.sums + kSumVar, s));
-    }
-    std::swap(xcur, xnext);
-    ++done;
+    PR_TRY(admm_step(&j, s));
     if (prm.rel_tol > 0) {
-      PR_TRY_HIP(hipMemcpyAsync(host_sums, w.sums, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PR_TRY_HIP(hipMemcpyAsync(host_sums, j.w.sums, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
       PR_TRY_HIP(hipStreamSynchronize(s));
       const double rv = host_sums[kSumVar + 1] > 0 ? std::sqrt(host_sums[kSumVar] / host_sums[kSumVar + 1]) : INFINITY;
       if (rv < prm.rel_tol) break;
     }
   }
-  if (xcur != x) PR_TRY_HIP(hipMemcpyAsync(x, xcur, n2 * rs, hipMemcpyDeviceToDevice, s));
-  if (rep) {
-    PR_TRY(psi_analysis(psi, x, w.alpha, s));
-    PR_TRY(reduce_abssum(w.alpha, psi->nb * n2, prec, w.partials, w.sums + kSumL1, s));
-    PR_TRY_HIP(hipMemcpyAsync(host_sums, w.sums, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
-    PR_TRY_HIP(hipStreamSynchronize(s));
-    rep->iters_done = done;
-    rep->rel_var = host_sums[kSumVar + 1] > 0 ? std::sqrt(host_sums[kSumVar] / host_sums[kSumVar + 1]) : INFINITY;
-    rep->resid_norm = std::sqrt(host_sums[kSumBall + 1]);
-    rep->l1_norm = host_sums[kSumL1];
-    rep->op_norm = op_norm;
-    rep->nonfinite = (host_sums[kSumBall + 3] != 0 || !std::isfinite(rep->rel_var) || !std::isfinite(rep->l1_norm) ||
-                      !std::isfinite(rep->resid_norm))
-                         ? 1
-                         : 0;
-  }
+  if (rep) PR_TRY(admm_report(&j, rep, s));
   return PR_OK;
 }
 

@@ -27,27 +27,6 @@ void clear_error() { g_err[0] = '\0'; }
 
 using namespace pr;
 
-#define PR_NONNULL(ptr)                                  \
-  do {                                                   \
-    if (!(ptr)) {                                        \
-      set_error("%s: %s is NULL", __func__, #ptr);       \
-      return PR_EINVAL;                                  \
-    }                                                    \
-  } while (0)
-
-static hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
-
-// A kernel fault from earlier work is reported before new work is queued.
-static int check_sticky() {
-  hipError_t e = hipPeekAtLastError();
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("pending HIP error: %s", hipGetErrorString(e));
-    return PR_EHIP;
-  }
-  return PR_OK;
-}
-
 extern "C" {
 
 const char* pr_last_error(void) { return g_err; }
@@ -143,6 +122,21 @@ int pr_phi_gw_adjoint(pr_phi_plan plan, const void* y, void* stream) {
   if (plan->M > 0) PR_NONNULL(y);
   PR_TRY(check_sticky());
   return phi_gw_adjoint(plan, y, 1.0, as_stream(stream));
+}
+
+int pr_phi_grid_patches(pr_phi_plan plan, const void* y, void* stream) {
+  clear_error();
+  PR_NONNULL(plan);
+  if (plan->M > 0) PR_NONNULL(y);
+  PR_TRY(check_sticky());
+  return phi_gw_adjoint_parts(plan, y, 1.0, 1, as_stream(stream));
+}
+
+int pr_phi_grid_merge(pr_phi_plan plan, void* stream) {
+  clear_error();
+  PR_NONNULL(plan);
+  PR_TRY(check_sticky());
+  return phi_gw_adjoint_parts(plan, nullptr, 1.0, 2, as_stream(stream));
 }
 
 int pr_phi_fzs_adjoint(pr_phi_plan plan, void* x, void* stream) {

@@ -32,6 +32,27 @@ void clear_error();
     if (rc_ != PR_OK) return rc_; \
   } while (0)
 
+#define PR_NONNULL(ptr)                                  \
+  do {                                                   \
+    if (!(ptr)) {                                        \
+      ::pr::set_error("%s: %s is NULL", __func__, #ptr); \
+      return PR_EINVAL;                                  \
+    }                                                    \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// A kernel fault from earlier work is reported before new work is queued.
+inline int check_sticky() {
+  hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("pending HIP error: %s", hipGetErrorString(e));
+    return PR_EHIP;
+  }
+  return PR_OK;
+}
+
 // Bump allocator over a caller-provided workspace. With base == nullptr it
 // only measures, so size queries and carving share one code path.
 struct Carver {

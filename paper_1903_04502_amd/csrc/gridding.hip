@@ -17,6 +17,10 @@
 // The item's patch value at cell q is sum_{a,b} m[q - (a,b)][a][b]. Patches are
 // written per item and a merge kernel adds the up to four overlapping tile
 // patches of each grid cell, items in order.
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "phi.hpp"
 #include "taps.hpp"
 
@@ -828,11 +832,20 @@ int grid_blocks(const pr_phi_plan_t* p) {
   return static_cast<int>(p->nItems < kGridBlocks ? p->nItems : kGridBlocks);
 }
 
+// Raise a kernel's dynamic LDS limit to the full 160 KB, once per kernel and
+// device, so that launches (also under stream capture) set no attributes.
 template <typename K>
 int allow_lds(K kernel, size_t bytes) {
-  if (bytes > 65536)
-    PR_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)));
+  if (bytes <= 65536) return PR_OK;
+  static std::mutex mu;
+  static std::set<std::pair<int, const void*>> done;
+  int dev = 0;
+  PR_TRY_HIP(hipGetDevice(&dev));
+  const void* f = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({dev, f})) return PR_OK;
+  PR_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsHard)));
+  done.insert({dev, f});
   return PR_OK;
 }
 
@@ -882,12 +895,13 @@ bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
 }
 
 template <typename R, int J, int MODE>
-int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s) {
+int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) {
   using C = cx_t<R>;
   constexpr int JA = GridSplit<R, J>::JA;
   const int G = grid_blocks(p);
   bool walked = false;
-  if constexpr (J <= 4) {
+  if (!(parts & 1)) walked = true;   // patches not asked for
+  if constexpr (J <= 4) if (parts & 1) {
     // segment walk: table in LDS if both fit the two-blocks-per-CU budget
     const WalkLds<R, J> with(a.T, a.tlen, true), without(a.T, a.tlen, false);
     const bool tl = with.total <= kLdsSoft;
@@ -921,10 +935,43 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s) {
     }
   }
   PR_TRY_LAUNCH();
-  merge_patches_kernel<R><<<p->nTiles, p->T * p->T < kThreads ? p->T * p->T : kThreads, 0, s>>>(
-      static_cast<const C*>(p->patches), p->item_off, static_cast<C*>(p->grid), p->K, p->T, p->P, p->nT, p->J);
-  PR_TRY_LAUNCH();
+  if (parts & 2) {
+    merge_patches_kernel<R><<<p->nTiles, p->T * p->T < kThreads ? p->T * p->T : kThreads, 0, s>>>(
+        static_cast<const C*>(p->patches), p->item_off, static_cast<C*>(p->grid), p->K, p->T, p->P, p->nT, p->J);
+    PR_TRY_LAUNCH();
+  }
   return PR_OK;
+}
+
+template <typename R, int J, int MODE>
+int setup_mode() {
+  constexpr int JA = GridSplit<R, J>::JA;
+  PR_TRY(allow_lds(degrid_kernel<R, J, MODE, true>, kLdsHard));
+  PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false>, kLdsHard));
+  if constexpr (J <= 4) {
+    PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true>, kLdsHard));
+    PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false>, kLdsHard));
+  }
+  PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true>, kLdsHard));
+  PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false>, kLdsHard));
+  return PR_OK;
+}
+
+template <typename R, int J>
+int setup_kernels() {
+  PR_TRY((setup_mode<R, J, 0>()));
+  return setup_mode<R, J, 1>();
+}
+
+template <typename R>
+int setup_prec(int J) {
+  switch (J) {
+    case 2: return setup_kernels<R, 2>();
+    case 4: return setup_kernels<R, 4>();
+    case 6: return setup_kernels<R, 6>();
+    case 8: return setup_kernels<R, 8>();
+    default: set_error("J = %d unsupported", J); return PR_EUNSUPPORTED;
+  }
 }
 
 template <typename R>
@@ -1006,10 +1053,10 @@ int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
 }
 
 template <typename R>
-int gwadj_plain(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s) {
+int gwadj_plain(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s, int parts) {
   GwAdjArgs<R> a = gwadj_args<R>(p, scale);
   a.y_in = static_cast<const cx_t<R>*>(y);
-#define CALL(JJ) launch_grid<R, JJ, 0>(p, a, s)
+#define CALL(JJ) launch_grid<R, JJ, 0>(p, a, s, parts)
   PR_DISPATCH_J(p->J, CALL)
 #undef CALL
 }
@@ -1036,13 +1083,22 @@ __global__ void zero_cx_kernel(cx_t<R>* a, int64_t n) {
 
 }  // namespace
 
+int phi_gridding_setup(pr_phi_plan_t* p) {
+  return p->prec == PR_F32 ? setup_prec<float>(p->J) : setup_prec<double>(p->J);
+}
+
 int phi_gw(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {
   if (p->M == 0) return PR_OK;
   return p->prec == PR_F32 ? gw_plain<float>(p, y, scale, s) : gw_plain<double>(p, y, scale, s);
 }
 
 int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s) {
+  return phi_gw_adjoint_parts(p, y, scale, 3, s);
+}
+
+int phi_gw_adjoint_parts(pr_phi_plan_t* p, const void* y, double scale, int parts, hipStream_t s) {
   if (p->nItems == 0) {
+    if (!(parts & 2)) return PR_OK;
     const int64_t K2 = static_cast<int64_t>(p->K) * p->K;
     if (p->prec == PR_F32)
       zero_cx_kernel<float><<<grid_for(K2, 256, 4096), 256, 0, s>>>(static_cast<float2*>(p->grid), K2);
@@ -1051,7 +1107,7 @@ int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s)
     PR_TRY_LAUNCH();
     return PR_OK;
   }
-  return p->prec == PR_F32 ? gwadj_plain<float>(p, y, scale, s) : gwadj_plain<double>(p, y, scale, s);
+  return p->prec == PR_F32 ? gwadj_plain<float>(p, y, scale, s, parts) : gwadj_plain<double>(p, y, scale, s, parts);
 }
 
 int phi_gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {

@@ -57,6 +57,39 @@ __global__ void abssum_stage1(const R* a, int64_t len, double* partials) {
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
+template <typename R>
+__global__ void absmax_stage1(const R* a, int64_t len, double* partials) {
+  __shared__ double sh[kThreads];
+  double m = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    m = fmax(m, fabs(static_cast<double>(a[i])));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+// *out = scale_factor * max(partials) * (*mul) (mul may be null)
+__global__ void max_stage2(const double* partials, int n, double factor, const double* mul, double* out) {
+  __shared__ double sh[kThreads];
+  double m = 0;
+  for (int i = threadIdx.x; i < n; i += kThreads) m = fmax(m, partials[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = factor * sh[0] * (mul ? *mul : 1.0);
+}
+
+// *inv = 1 / ||Phi|| from the power method's ||A x||^2 (A = Phi^dagger Phi)
+__global__ void inv_norm_kernel(const double* s2, double* inv) { *inv = 1.0 / sqrt(sqrt(*s2)); }
+
 __global__ void sum_stage2(const double* partials, int n, double* out, double* nonfinite_flag) {
   __shared__ double sh[kThreads];
   double acc = 0;
@@ -109,6 +142,19 @@ int reduce_sumsq(const void* a, const void* b, int64_t len, int prec, double* pa
                                                 partials);
   PR_TRY_LAUNCH();
   sum_stage2<<<1, kThreads, 0, s>>>(partials, G, out, nonfinite_flag);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int reduce_absmax_scaled(const void* a, int64_t len, int prec, double factor, const double* mul, double* partials,
+                         double* out, hipStream_t s) {
+  const int G = grid_for(len, kThreads, kRedBlocks);
+  if (prec == PR_F32)
+    absmax_stage1<float><<<G, kThreads, 0, s>>>(static_cast<const float*>(a), len, partials);
+  else
+    absmax_stage1<double><<<G, kThreads, 0, s>>>(static_cast<const double*>(a), len, partials);
+  PR_TRY_LAUNCH();
+  max_stage2<<<1, kThreads, 0, s>>>(partials, G, factor, mul, out);
   PR_TRY_LAUNCH();
   return PR_OK;
 }
@@ -191,6 +237,23 @@ int normalise(void* a, const void* b, int64_t len, int prec, const double* s2, h
     normalise_kernel<float><<<G, kThreads, 0, s>>>(static_cast<float*>(a), static_cast<const float*>(b), len, s2);
   else
     normalise_kernel<double><<<G, kThreads, 0, s>>>(static_cast<double*>(a), static_cast<const double*>(b), len, s2);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int phi_norm_device(pr_phi_plan_t* p, int iters, void* vis, double* inv_norm, hipStream_t s) {
+  const int64_t N = static_cast<int64_t>(p->n) * p->n;
+  double* s2 = p->scalars + 8;
+  PR_TRY(fill_real(p->img_a, N, p->prec, 1.0 / p->n, s));
+  for (int it = 0; it < iters; ++it) {
+    PR_TRY(phi_fzs(p, p->img_a, s));
+    PR_TRY(phi_gw(p, vis, 1.0, s));
+    PR_TRY(phi_gw_adjoint(p, vis, 1.0, s));
+    PR_TRY(phi_fzs_adjoint(p, p->img_b, s));
+    PR_TRY(reduce_sumsq(p->img_b, nullptr, N, p->prec, p->partials, s2, s, nullptr));
+    PR_TRY(normalise(p->img_a, p->img_b, N, p->prec, s2, s));
+  }
+  inv_norm_kernel<<<1, 1, 0, s>>>(s2, inv_norm);
   PR_TRY_LAUNCH();
   return PR_OK;
 }

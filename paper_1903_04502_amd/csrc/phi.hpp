@@ -50,12 +50,18 @@ int phi_validate(const pr_phi_desc* d);
 // Geometry (sizes, tile, kernel shape) from a validated descriptor.
 int phi_prepare(pr_phi_plan_t* p, const pr_phi_desc* d);
 int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s);
+// Set the LDS limits of the plan's gridding kernels (once per process and
+// device), so that later launches, also under stream capture, set nothing.
+int phi_gridding_setup(pr_phi_plan_t* p);
 
 // Operator stages.
 int phi_fzs(pr_phi_plan_t* p, const void* x, hipStream_t s);
 int phi_fzs_adjoint(pr_phi_plan_t* p, void* x, hipStream_t s);
 int phi_gw(pr_phi_plan_t* p, void* y, double scale, hipStream_t s);
 int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s);
+// The two launches of phi_gw_adjoint: parts bit 0 = per-item patches from the
+// visibilities, bit 1 = merge of the patches into the grid.
+int phi_gw_adjoint_parts(pr_phi_plan_t* p, const void* y, double scale, int parts, hipStream_t s);
 int phi_norm(pr_phi_plan_t* p, int iters, void* vis, double* norm, hipStream_t s);
 
 // Fused ADMM stages (defined with the operator kernels).

@@ -470,6 +470,7 @@ static int create_impl(pr_phi_plan_t* p, const R* uv, const R* w, hipStream_t s)
 }
 
 int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s) {
+  PR_TRY(phi_gridding_setup(p));
   if (p->prec == PR_F32)
     return create_impl<float>(p, static_cast<const float*>(uv), static_cast<const float*>(w), s);
   return create_impl<double>(p, static_cast<const double*>(uv), static_cast<const double*>(w), s);

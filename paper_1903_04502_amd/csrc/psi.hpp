@@ -40,10 +40,12 @@ int psi_synthesis(pr_psi_plan_t* p, const void* alpha, void* x, hipStream_t s);
 // DualFB steps of Algorithm 1 (fused forms used by the solver):
 // d <- (1/eta) clip_gamma(eta d + Psi^dagger zbar), with zbar = max(z, 0) on
 // load when `positive_in` is set.
+// gamma_dev, when set, holds gamma in device memory and overrides `gamma`.
 int psi_dual_update(pr_psi_plan_t* p, const void* zbar, int positive_in, void* d, double gamma, double eta,
-                    hipStream_t s);
+                    hipStream_t s, const double* gamma_dev = nullptr);
 // zbar = max(z - Psi d, 0); optional FP64 partials of ||zbar - xprev||^2 and
-// ||zbar||^2 into sums[0], sums[1] (device) when xprev is not null.
+// ||zbar||^2 into sums[0], sums[1] (device) when xprev is not null. zbar may
+// be xprev (the iterate updated in place).
 int psi_synthesis_step(pr_psi_plan_t* p, const void* d, const void* z, void* zbar, const void* xprev,
                        double* partials, double* sums, hipStream_t s);
 

@@ -67,7 +67,8 @@ __global__ void dwt_rows_kernel(const R* __restrict__ src, int64_t src_basis_str
 template <typename R, int MODE>
 __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, int n, R* __restrict__ ll_out,
                                 int last, R* __restrict__ coef, const Filt<R>* __restrict__ filt, R scale,
-                                R gamma, R eta) {
+                                R gamma_h, const double* __restrict__ gamma_dev, R eta) {
+  const R gamma = (MODE == 1 && gamma_dev) ? static_cast<R>(*gamma_dev) : gamma_h;
   const int bi = blockIdx.y;
   const Filt<R>& f = filt[bi];
   const R* in = rows + bi * n2;
@@ -102,8 +103,9 @@ __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, i
 }
 
 template <typename R, int MODE>
-__global__ void dirac_analysis_kernel(const R* __restrict__ x, R* __restrict__ coef, int64_t n2, R scale, R gamma,
-                                      R eta) {
+__global__ void dirac_analysis_kernel(const R* __restrict__ x, R* __restrict__ coef, int64_t n2, R scale, R gamma_h,
+                                      const double* __restrict__ gamma_dev, R eta) {
+  const R gamma = (MODE == 1 && gamma_dev) ? static_cast<R>(*gamma_dev) : gamma_h;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n2;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
     if (MODE == 0) coef[i] = x[i] * scale;
@@ -171,8 +173,7 @@ __global__ void idwt_rows_kernel(const R* __restrict__ rows, int64_t n2, int L, 
 // of ||zbar - xprev||^2 and ||zbar||^2 when xprev is given.
 template <typename R, int MODE>
 __global__ void combine_kernel(const R* __restrict__ dirac, const R* __restrict__ recon, int ndb, int64_t n2, R scale,
-                               const R* __restrict__ z, R* __restrict__ out, const R* __restrict__ xprev,
-                               double* __restrict__ partials) {
+                               const R* __restrict__ z, R* out, const R* xprev, double* __restrict__ partials) {
   __shared__ double sh[kThreads];
   double dd = 0, xx = 0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n2;
@@ -183,11 +184,13 @@ __global__ void combine_kernel(const R* __restrict__ dirac, const R* __restrict_
     if (MODE == 0) {
       out[i] = acc;
     } else {
+      // out may be xprev (in-place iterate): read before the store
+      const R xp = xprev ? xprev[i] : R(0);
       const R v = z[i] - acc;
       const R zb = v > R(0) ? v : R(0);
       out[i] = zb;
       if (xprev) {
-        const double df = static_cast<double>(zb) - static_cast<double>(xprev[i]);
+        const double df = static_cast<double>(zb) - static_cast<double>(xp);
         dd += df * df;
         xx += static_cast<double>(zb) * zb;
       }
@@ -219,7 +222,8 @@ __global__ void combine_finish_kernel(const double* partials, int nblocks, doubl
 }
 
 template <typename R>
-int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma, double eta, hipStream_t s) {
+int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma, const double* gamma_dev, double eta,
+                  hipStream_t s) {
   const int n = p->n;
   const int64_t n2 = static_cast<int64_t>(n) * n;
   const R scale = static_cast<R>(p->scale);
@@ -227,9 +231,9 @@ int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma,
   if (p->has_dirac) {
     const int G = grid_for(n2, kThreads, 4096);
     if (mode == 0)
-      dirac_analysis_kernel<R, 0><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), R(eta));
+      dirac_analysis_kernel<R, 0><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), gamma_dev, R(eta));
     else
-      dirac_analysis_kernel<R, 1><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), R(eta));
+      dirac_analysis_kernel<R, 1><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), gamma_dev, R(eta));
     PR_TRY_LAUNCH();
   }
   if (p->ndb == 0) return PR_OK;
@@ -249,9 +253,9 @@ int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma,
     const int last = lev == p->levels;
     R* llout = last ? nullptr : (lev & 1 ? lla : llb);
     if (mode == 0)
-      dwt_cols_kernel<R, 0><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), R(eta));
+      dwt_cols_kernel<R, 0><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev, R(eta));
     else
-      dwt_cols_kernel<R, 1><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), R(eta));
+      dwt_cols_kernel<R, 1><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev, R(eta));
     PR_TRY_LAUNCH();
   }
   return PR_OK;
@@ -381,8 +385,8 @@ int psi_create(pr_psi_plan_t* p, hipStream_t s) {
 
 int psi_analysis(pr_psi_plan_t* p, const void* x, void* alpha, hipStream_t s) {
   if (p->prec == PR_F32)
-    return analysis_impl<float>(p, static_cast<const float*>(x), static_cast<float*>(alpha), 0, 0, 1, s);
-  return analysis_impl<double>(p, static_cast<const double*>(x), static_cast<double*>(alpha), 0, 0, 1, s);
+    return analysis_impl<float>(p, static_cast<const float*>(x), static_cast<float*>(alpha), 0, 0, nullptr, 1, s);
+  return analysis_impl<double>(p, static_cast<const double*>(x), static_cast<double*>(alpha), 0, 0, nullptr, 1, s);
 }
 
 int psi_synthesis(pr_psi_plan_t* p, const void* alpha, void* x, hipStream_t s) {
@@ -391,11 +395,12 @@ int psi_synthesis(pr_psi_plan_t* p, const void* alpha, void* x, hipStream_t s) {
 }
 
 int psi_dual_update(pr_psi_plan_t* p, const void* zbar, int positive_in, void* d, double gamma, double eta,
-                    hipStream_t s) {
+                    hipStream_t s, const double* gamma_dev) {
   (void)positive_in;
   if (p->prec == PR_F32)
-    return analysis_impl<float>(p, static_cast<const float*>(zbar), static_cast<float*>(d), 1, gamma, eta, s);
-  return analysis_impl<double>(p, static_cast<const double*>(zbar), static_cast<double*>(d), 1, gamma, eta, s);
+    return analysis_impl<float>(p, static_cast<const float*>(zbar), static_cast<float*>(d), 1, gamma, gamma_dev, eta, s);
+  return analysis_impl<double>(p, static_cast<const double*>(zbar), static_cast<double*>(d), 1, gamma, gamma_dev, eta,
+                               s);
 }
 
 int psi_synthesis_step(pr_psi_plan_t* p, const void* d, const void* z, void* zbar, const void* xprev,

@@ -37,12 +37,19 @@ class pr_phi_desc(C.Structure):
 class pr_admm_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("inner_iters", C.c_int32), ("eps", C.c_double),
                 ("gamma", C.c_double), ("rho", C.c_double), ("varrho", C.c_double),
-                ("eta", C.c_double), ("rel_tol", C.c_double), ("op_norm", C.c_double)]
+                ("eta", C.c_double), ("rel_tol", C.c_double), ("op_norm", C.c_double),
+                ("gamma_factor", C.c_double), ("norm_iters", C.c_int32)]
 
 
 class pr_admm_report(C.Structure):
     _fields_ = [("iters_done", C.c_int32), ("rel_var", C.c_double), ("resid_norm", C.c_double),
                 ("l1_norm", C.c_double), ("op_norm", C.c_double), ("nonfinite", C.c_int32)]
+
+
+class pr_job_desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("J", C.c_int32), ("D", C.c_int32), ("tile", C.c_int32),
+                ("levels", C.c_int32), ("basis_mask", C.c_uint32), ("prec", C.c_int32), ("M", C.c_int64),
+                ("uv", C.c_void_p), ("w", C.c_void_p), ("y", C.c_void_p), ("params", pr_admm_params)]
 
 
 _VP, _I32, _I64, _U32, _D, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double, C.c_size_t
@@ -61,6 +68,8 @@ _SIGS = {
     "pr_phi_gw": (C.c_int, [_VP, _VP, _VP]),
     "pr_phi_gw_adjoint": (C.c_int, [_VP, _VP, _VP]),
     "pr_phi_fzs_adjoint": (C.c_int, [_VP, _VP, _VP]),
+    "pr_phi_grid_patches": (C.c_int, [_VP, _VP, _VP]),
+    "pr_phi_grid_merge": (C.c_int, [_VP, _VP]),
     "pr_phi_norm": (C.c_int, [_VP, _I32, _VP, C.POINTER(_D), _VP]),
     "pr_psi_plan_sizes": (C.c_int, [_I32, _I32, _U32, _I32, C.POINTER(_SZ), C.POINTER(_SZ)]),
     "pr_psi_plan_create": (C.c_int, [_I32, _I32, _U32, _I32, _VP, _VP, _VP, C.POINTER(_VP)]),
@@ -75,6 +84,25 @@ _SIGS = {
     "pr_admm_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
     "pr_admm_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_admm_params), _VP, _VP,
                                 C.POINTER(pr_admm_report), _VP]),
+    "pr_phi_tune": (C.c_int, [C.POINTER(pr_phi_desc), _VP, _VP, _VP, _VP, _VP, _I32, _VP, C.POINTER(_I32),
+                              C.POINTER(_D)]),
+    "pr_batch_create": (C.c_int, [_I32, _I32, C.POINTER(_VP)]),
+    "pr_batch_destroy": (C.c_int, [_VP]),
+    "pr_batch_add": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(pr_admm_params), _VP, _VP, C.POINTER(_I32)]),
+    "pr_batch_remove": (C.c_int, [_VP, _I32]),
+    "pr_batch_members": (C.c_int, [_VP, C.POINTER(_I32)]),
+    "pr_batch_step": (C.c_int, [_VP, _I32, _I32, _VP]),
+    "pr_batch_phi_apply": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), _VP]),
+    "pr_batch_phi_adjoint": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), _VP]),
+    "pr_batch_report": (C.c_int, [_VP, _I32, C.POINTER(pr_admm_report), _VP]),
+    "pr_server_job_bytes": (C.c_int, [C.POINTER(pr_job_desc), C.POINTER(_SZ)]),
+    "pr_server_create": (C.c_int, [_VP, _SZ, _I32, _I32, C.POINTER(_VP)]),
+    "pr_server_destroy": (C.c_int, [_VP]),
+    "pr_server_submit": (C.c_int, [_VP, C.POINTER(pr_job_desc), C.POINTER(_I64)]),
+    "pr_server_tick": (C.c_int, [_VP, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32)]),
+    "pr_server_job_state": (C.c_int, [_VP, _I64, C.POINTER(_I32), C.POINTER(_I32)]),
+    "pr_server_fetch": (C.c_int, [_VP, _I64, _VP, C.POINTER(pr_admm_report), _VP]),
+    "pr_server_free_bytes": (C.c_int, [_VP, C.POINTER(_SZ), C.POINTER(_SZ)]),
 }
 
 _lib = None
@@ -192,6 +220,14 @@ def pr_phi_fzs_adjoint(plan, x, stream=None):
     _check(lib().pr_phi_fzs_adjoint(plan, _ptr(x), stream if stream is not None else _stream()))
 
 
+def pr_phi_grid_patches(plan, y, stream=None):
+    _check(lib().pr_phi_grid_patches(plan, _ptr(y), stream if stream is not None else _stream()))
+
+
+def pr_phi_grid_merge(plan, stream=None):
+    _check(lib().pr_phi_grid_merge(plan, stream if stream is not None else _stream()))
+
+
 def pr_phi_norm(plan, iters, vis_ws, stream=None) -> float:
     v = _D()
     _check(lib().pr_phi_norm(plan, iters, _ptr(vis_ws), C.byref(v), stream if stream is not None else _stream()))
@@ -266,6 +302,116 @@ def pr_admm_solve(phi, psi, y, params: pr_admm_params, x, workspace, want_report
     return rep if want_report else None
 
 
+def pr_phi_tune(desc: pr_phi_desc, uv, w, persistent, scratch, vis_ws, reps=3, stream=None):
+    t, ms = _I32(), _D()
+    _check(lib().pr_phi_tune(C.byref(desc), _ptr(uv), _ptr(w), _ptr(persistent), _ptr(scratch), _ptr(vis_ws),
+                             reps, stream if stream is not None else _stream(), C.byref(t), C.byref(ms)))
+    return t.value, ms.value
+
+
+def pr_batch_create(max_members: int, nstreams: int):
+    h = _VP()
+    _check(lib().pr_batch_create(max_members, nstreams, C.byref(h)))
+    return h.value
+
+
+def pr_batch_destroy(b):
+    _check(lib().pr_batch_destroy(b))
+
+
+def pr_batch_add(b, phi, psi, y, x, params: pr_admm_params, workspace, stream=None) -> int:
+    slot = _I32()
+    _check(lib().pr_batch_add(b, phi, psi, _ptr(y), _ptr(x), C.byref(params), _ptr(workspace),
+                              stream if stream is not None else _stream(), C.byref(slot)))
+    return slot.value
+
+
+def pr_batch_remove(b, slot: int):
+    _check(lib().pr_batch_remove(b, slot))
+
+
+def pr_batch_members(b) -> int:
+    c = _I32()
+    _check(lib().pr_batch_members(b, C.byref(c)))
+    return c.value
+
+
+def pr_batch_step(b, iters: int, use_graph: bool = True, stream=None):
+    _check(lib().pr_batch_step(b, iters, 1 if use_graph else 0, stream if stream is not None else _stream()))
+
+
+def _ptr_array(ts, n):
+    arr = (_VP * n)()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t)
+    return arr
+
+
+def pr_batch_phi_apply(b, xs, ys, stream=None):
+    n = max(len(xs), len(ys))
+    _check(lib().pr_batch_phi_apply(b, _ptr_array(xs, n), _ptr_array(ys, n),
+                                    stream if stream is not None else _stream()))
+
+
+def pr_batch_phi_adjoint(b, ys, xs, stream=None):
+    n = max(len(xs), len(ys))
+    _check(lib().pr_batch_phi_adjoint(b, _ptr_array(ys, n), _ptr_array(xs, n),
+                                      stream if stream is not None else _stream()))
+
+
+def pr_batch_report(b, slot: int, stream=None) -> pr_admm_report:
+    rep = pr_admm_report()
+    _check(lib().pr_batch_report(b, slot, C.byref(rep), stream if stream is not None else _stream()))
+    return rep
+
+
+def pr_server_job_bytes(desc: pr_job_desc) -> int:
+    v = _SZ()
+    _check(lib().pr_server_job_bytes(C.byref(desc), C.byref(v)))
+    return v.value
+
+
+def pr_server_create(arena, arena_bytes: int, max_active: int, nstreams: int):
+    h = _VP()
+    _check(lib().pr_server_create(_ptr(arena), arena_bytes, max_active, nstreams, C.byref(h)))
+    return h.value
+
+
+def pr_server_destroy(srv):
+    _check(lib().pr_server_destroy(srv))
+
+
+def pr_server_submit(srv, desc: pr_job_desc) -> int:
+    jid = _I64()
+    _check(lib().pr_server_submit(srv, C.byref(desc), C.byref(jid)))
+    return jid.value
+
+
+def pr_server_tick(srv):
+    q, r, f = _I32(), _I32(), _I32()
+    _check(lib().pr_server_tick(srv, C.byref(q), C.byref(r), C.byref(f)))
+    return q.value, r.value, f.value
+
+
+def pr_server_job_state(srv, job_id: int):
+    st, it = _I32(), _I32()
+    _check(lib().pr_server_job_state(srv, job_id, C.byref(st), C.byref(it)))
+    return st.value, it.value
+
+
+def pr_server_fetch(srv, job_id: int, x_out=None, want_report=True, stream=None):
+    rep = pr_admm_report()
+    _check(lib().pr_server_fetch(srv, job_id, _ptr(x_out), C.byref(rep) if want_report else None,
+                                 stream if stream is not None else _stream()))
+    return rep if want_report else None
+
+
+def pr_server_free_bytes(srv):
+    f, l = _SZ(), _SZ()
+    _check(lib().pr_server_free_bytes(srv, C.byref(f), C.byref(l)))
+    return f.value, l.value
+
+
 # --------------------------------------------------------------------------
 # plan holders: workspaces are torch tensors on the plan's device
 # --------------------------------------------------------------------------
@@ -274,8 +420,29 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def tune_tile(n, uv, w=None, J=4, D=2000, oversample=2, prec=None, reps=3) -> int:
+    """Fastest tile side for these baselines, measured by pr_phi_tune."""
+    dev = uv.device
+    prec = _prec_of(uv.dtype) if prec is None else prec
+    M = uv.shape[0]
+    pb = sb = 0
+    for T in (8, 16, 32):
+        try:
+            p, s_ = pr_phi_plan_sizes(pr_phi_desc(n, oversample, J, D, M, prec, T))
+        except PrError:
+            continue
+        pb, sb = max(pb, p), max(sb, s_)
+    cdt = torch.complex64 if prec == PR_F32 else torch.complex128
+    vis = torch.empty(max(M, 1), dtype=cdt, device=dev)
+    t, _ = pr_phi_tune(pr_phi_desc(n, oversample, J, D, M, prec, 0), uv.contiguous(),
+                       None if w is None else w.contiguous(), _workspace(pb, dev), _workspace(sb, dev), vis, reps,
+                       _stream(dev))
+    return t
+
+
 class PhiPlan:
-    """Measurement operator plan for one set of baselines (see pr_phi_plan_create)."""
+    """Measurement operator plan for one set of baselines (see pr_phi_plan_create).
+    tile: 0 = the library default, "auto" = measured by the autotuner."""
 
     def __init__(self, n, uv, w=None, J=4, D=2000, oversample=2, tile=0, prec=None):
         dev = uv.device
@@ -283,6 +450,8 @@ class PhiPlan:
         self.rdtype = torch.float32 if self.prec == PR_F32 else torch.float64
         self.cdtype = torch.complex64 if self.prec == PR_F32 else torch.complex128
         M = uv.shape[0]
+        if tile == "auto":
+            tile = tune_tile(n, uv, w, J, D, oversample, self.prec)
         self.desc = pr_phi_desc(n, oversample, J, D, M, self.prec, tile)
         self.n, self.M, self.device = n, M, dev
         pb, sb = pr_phi_plan_sizes(self.desc)
@@ -350,8 +519,10 @@ class PsiPlan:
             self.handle = None
 
 
-def admm_params(eps, gamma, iters=50, inner_iters=1, rho=0.5, varrho=1.0, eta=1.0, rel_tol=0.0, op_norm=0.0):
-    return pr_admm_params(iters, inner_iters, eps, gamma, rho, varrho, eta, rel_tol, op_norm)
+def admm_params(eps, gamma, iters=50, inner_iters=1, rho=0.5, varrho=1.0, eta=1.0, rel_tol=0.0, op_norm=0.0,
+                gamma_factor=0.0, norm_iters=0):
+    return pr_admm_params(iters, inner_iters, eps, gamma, rho, varrho, eta, rel_tol, op_norm, gamma_factor,
+                          norm_iters)
 
 
 def admm_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_admm_params, x0=None, want_report=True):
@@ -360,3 +531,79 @@ def admm_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_admm_params, x0=None, w
     x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
     rep = pr_admm_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
     return x, rep
+
+
+class Batch:
+    """Independent solves stepped together (see pr_batch_create). Keeps the
+    members' plans, data and workspaces alive while they are members."""
+
+    def __init__(self, max_members=64, nstreams=4):
+        self.handle = pr_batch_create(max_members, nstreams)
+        self.max_members = max_members
+        self._keep = {}
+
+    def add(self, phi: PhiPlan, psi: PsiPlan, y, params: pr_admm_params, x0=None) -> int:
+        ws = _workspace(pr_admm_workspace_size(phi.handle, psi.handle), phi.device)
+        x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
+        slot = pr_batch_add(self.handle, phi.handle, psi.handle, y, x, params, ws)
+        self._keep[slot] = (phi, psi, y, x, ws)
+        return slot
+
+    def x(self, slot: int):
+        return self._keep[slot][3]
+
+    def remove(self, slot: int):
+        pr_batch_remove(self.handle, slot)
+        self._keep.pop(slot, None)
+
+    def step(self, iters=1, use_graph=True):
+        pr_batch_step(self.handle, iters, use_graph)
+
+    def report(self, slot: int) -> pr_admm_report:
+        return pr_batch_report(self.handle, slot)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.pr_batch_destroy(h)
+            self.handle = None
+
+
+def job_desc(n, uv, y, params: pr_admm_params, w=None, J=4, D=2000, levels=3, mask=0x1FF, tile=0) -> pr_job_desc:
+    prec = _prec_of(uv.dtype)
+    return pr_job_desc(n, J, D, tile, levels, mask, prec, uv.shape[0], _ptr(uv), _ptr(w), _ptr(y), params)
+
+
+class Server:
+    """Continuous-batching request loop (see pr_server_create); the arena is
+    one device tensor owned by this object."""
+
+    def __init__(self, arena_bytes, max_active=64, nstreams=4, device="cuda"):
+        self.arena = _workspace(arena_bytes, torch.device(device))
+        self.handle = pr_server_create(self.arena, int(arena_bytes), max_active, nstreams)
+        self._inputs = {}
+
+    def submit(self, desc: pr_job_desc, keep=()) -> int:
+        jid = pr_server_submit(self.handle, desc)
+        self._inputs[jid] = keep          # uv / w / y tensors, alive until admission
+        return jid
+
+    def tick(self):
+        q, r, f = pr_server_tick(self.handle)
+        for jid in [j for j in self._inputs if pr_server_job_state(self.handle, j)[0] >= 1]:
+            self._inputs.pop(jid)
+        return q, r, f
+
+    def state(self, jid: int) -> int:
+        return pr_server_job_state(self.handle, jid)[0]
+
+    def fetch(self, jid: int, n: int, dtype=torch.float32, want_report=True):
+        x = torch.empty((n, n), dtype=dtype, device=self.arena.device)
+        rep = pr_server_fetch(self.handle, jid, x, want_report)
+        return x, rep
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.pr_server_destroy(h)
+            self.handle = None
