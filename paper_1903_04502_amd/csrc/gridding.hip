@@ -498,7 +498,10 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
 // LDS: kernel table (optional), moments [J*J][T*T] (entry-major), one region
 // holding either a staged chunk (u, v and the weighted value of WC positions
 // per thread, lane-transposed) or the side slots [J*J][kThreads], and the
-// first/last base cell per thread.
+// first/last base cell per thread. With the table in LDS the cell lists
+// borrow the table's first 2 KB after the walk (the epilogue reads no taps)
+// and that part of the table is reloaded before the next item's walk: this
+// keeps a 16 x 16 tile with its table within half of the 160 KB.
 // Positions per thread and staged chunk: FP32 8, FP64 4 (the prefetch
 // registers hold one chunk).
 template <typename R> struct WalkChunk { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
@@ -506,17 +509,27 @@ template <typename R> struct WalkChunk { static constexpr int value = sizeof(R) 
 template <typename R, int J>
 struct WalkLds {
   size_t tab, mom, stage, fcell, lcell, total;
+  int borrow;   // table entries under the cell lists (0: lists have their own space)
   __host__ __device__ WalkLds(int T, int tlen, bool tab_lds) {
     using C = cx_t<R>;
     constexpr int WC = WalkChunk<R>::value;
+    const size_t lists = 2 * align16(static_cast<size_t>(kThreads) * sizeof(int));
+    const size_t tab_bytes = tab_lds ? align16(static_cast<size_t>(tlen) * sizeof(R)) : 0;
     size_t o = 0;
-    tab = o;   o += tab_lds ? align16(static_cast<size_t>(tlen) * sizeof(R)) : 0;
+    tab = o;   o += tab_bytes;
     mom = o;   o += align16(static_cast<size_t>(T) * T * J * J * sizeof(C));
     const size_t staged = align16(static_cast<size_t>(kThreads) * WC * 2 * sizeof(C));
     const size_t sides = align16(static_cast<size_t>(kThreads) * J * J * sizeof(C));
     stage = o; o += staged > sides ? staged : sides;
-    fcell = o; o += align16(static_cast<size_t>(kThreads) * sizeof(int));
-    lcell = o; o += align16(static_cast<size_t>(kThreads) * sizeof(int));
+    if (tab_bytes >= lists) {
+      fcell = tab;
+      borrow = static_cast<int>(lists / sizeof(R));
+    } else {
+      fcell = o;
+      o += lists;
+      borrow = 0;
+    }
+    lcell = fcell + lists / 2;
     total = o;
   }
 };
@@ -703,6 +716,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         }
       }
     }
+    if (TAB_LDS && lay.borrow) __syncthreads();   // every walk done with the table head
     fcell[tid] = first;
     lcell[tid] = cur;
     __syncthreads();   // staging consumed; first and last cells published
@@ -720,7 +734,11 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     if (owner) {
       while (jend < kThreads && fcell[jend] == cur && lcell[jend] == cur) ++jend;
     }
-    __syncthreads();   // side slots written
+    __syncthreads();   // side slots written; cell lists no longer read
+    if (TAB_LDS && lay.borrow) {
+      R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
+      for (int i = tid; i < lay.borrow; i += kThreads) t[i] = a.table[i];
+    }
     if (owner) {
       for (int j = tid + 1; j < jend; ++j) {
 #pragma unroll
@@ -743,18 +761,27 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     const float invP = 1.0f / P;
     for (int pc = tid; pc < P * P; pc += kThreads) {
       const int pv = small_div(pc, P, invP), pu = pc - pv * P;
+      // every load in range (clamped), out-of-tile base cells masked: the
+      // J^2 loads issue together
+      C m[JJ];
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        const int cv = min(max(pv - b, 0), T - 1);
+#pragma unroll
+        for (int qq = 0; qq < J; ++qq) {
+          const int cu = min(max(pu - qq, 0), T - 1);
+          m[b * J + qq] = mom[(qq * J + b) * TT + cv * T + cu];
+        }
+      }
       R sr2 = 0, si2 = 0;
 #pragma unroll
       for (int b = 0; b < J; ++b) {
-        const int cv = pv - b;
-        if (cv < 0 || cv >= T) continue;
+        const bool okv = static_cast<unsigned>(pv - b) < static_cast<unsigned>(T);
 #pragma unroll
         for (int qq = 0; qq < J; ++qq) {
-          const int cu = pu - qq;
-          if (cu < 0 || cu >= T) continue;
-          const C m = mom[(qq * J + b) * TT + cv * T + cu];
-          sr2 += m.x;
-          si2 += m.y;
+          const bool ok = okv && static_cast<unsigned>(pu - qq) < static_cast<unsigned>(T);
+          sr2 += ok ? m[b * J + qq].x : R(0);
+          si2 += ok ? m[b * J + qq].y : R(0);
         }
       }
       out[pc] = cmk<C>(sr2, si2);
@@ -902,9 +929,10 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
   bool walked = false;
   if (!(parts & 1)) walked = true;   // patches not asked for
   if constexpr (J <= 4) if (parts & 1) {
-    // segment walk: table in LDS if both fit the two-blocks-per-CU budget
+    // segment walk: table in LDS if that keeps two blocks per CU, or if one
+    // block per CU is all that fits either way
     const WalkLds<R, J> with(a.T, a.tlen, true), without(a.T, a.tlen, false);
-    const bool tl = with.total <= kLdsSoft;
+    const bool tl = with.total <= kLdsSoft || (without.total > kLdsSoft && with.total <= kLdsHard);
     const size_t bytes = tl ? with.total : without.total;
     if (bytes <= kLdsHard) {
       if (tl) {

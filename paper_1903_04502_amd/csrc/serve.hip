@@ -6,10 +6,11 @@
 //   2. admits queued jobs in arrival order while the active-job limit and the
 //      caller's device arena allow: the job's footprint (plans, workspace,
 //      plan-ordered visibilities, image) is carved from the arena, its plans
-//      are built and its data prepared on the admission stream, ending with the
-//      device-side set-up of 1 / ||Phi|| and gamma (nothing read back);
-//   3. queues the next outer iteration of every running job on the job's own
-//      stream, keeping at most kDepth iterations in flight per job.
+//      are built on the admission stream, and its data are prepared on the
+//      job's own stream, ending with the device-side set-up of 1 / ||Phi||
+//      and gamma (nothing read back);
+//   3. queues outer iterations of every running job on the job's stream,
+//      keeping up to kDepth of them in flight per job.
 // Jobs therefore join and leave while others run, and the work of all active
 // jobs overlaps on the device. Each job runs exactly the kernels of a solve
 // run alone (its own plans and workspace), so its result does not depend on
@@ -27,7 +28,7 @@
 namespace pr {
 namespace {
 
-constexpr int kDepth = 2;   // outer iterations in flight per job
+constexpr int kDepth = 3;   // outer iterations in flight per job
 
 template <typename R>
 __global__ void gather_cx_kernel(const cx_t<R>* __restrict__ src, const int32_t* __restrict__ perm, int64_t M,
@@ -169,8 +170,10 @@ void release(pr_server_t* s, pr_server_t::Job* j) {
   j->has_mem = false;
 }
 
-// Build plans and device state of an admitted job on the admission stream.
+// Build the plans of an admitted job on the admission stream (plan creation
+// waits for its own sort only), then its device state on the job's stream.
 int setup_job(pr_server_t* s, pr_server_t::Job* j) {
+  const hipStream_t js = s->streams[j->stream];
   char* base = s->arena + j->off;
   const pr_job_desc& d = j->d;
   const pr_phi_desc pd = phi_desc_of(d);
@@ -182,20 +185,20 @@ int setup_job(pr_server_t* s, pr_server_t::Job* j) {
   const int64_t n2 = static_cast<int64_t>(d.n) * d.n;
   const int G = grid_for(d.M, 256, 8192);
   if (d.prec == PR_F32) {
-    gather_cx_kernel<float><<<G, 256, 0, s->adm>>>(static_cast<const float2*>(d.y), j->phi->perm, d.M,
-                                                   static_cast<float2*>(yplan));
-    zero_real_kernel<float><<<grid_for(n2, 256, 4096), 256, 0, s->adm>>>(static_cast<float*>(x), n2);
+    gather_cx_kernel<float><<<G, 256, 0, js>>>(static_cast<const float2*>(d.y), j->phi->perm, d.M,
+                                               static_cast<float2*>(yplan));
+    zero_real_kernel<float><<<grid_for(n2, 256, 4096), 256, 0, js>>>(static_cast<float*>(x), n2);
   } else {
-    gather_cx_kernel<double><<<G, 256, 0, s->adm>>>(static_cast<const double2*>(d.y), j->phi->perm, d.M,
-                                                    static_cast<double2*>(yplan));
-    zero_real_kernel<double><<<grid_for(n2, 256, 4096), 256, 0, s->adm>>>(static_cast<double*>(x), n2);
+    gather_cx_kernel<double><<<G, 256, 0, js>>>(static_cast<const double2*>(d.y), j->phi->perm, d.M,
+                                                static_cast<double2*>(yplan));
+    zero_real_kernel<double><<<grid_for(n2, 256, 4096), 256, 0, js>>>(static_cast<double*>(x), n2);
   }
   PR_TRY_LAUNCH();
-  PR_TRY(admm_job_init(&j->job, j->phi, j->psi, yplan, x, base + j->lay.o_admm, d.params, s->adm));
-  PR_TRY(admm_device_setup(&j->job, s->adm));
+  PR_TRY(admm_job_init(&j->job, j->phi, j->psi, yplan, x, base + j->lay.o_admm, d.params, js));
+  PR_TRY(admm_device_setup(&j->job, js));
   PR_TRY_HIP(hipEventCreateWithFlags(&j->ready, hipEventDisableTiming));
   for (auto& e : j->ev) PR_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  PR_TRY_HIP(hipEventRecord(j->ready, s->adm));
+  PR_TRY_HIP(hipEventRecord(j->ready, js));
   return PR_OK;
 }
 
@@ -324,14 +327,14 @@ int pr_server_tick(pr_server s, int32_t* queued, int32_t* running, int32_t* fini
     s->queue.pop_front();
     j->off = off;
     j->has_mem = true;
+    const int k = static_cast<int>(std::min_element(s->load.begin(), s->load.end()) - s->load.begin());
+    j->stream = k;
     const int rc = setup_job(s, j);
     if (rc != PR_OK) {
       release(s, j);
       j->state = 3;
       return rc;
     }
-    const int k = static_cast<int>(std::min_element(s->load.begin(), s->load.end()) - s->load.begin());
-    j->stream = k;
     s->load[k] += j->cost * j->d.params.iters;
     j->state = 1;
     ++s->active;
@@ -344,20 +347,22 @@ int pr_server_tick(pr_server s, int32_t* queued, int32_t* running, int32_t* fini
     return a->cost > b->cost;
   });
   for (pr_server_t::Job* j : run) {
-    hipEvent_t& slot = j->ev[j->enq % kDepth];
-    if (j->enq >= kDepth) {
-      const hipError_t q = hipEventQuery(slot);   // iteration enq - kDepth
-      if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess) {
-        set_error("job %lld: %s", static_cast<long long>(j->id), hipGetErrorString(q));
-        return PR_EHIP;
+    // fill the job's pipeline: up to kDepth outer iterations in flight
+    while (j->enq < j->d.params.iters) {
+      hipEvent_t& slot = j->ev[j->enq % kDepth];
+      if (j->enq >= kDepth) {
+        const hipError_t q = hipEventQuery(slot);   // iteration enq - kDepth
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          set_error("job %lld: %s", static_cast<long long>(j->id), hipGetErrorString(q));
+          return PR_EHIP;
+        }
       }
+      hipStream_t st = s->streams[j->stream];
+      PR_TRY(admm_step(&j->job, st));
+      PR_TRY_HIP(hipEventRecord(slot, st));
+      ++j->enq;
     }
-    hipStream_t st = s->streams[j->stream];
-    if (j->enq == 0) PR_TRY_HIP(hipStreamWaitEvent(st, j->ready, 0));
-    PR_TRY(admm_step(&j->job, st));
-    PR_TRY_HIP(hipEventRecord(slot, st));
-    ++j->enq;
   }
   int nq = 0, nr = 0, nf = 0;
   for (auto& kv : s->jobs) {
