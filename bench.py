@@ -275,7 +275,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c1j6"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c1j6", "c2"],
+                    help="c2: 2048^2 image, 5e8 ring-plus-core visibilities, FP32 (FP64 scalars) only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -306,24 +307,41 @@ def main():
     rng = W.rng_for(wl.index)
     log(f"workload {wl.name}: generating inputs")
     x_true = W.make_sky(wl, rng)
-    uv32 = W.make_uv(wl, rng)
-    noise = W.unit_complex_noise(M, rng)
+    big = args.workload == "c2"
+    if big:
+        # 5e8 baselines and noise drawn on the device (seeded torch generator)
+        args.no_fp64 = True
+        args.no_batch = args.no_serve = True
+        gen = W.torch_generator(wl.index, dev)
+        uv_dev = W.uv_ring_core_torch(M, gen, dev)
+        uv32 = None
+    else:
+        uv32 = W.make_uv(wl, rng)
+        noise = W.unit_complex_noise(M, rng)
     K_steps, W_steps = args.steps, args.warmup
     out = {}
 
     def run_prec(prec):
         rdt = torch.float32 if prec == P.PR_F32 else torch.float64
-        uv = torch.as_tensor(uv32.astype(np.float64) if prec == P.PR_F64 else uv32).to(dev)
+        if big:
+            uv = uv_dev
+        else:
+            uv = torch.as_tensor(uv32.astype(np.float64) if prec == P.PR_F64 else uv32).to(dev)
         plan = P.PhiPlan(n, uv, None, J=J, D=D, prec=prec)
         psi = P.PsiPlan(n, L, 0x1FF, prec, dev)
         perm = plan.perm()
         x = torch.as_tensor(x_true).to(dev, rdt)
         y0 = plan.apply(x)
-        # noisy data at 30 dB in plan order (noise draws are indexed by user order)
-        y0_user = torch.empty_like(y0)
-        y0_user[perm] = y0
-        y_user, sigma, eps = W.add_noise(y0_user.cpu().numpy().astype(np.complex128), noise, wl.snr_db)
-        y = torch.as_tensor(y_user).to(dev, plan.cdtype)[perm].contiguous()
+        if big:
+            # noise is iid: drawn directly in plan order on the device
+            y, sigma, eps = W.add_noise_torch(y0, W.unit_complex_noise_torch(M, gen, dev), wl.snr_db)
+            del y0
+        else:
+            # noisy data at 30 dB in plan order (noise draws are indexed by user order)
+            y0_user = torch.empty_like(y0)
+            y0_user[perm] = y0
+            y_user, sigma, eps = W.add_noise(y0_user.cpu().numpy().astype(np.complex128), noise, wl.snr_db)
+            y = torch.as_tensor(y_user).to(dev, plan.cdtype)[perm].contiguous()
         op_norm = plan.norm(100)
         dirty = plan.adjoint(y) / op_norm
         gamma = 1e-3 * float(psi.adjoint(dirty).abs().max().item())
@@ -427,7 +445,29 @@ def main():
                        "phi_adjoint_ms": r64["t_adj"], "admm_iter_ms": r64["t_admm"],
                        "stage_ms": {"fzs": r64["t_fzs"], "gw": r64["t_gw"], "grid_patches": r64["t_patch"],
                                     "grid_merge": r64["t_merge"], "fzs_adjoint": r64["t_fzsa"]}}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and big:
+        log("CPU baseline: oracle Phi and Phi^dagger on a 2e6-visibility sample of the 5e8")
+        from oracle import measurement as ms
+        spec = ms.PhiSpec(n, 2 * n, J, D)
+        Ms = 2_000_000
+        uv_s = uv_dev[:Ms].double().cpu().numpy()
+        t0 = time.perf_counter()
+        y_s = ms.phi(x_true, uv_s, None, spec)
+        t1 = time.perf_counter()
+        ms.phi_adjoint(y_s, uv_s, None, spec)
+        t2 = time.perf_counter()
+        res["cpu_baseline"] = {"value": Ms / (t2 - t0), "unit": "visibilities/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one Phi ({t1 - t0:.1f} s) and one Phi^dagger ({t2 - t1:.1f} s) of the "
+                                         f"FP64 NumPy oracle on the full 2048^2 image and the first {Ms} of the "
+                                         f"5e8 baselines (single thread; the 4096^2 FFTs are not amortised)",
+                               "host_cpus": os.cpu_count()}
+        # sampled parity of the timed Phi: the sample's visibilities in plan order
+        perm = r32["perm"]
+        pos = torch.nonzero(perm < Ms).squeeze(1)
+        y_gpu = r32["y_plan"][pos].cpu().numpy().astype(np.complex128)
+        y_or = y_s[perm[pos].cpu().numpy()]
+        res["phi_rel_err_fp32_vs_oracle_sample"] = float(np.linalg.norm(y_gpu - y_or) / np.linalg.norm(y_or))
+    elif not args.no_cpu_baseline:
         log("CPU baseline: oracle Phi and Phi^dagger on the full input")
         from oracle import measurement as ms
         spec = ms.PhiSpec(n, 2 * n, J, D)

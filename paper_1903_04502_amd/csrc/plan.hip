@@ -280,13 +280,13 @@ __global__ void gather_sorted_kernel(const R* uv, const R* w, const uint32_t* pe
 // ---------------------------------------------------------------------------
 static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Default tile side: aims at about a thousand visibilities per tile for the
-// gridding work items. FP32 with J <= 4 uses 16 (moments 32 KB of LDS) unless
-// the baselines are dense (8 or more per grid cell on average), then 8; wider
-// kernels and FP64 use 8.
+// Default tile side: FP32 with J <= 4 uses 16 (moments 32 KB of LDS, table
+// still in LDS, two blocks per CU; fewer, fuller work items than 8 at every
+// density measured); wider kernels and FP64 use 8. pr_phi_tune measures.
 static int default_tile(int J, int prec, int64_t M, int K) {
-  if (prec == PR_F32 && J <= 4) return M < 8 * static_cast<int64_t>(K) * K ? 16 : 8;
-  return 8;
+  (void)M;
+  (void)K;
+  return (prec == PR_F32 && J <= 4) ? 16 : 8;
 }
 
 // Smallest LDS footprint of the gridding kernel for a tile: moments, one side
