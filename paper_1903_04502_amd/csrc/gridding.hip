@@ -81,23 +81,80 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   }
   const int P = a.P, T = a.T, K = a.K;
   double sum_t = 0.0, sum_r = 0.0;
-  // inputs of this thread's visibilities for the current and the next chunk
-  R cu_[kDegridPer], cv_[kDegridPer], cw_[kDegridPer], nu_[kDegridPer], nv_[kDegridPer], nw_[kDegridPer];
-  auto load = [&](int c0, int cend, R* u, R* v, R* w) {
+  // Inputs of this thread's visibilities, two register sets used in turn:
+  // while one chunk is computed the next one's loads are in flight. Loads are
+  // unconditional (an index past the item reads its last visibility, unused),
+  // so loaded values land in place and no wait is taken before their use.
+  C uva[kDegridPer], uvb[kDegridPer];
+  R wa[kDegridPer], wb[kDegridPer];
+  const C* uv2 = reinterpret_cast<const C*>(a.uv);
+  auto load = [&](int c0, int cend, C* uv, R* w) {
 #pragma unroll
     for (int j = 0; j < kDegridPer; ++j) {
-      const int64_t k = c0 + tid + j * kThreads;
-      if (k < cend) {
-        u[j] = a.uv[2 * k];
-        v[j] = a.uv[2 * k + 1];
-        w[j] = a.w[k];
+      const int k = min(c0 + tid + j * kThreads, cend - 1);
+      uv[j] = uv2[k];
+      w[j] = a.w[k];
+    }
+  };
+  // Every slot is computed (a slot past the item holds its last visibility's
+  // inputs) and only the stores are predicated: the loaded registers are
+  // consumed on every path, so no conservative wait stalls the next loads.
+  auto compute = [&](int c0, int cend, int tu, int tv, const C* uv, const R* w) {
+#pragma unroll
+    for (int j = 0; j < kDegridPer; ++j) {
+      const int k = c0 + tid + j * kThreads;
+      const bool live = k < cend;
+      const AxisTaps xu = axis_taps(static_cast<double>(uv[j].x), a.kappa, J, a.D);
+      const AxisTaps xv = axis_taps(static_cast<double>(uv[j].y), a.kappa, J, a.D);
+      int lu = mod_pow2(xu.j0, K) - tu * T;
+      int lv = mod_pow2(xv.j0, K) - tv * T;
+      // cannot happen for a plan's own sorted baselines: read inside the patch, flag the value
+      const bool bad = static_cast<unsigned>(lu) >= static_cast<unsigned>(T) ||
+                       static_cast<unsigned>(lv) >= static_cast<unsigned>(T);
+      if (bad) lu = lv = 0;
+      R wu[J], wv[J];
+#pragma unroll
+      for (int q = 0; q < J; ++q) {
+        wu[q] = tab[tap_index(xu, q, J, a.D)];
+        wv[q] = tab[tap_index(xv, q, J, a.D)];
+      }
+      R accr = 0, acci = 0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        const C* row = patch + (lv + b) * P + lu;
+        R rr = 0, ri = 0;
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+          const C g = row[q];
+          rr += wu[q] * g.x;
+          ri += wu[q] * g.y;
+        }
+        accr += wv[b] * rr;
+        acci += wv[b] * ri;
+      }
+      const R ws = w[j] * scale;
+      C yk = cmk<C>(accr * ws, acci * ws);
+      if (bad) yk = cmk<C>(R(NAN), R(NAN));
+      if (MODE == 0) {
+        if (live) a.y_out[k] = yk;
+      } else {
+        const int kc = live ? k : cend - 1;
+        const C yo = a.y_obs[kc], sk = a.s_in[kc];
+        const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
+        if (live) {
+          a.t_out[k] = t;
+          const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x,
+                       di = static_cast<double>(yk.y) - yo.y;
+          sum_t += tr * tr + ti * ti;
+          sum_r += dr * dr + di * di;
+        }
       }
     }
   };
   for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
     const int4 it = a.items[item];
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
-    load(it.y, it.z, cu_, cv_, cw_);
+    load(it.y, it.z, uva, wa);
     __syncthreads();
     const float invP = 1.0f / P;
     for (int i = tid; i < P * P; i += kThreads) {
@@ -106,62 +163,12 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       patch[i] = a.grid[static_cast<int64_t>(gv) * K + gu];
     }
     __syncthreads();
-    for (int c0 = it.y; c0 < it.z; c0 += CH) {
-      if (c0 + CH < it.z) load(c0 + CH, it.z, nu_, nv_, nw_);
-#pragma unroll
-      for (int j = 0; j < kDegridPer; ++j) {
-        const int k = c0 + tid + j * kThreads;
-        if (k >= it.z) continue;
-        const AxisTaps xu = axis_taps(static_cast<double>(cu_[j]), a.kappa, J, a.D);
-        const AxisTaps xv = axis_taps(static_cast<double>(cv_[j]), a.kappa, J, a.D);
-        const int lu = mod_pow2(xu.j0, K) - tu * T;
-        const int lv = mod_pow2(xv.j0, K) - tv * T;
-        if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
-          // cannot happen for a plan's own sorted baselines; flag instead of reading out of the patch
-          const R nan = R(NAN);
-          if (MODE == 0) a.y_out[k] = cmk<C>(nan, nan);
-          else a.t_out[k] = cmk<C>(nan, nan);
-          continue;
-        }
-        R wu[J], wv[J];
-#pragma unroll
-        for (int q = 0; q < J; ++q) {
-          wu[q] = tab[tap_index(xu, q, J, a.D)];
-          wv[q] = tab[tap_index(xv, q, J, a.D)];
-        }
-        R accr = 0, acci = 0;
-#pragma unroll
-        for (int b = 0; b < J; ++b) {
-          const C* row = patch + (lv + b) * P + lu;
-          R rr = 0, ri = 0;
-#pragma unroll
-          for (int q = 0; q < J; ++q) {
-            const C g = row[q];
-            rr += wu[q] * g.x;
-            ri += wu[q] * g.y;
-          }
-          accr += wv[b] * rr;
-          acci += wv[b] * ri;
-        }
-        const R ws = cw_[j] * scale;
-        const C yk = cmk<C>(accr * ws, acci * ws);
-        if (MODE == 0) {
-          a.y_out[k] = yk;
-        } else {
-          const C yo = a.y_obs[k], sk = a.s_in[k];
-          const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
-          a.t_out[k] = t;
-          const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
-          sum_t += tr * tr + ti * ti;
-          sum_r += dr * dr + di * di;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < kDegridPer; ++j) {
-        cu_[j] = nu_[j];
-        cv_[j] = nv_[j];
-        cw_[j] = nw_[j];
-      }
+    for (int c0 = it.y; c0 < it.z; c0 += 2 * CH) {
+      if (c0 + CH < it.z) load(c0 + CH, it.z, uvb, wb);
+      compute(c0, it.z, tu, tv, uva, wa);
+      if (c0 + CH >= it.z) break;
+      if (c0 + 2 * CH < it.z) load(c0 + 2 * CH, it.z, uva, wa);
+      compute(c0 + CH, it.z, tu, tv, uvb, wb);
     }
   }
   if (MODE == 1) {
@@ -505,6 +512,10 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
 // Positions per thread and staged chunk: FP32 8, FP64 4 (the prefetch
 // registers hold one chunk).
 template <typename R> struct WalkChunk { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
+// Row pitch of the staged chunk, in entries: one more than the thread count,
+// so the WC lanes that store the WC positions of one segment hit different
+// banks (a pitch of exactly kThreads puts them on one bank).
+constexpr int kStagePitch = kThreads + 1;
 
 template <typename R, int J>
 struct WalkLds {
@@ -518,7 +529,7 @@ struct WalkLds {
     size_t o = 0;
     tab = o;   o += tab_bytes;
     mom = o;   o += align16(static_cast<size_t>(T) * T * J * J * sizeof(C));
-    const size_t staged = align16(static_cast<size_t>(kThreads) * WC * 2 * sizeof(C));
+    const size_t staged = align16(static_cast<size_t>(kStagePitch) * WC * 2 * sizeof(C));
     const size_t sides = align16(static_cast<size_t>(kThreads) * J * J * sizeof(C));
     stage = o; o += staged > sides ? staged : sides;
     if (tab_bytes >= lists) {
@@ -573,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int WC = WalkChunk<R>::value;
-  constexpr int CB = kThreads * WC;
+  constexpr int CB = kStagePitch * WC;
   constexpr int kSegStride = kThreads / WC;
   extern __shared__ char smem_raw[];
   const WalkLds<R, J> lay(a.T, a.tlen, TAB_LDS);
@@ -600,31 +611,38 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 
   WalkPrefetch<R, MODE> pf;
   // issue the loads of positions q0 .. q0 + WC - 1 of every segment of item it
+  // Every slot loads (a slot past its segment reads the item's first
+  // position, unused): no branches around the loads, so the loaded registers
+  // are not moved and nothing waits for them before the commit.
   auto issue = [&](const int4& it, int L, int q0) {
     pf.ok = 0u;
 #pragma unroll
     for (int r = 0; r < WC; ++r) {
       const int q = q0 + lane_q;
       const int pos = it.y + (lane_t + r * kSegStride) * L + q;
-      if (q < L && pos < it.z) {
-        pf.ok |= 1u << r;
-        pf.uv[r] = uv2[pos];
-        pf.w[r] = a.w[pos];
-        if (MODE == 0) {
-          pf.val[r] = a.y_in[pos];
-        } else {
-          pf.val[r] = a.t_in[pos];
-          pf.s[MODE == 1 ? r : 0] = a.s_io[pos];
-        }
+      const bool ok = q < L && pos < it.z;
+      pf.ok |= static_cast<unsigned>(ok) << r;
+      const int pc = ok ? pos : it.y;
+      pf.uv[r] = uv2[pc];
+      pf.w[r] = a.w[pc];
+      if (MODE == 0) {
+        pf.val[r] = a.y_in[pc];
+      } else {
+        pf.val[r] = a.t_in[pc];
+        pf.s[MODE == 1 ? r : 0] = a.s_io[pc];
       }
     }
   };
-  // store the prefetched chunk lane-transposed (ADMM prologue applied here)
+  // store the prefetched chunk lane-transposed (ADMM prologue applied here).
+  // The values are formed for every slot and only the stores are predicated,
+  // so every prefetched register is consumed on every path (no conservative
+  // waits on them later).
   auto commit = [&](const int4& it, int L, int q0) {
 #pragma unroll
     for (int r = 0; r < WC; ++r) {
-      if (!((pf.ok >> r) & 1u)) continue;
+      const bool ok = (pf.ok >> r) & 1u;
       C val;
+      C sn = cmk<C>(R(0), R(0));
       if (MODE == 0) {
         val = pf.val[r];
       } else {
@@ -633,15 +651,24 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         const C tt = pf.val[r], sk = pf.s[MODE == 1 ? r : 0];
         const R omk = R(1) - kappa_ball;
         const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
-        const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
-        a.s_io[it.y + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
+        sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
         val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
       }
       const R ws = pf.w[r] * scale;
-      const int slot = lane_q * kThreads + lane_t + r * kSegStride;
-      st_uv[slot] = pf.uv[r];
-      st_val[slot] = cmk<C>(val.x * ws, val.y * ws);
+      const C uvr = pf.uv[r];
+      const C wv = cmk<C>(val.x * ws, val.y * ws);
+      if (ok) {
+        if (MODE == 1) a.s_io[it.y + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
+        const int slot = lane_q * kStagePitch + lane_t + r * kSegStride;
+        st_uv[slot] = uvr;
+        st_val[slot] = wv;
+      }
     }
+    // every prefetched load has landed (the values above needed them): say so
+    // explicitly (vmcnt(0), other counters untouched), so the compiler does
+    // not keep them pending across the predicated stores and stall the next
+    // prefetch on its own registers
+    __builtin_amdgcn_s_waitcnt(0x0F70);
   };
   auto seg_len = [](const int4& it) { return (it.z - it.y + kThreads - 1) / kThreads; };
 
@@ -659,8 +686,14 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     const int Ln = seg_len(itn);
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
     const int segn = max(0, min(L, it.z - (it.y + tid * L)));   // this thread's positions
-    __syncthreads();   // the previous item is done with the moments and side slots
+    __syncthreads();   // the previous item is done with the moments, side slots and cell lists
     for (int i = tid; i < TT * JJ; i += kThreads) mom[i] = cmk<C>(R(0), R(0));
+    if (TAB_LDS && lay.borrow) {
+      // restore the table head the cell lists borrowed (its loads complete
+      // with the first chunk's, which the commit below waits for anyway)
+      R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
+      for (int i = tid; i < lay.borrow; i += kThreads) t[i] = a.table[i];
+    }
 
     R ar[JJ], ai[JJ];
     int first = -1, cur = -1, nruns = 0;
@@ -669,13 +702,16 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     for (int q0 = 0; q0 < L; q0 += WC) {
       if (q0 > 0) __syncthreads();   // the previous chunk has been walked
       commit(it, L, q0);
-      if (q0 + WC < L) issue(it, L, q0 + WC);
-      else if (nxt < a.nItems) issue(itn, Ln, 0);
+      {
+        // one call site for both prefetch targets (next chunk, or next item's first)
+        const bool more = q0 + WC < L;
+        if (more || nxt < a.nItems) issue(more ? it : itn, more ? L : Ln, more ? q0 + WC : 0);
+      }
       __syncthreads();
       const int qn = min(WC, segn - q0);
       for (int i = 0; i < qn; ++i) {
-        const C uv = st_uv[i * kThreads + tid];
-        C val = st_val[i * kThreads + tid];
+        const C uv = st_uv[i * kStagePitch + tid];
+        C val = st_val[i * kStagePitch + tid];
         const AxisTaps xu = axis_taps(static_cast<double>(uv.x), a.kappa, J, a.D);
         const AxisTaps xv = axis_taps(static_cast<double>(uv.y), a.kappa, J, a.D);
         int lu = mod_pow2(xu.j0, K) - tu * T;
@@ -735,10 +771,6 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       while (jend < kThreads && fcell[jend] == cur && lcell[jend] == cur) ++jend;
     }
     __syncthreads();   // side slots written; cell lists no longer read
-    if (TAB_LDS && lay.borrow) {
-      R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
-      for (int i = tid; i < lay.borrow; i += kThreads) t[i] = a.table[i];
-    }
     if (owner) {
       for (int j = tid + 1; j < jend; ++j) {
 #pragma unroll
