@@ -81,80 +81,23 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   }
   const int P = a.P, T = a.T, K = a.K;
   double sum_t = 0.0, sum_r = 0.0;
-  // Inputs of this thread's visibilities, two register sets used in turn:
-  // while one chunk is computed the next one's loads are in flight. Loads are
-  // unconditional (an index past the item reads its last visibility, unused),
-  // so loaded values land in place and no wait is taken before their use.
-  C uva[kDegridPer], uvb[kDegridPer];
-  R wa[kDegridPer], wb[kDegridPer];
-  const C* uv2 = reinterpret_cast<const C*>(a.uv);
-  auto load = [&](int c0, int cend, C* uv, R* w) {
+  // inputs of this thread's visibilities for the current and the next chunk
+  R cu_[kDegridPer], cv_[kDegridPer], cw_[kDegridPer], nu_[kDegridPer], nv_[kDegridPer], nw_[kDegridPer];
+  auto load = [&](int c0, int cend, R* u, R* v, R* w) {
 #pragma unroll
     for (int j = 0; j < kDegridPer; ++j) {
-      const int k = min(c0 + tid + j * kThreads, cend - 1);
-      uv[j] = uv2[k];
-      w[j] = a.w[k];
-    }
-  };
-  // Every slot is computed (a slot past the item holds its last visibility's
-  // inputs) and only the stores are predicated: the loaded registers are
-  // consumed on every path, so no conservative wait stalls the next loads.
-  auto compute = [&](int c0, int cend, int tu, int tv, const C* uv, const R* w) {
-#pragma unroll
-    for (int j = 0; j < kDegridPer; ++j) {
-      const int k = c0 + tid + j * kThreads;
-      const bool live = k < cend;
-      const AxisTaps xu = axis_taps(static_cast<double>(uv[j].x), a.kappa, J, a.D);
-      const AxisTaps xv = axis_taps(static_cast<double>(uv[j].y), a.kappa, J, a.D);
-      int lu = mod_pow2(xu.j0, K) - tu * T;
-      int lv = mod_pow2(xv.j0, K) - tv * T;
-      // cannot happen for a plan's own sorted baselines: read inside the patch, flag the value
-      const bool bad = static_cast<unsigned>(lu) >= static_cast<unsigned>(T) ||
-                       static_cast<unsigned>(lv) >= static_cast<unsigned>(T);
-      if (bad) lu = lv = 0;
-      R wu[J], wv[J];
-#pragma unroll
-      for (int q = 0; q < J; ++q) {
-        wu[q] = tab[tap_index(xu, q, J, a.D)];
-        wv[q] = tab[tap_index(xv, q, J, a.D)];
-      }
-      R accr = 0, acci = 0;
-#pragma unroll
-      for (int b = 0; b < J; ++b) {
-        const C* row = patch + (lv + b) * P + lu;
-        R rr = 0, ri = 0;
-#pragma unroll
-        for (int q = 0; q < J; ++q) {
-          const C g = row[q];
-          rr += wu[q] * g.x;
-          ri += wu[q] * g.y;
-        }
-        accr += wv[b] * rr;
-        acci += wv[b] * ri;
-      }
-      const R ws = w[j] * scale;
-      C yk = cmk<C>(accr * ws, acci * ws);
-      if (bad) yk = cmk<C>(R(NAN), R(NAN));
-      if (MODE == 0) {
-        if (live) a.y_out[k] = yk;
-      } else {
-        const int kc = live ? k : cend - 1;
-        const C yo = a.y_obs[kc], sk = a.s_in[kc];
-        const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
-        if (live) {
-          a.t_out[k] = t;
-          const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x,
-                       di = static_cast<double>(yk.y) - yo.y;
-          sum_t += tr * tr + ti * ti;
-          sum_r += dr * dr + di * di;
-        }
+      const int64_t k = c0 + tid + j * kThreads;
+      if (k < cend) {
+        u[j] = a.uv[2 * k];
+        v[j] = a.uv[2 * k + 1];
+        w[j] = a.w[k];
       }
     }
   };
   for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
     const int4 it = a.items[item];
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
-    load(it.y, it.z, uva, wa);
+    load(it.y, it.z, cu_, cv_, cw_);
     __syncthreads();
     const float invP = 1.0f / P;
     for (int i = tid; i < P * P; i += kThreads) {
@@ -163,12 +106,62 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       patch[i] = a.grid[static_cast<int64_t>(gv) * K + gu];
     }
     __syncthreads();
-    for (int c0 = it.y; c0 < it.z; c0 += 2 * CH) {
-      if (c0 + CH < it.z) load(c0 + CH, it.z, uvb, wb);
-      compute(c0, it.z, tu, tv, uva, wa);
-      if (c0 + CH >= it.z) break;
-      if (c0 + 2 * CH < it.z) load(c0 + 2 * CH, it.z, uva, wa);
-      compute(c0 + CH, it.z, tu, tv, uvb, wb);
+    for (int c0 = it.y; c0 < it.z; c0 += CH) {
+      if (c0 + CH < it.z) load(c0 + CH, it.z, nu_, nv_, nw_);
+#pragma unroll
+      for (int j = 0; j < kDegridPer; ++j) {
+        const int k = c0 + tid + j * kThreads;
+        if (k >= it.z) continue;
+        const AxisTaps xu = axis_taps(static_cast<double>(cu_[j]), a.kappa, J, a.D);
+        const AxisTaps xv = axis_taps(static_cast<double>(cv_[j]), a.kappa, J, a.D);
+        const int lu = mod_pow2(xu.j0, K) - tu * T;
+        const int lv = mod_pow2(xv.j0, K) - tv * T;
+        if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
+          // cannot happen for a plan's own sorted baselines; flag instead of reading out of the patch
+          const R nan = R(NAN);
+          if (MODE == 0) a.y_out[k] = cmk<C>(nan, nan);
+          else a.t_out[k] = cmk<C>(nan, nan);
+          continue;
+        }
+        R wu[J], wv[J];
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+          wu[q] = tab[tap_index(xu, q, J, a.D)];
+          wv[q] = tab[tap_index(xv, q, J, a.D)];
+        }
+        R accr = 0, acci = 0;
+#pragma unroll
+        for (int b = 0; b < J; ++b) {
+          const C* row = patch + (lv + b) * P + lu;
+          R rr = 0, ri = 0;
+#pragma unroll
+          for (int q = 0; q < J; ++q) {
+            const C g = row[q];
+            rr += wu[q] * g.x;
+            ri += wu[q] * g.y;
+          }
+          accr += wv[b] * rr;
+          acci += wv[b] * ri;
+        }
+        const R ws = cw_[j] * scale;
+        const C yk = cmk<C>(accr * ws, acci * ws);
+        if (MODE == 0) {
+          a.y_out[k] = yk;
+        } else {
+          const C yo = a.y_obs[k], sk = a.s_in[k];
+          const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
+          a.t_out[k] = t;
+          const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
+          sum_t += tr * tr + ti * ti;
+          sum_r += dr * dr + di * di;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kDegridPer; ++j) {
+        cu_[j] = nu_[j];
+        cv_[j] = nv_[j];
+        cw_[j] = nw_[j];
+      }
     }
   }
   if (MODE == 1) {
