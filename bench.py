@@ -79,6 +79,26 @@ def kernel_traffic(kernel: str, workload: str):
         return None
 
 
+def copy_bandwidth(dev, nbytes=1 << 31, reps=5):
+    """Device-to-device copy rate (read + write bytes / time), the practical
+    HBM ceiling the visibility kernels are also compared against."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / t / 1e9
+
+
 def run_batch(P, dev, args):
     """64 channels of uneven n and M stepped together (tiles from the autotuner)."""
     import torch
@@ -406,6 +426,7 @@ def main():
         log(f"FP64: phi {r64['t_phi']:.3f} ms, adj {r64['t_adj']:.3f} ms, admm {r64['t_admm']:.3f} ms")
 
     value = M / ((r32["t_phi"] + r32["t_adj"]) * 1e-3)
+    copy_gbs = copy_bandwidth(dev)
     # dominant single-kernel stage of the operator pair: gridding patches or degridding
     vis_bytes = 20.0 * M            # u, v, w, y in FP32 per visibility, once per launch
     kernels = {"grid_walk_kernel": r32["t_patch"], "degrid_kernel": r32["t_gw"]}
@@ -415,7 +436,8 @@ def main():
         ach = vis_bytes / (t_ms * 1e-3) / 1e9
         roof[kname] = {"bound": "hbm", "kernel": kname, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": ach / HBM_PEAK_GBS, "traffic": kernel_traffic(kname, wl.name),
-                       "algorithmic_bytes_per_launch": vis_bytes, "launch_ms": t_ms}
+                       "algorithmic_bytes_per_launch": vis_bytes, "launch_ms": t_ms,
+                       "frac_of_copy": ach / copy_gbs}
     res = {
         "metric": METRIC,
         "value": value,
@@ -437,6 +459,7 @@ def main():
                      "grid_merge": r32["t_merge"], "fzs_adjoint": r32["t_fzsa"]},
         "admm_iter_ms_fp32": r32["t_admm"],
         "roofline": roof[dom],
+        "copy_gbs": copy_gbs,
         "roofline_other": [v for k, v in roof.items() if k != dom],
         "work_items": r32["items"],
     }

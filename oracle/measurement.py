@@ -7,9 +7,10 @@ e^{-2 pi i (lu + mv)}; eq. (matrix_equation) factors the discrete operator as
 y = W G F Z S x with S the gridding correction, Z zero padding, F an FFT, G the
 convolutional interpolation off the grid and W noise weights; the adjoint
 applies the adjoints in reverse order (S^H Z^H F^H G^H W^H). The pre-sampled
-kernel is looked up by nearest sample (Section "Kernel Pre-Sampling"). The
-operator is normalised by its norm from the power method (Section
-"Distributed Images").
+kernel is looked up by nearest sample (zeroth order) or interpolated linearly
+between the two samples that bracket the tap distance (first order), the two
+options the paper weighs in Section "Kernel Pre-Sampling". The operator is
+normalised by its norm from the power method (Section "Distributed Images").
 
 Conventions (readings where the paper is silent; every one is a parameter the
 GPU library follows too):
@@ -25,6 +26,12 @@ GPU library follows too):
     tap a at distance t_a = |s - j_a| uses sample round(t_a D) with ties toward
     the larger distance; written with m = J/2 - 1 - a this is
     m D + round_half_up(f) for m >= 0 and |m| D - round_half_down(f) for m < 0;
+  * first-order rule: the distance in samples x_a = t_a D is formed as
+    m D + f (m >= 0) or |m| D - f (m < 0) from the same FP64 f; with
+    i = floor(x_a) and phi = x_a - i the weight is (1 - phi) T[i] + phi T[i+1]
+    (for m >= 0: i = m D + floor(f), phi = f - floor(f); for m < 0 and f not an
+    integer: i = |m| D - floor(f) - 1, phi = 1 - (f - floor(f)); for m < 0 and
+    f an integer: i = |m| D - f, phi = 0);
   * weights W are real.
 
 Parity: Phi, Phi^H are exact linear maps once the table is fixed, pinned by the
@@ -47,10 +54,13 @@ class PhiSpec:
     K: int
     J: int = 4
     D: int = 2000
+    interp: str = "nearest"     # "nearest" (zeroth order) or "linear" (first order)
 
     def __post_init__(self):
         if self.J % 2:
             raise ValueError("J must be even")
+        if self.interp not in ("nearest", "linear"):
+            raise ValueError("interp must be 'nearest' or 'linear'")
         self.beta = kb.kb_beta(self.J, self.K / self.n)
         self.table = kb.kb_table(self.J, self.D, self.beta)
         self.corr = kb.correction(self.n, self.K, self.J, self.beta)
@@ -94,8 +104,48 @@ def taps_1d(u, K: int, J: int, D: int):
     return taps_from_coordinate(grid_coordinate(u, K), J, D)
 
 
+def linear_taps_from_coordinate(s, J: int, D: int):
+    """First tap cell, lower sample index and fraction for first-order lookup.
+
+    Returns (j0, i, phi): i and phi of shape (M, J) such that the tap weight
+    is (1 - phi) T[i] + phi T[i + 1], the straight line between the two
+    samples bracketing the tap distance x = t D (see the module header).
+    """
+    s = np.asarray(s, dtype=np.float64).reshape(-1)
+    fl = np.floor(s)
+    fr = s - fl
+    f = fr * D
+    ff = np.floor(f)
+    r = f - ff
+    i = np.empty((s.size, J), dtype=np.int64)
+    ph = np.empty((s.size, J), dtype=np.float64)
+    for a in range(J):
+        m = J // 2 - 1 - a
+        if m >= 0:                       # x = m D + f
+            i[:, a] = (m * D + ff).astype(np.int64)
+            ph[:, a] = r
+        else:                            # x = |m| D - f
+            frac = r > 0
+            i[:, a] = ((-m) * D - ff - frac).astype(np.int64)
+            ph[:, a] = np.where(frac, 1.0 - r, 0.0)
+    j0 = fl.astype(np.int64) - J // 2 + 1
+    return j0, i, ph
+
+
+def linear_weights(table, i, ph):
+    """(1 - phi) T[i] + phi T[i + 1]; with phi = 0 only T[i] is used."""
+    i1 = np.minimum(i + 1, table.size - 1)
+    return (1.0 - ph) * table[i] + ph * table[i1]
+
+
 def tap_weights(uv, spec: PhiSpec):
     """Per-visibility first cells and kernel weights on both axes."""
+    if spec.interp == "linear":
+        su = grid_coordinate(uv[:, 0], spec.K)
+        sv = grid_coordinate(uv[:, 1], spec.K)
+        ju, iu, pu = linear_taps_from_coordinate(su, spec.J, spec.D)
+        jv, iv, pv = linear_taps_from_coordinate(sv, spec.J, spec.D)
+        return ju, linear_weights(spec.table, iu, pu), jv, linear_weights(spec.table, iv, pv)
     ju, iu = taps_1d(uv[:, 0], spec.K, spec.J, spec.D)
     jv, iv = taps_1d(uv[:, 1], spec.K, spec.J, spec.D)
     return ju, spec.table[iu], jv, spec.table[iv]
