@@ -8,8 +8,9 @@ Kaiser-Bessel J = 4 at D = 2000 samples per cell, SARA (Dirac + db1..db8) at
 before timing starts.
 
 Timed, after W warm-up passes, on torch's current stream with HIP events:
-  * K pairs (Phi, Phi^dagger), each launch bracketed by events:
-    value = M / (t_Phi + t_Phi^dagger) in visibilities/s (FP32);
+  * K pairs (Phi, Phi^dagger) between two events: value = M / t_pair in
+    visibilities/s (FP32); then K more pairs with every launch bracketed by
+    events for the per-stage times and the roofline kernel's duration;
   * K ADMM iterations (Algorithm 1, one DualFB iteration each) in one
     solve call: ms_per_step = its time / K (FP32);
   * the same two figures in FP64 (reported beside, not as `value`);
@@ -97,6 +98,35 @@ def copy_bandwidth(dev, nbytes=1 << 31, reps=5):
     del src, dst
     torch.cuda.empty_cache()
     return 2.0 * nbytes / t / 1e9
+
+
+def run_linear(P, dev, n, J, D, uv32, x_true, K_steps, W_steps, with_oracle):
+    """The same workload with first-order (linear) kernel lookup, FP32."""
+    import torch
+    plan = P.PhiPlan(n, torch.as_tensor(uv32).to(dev), None, J=J, D=D, interp=1)
+    x = torch.as_tensor(x_true, dtype=torch.float32, device=dev)
+    y = torch.empty(plan.M, dtype=torch.complex64, device=dev)
+    xg = torch.empty_like(x)
+    for _ in range(W_steps):
+        P.pr_phi_apply(plan.handle, x, y)
+        P.pr_phi_adjoint(plan.handle, y, xg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K_steps):
+        P.pr_phi_apply(plan.handle, x, y)
+        P.pr_phi_adjoint(plan.handle, y, xg)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / K_steps
+    out = {"interp": "linear (first order)", "phi_pair_ms": t, "vis_per_s": plan.M / (t * 1e-3)}
+    if with_oracle:
+        from oracle import measurement as ms
+        P.pr_phi_apply(plan.handle, x, y)
+        y_ref = ms.phi(x_true, uv32.astype(np.float64), None, ms.PhiSpec(n, 2 * n, J, D, "linear"))
+        perm = plan.perm().cpu().numpy()
+        out["phi_rel_err_vs_oracle"] = float(np.linalg.norm(y.cpu().numpy() - y_ref[perm]) / np.linalg.norm(y_ref))
+    return out
 
 
 def run_batch(P, dev, args):
@@ -369,11 +399,20 @@ def main():
         yv = torch.empty_like(y)
         stream = torch.cuda.current_stream(dev)
         h = plan.handle
-        # ---- Phi, Phi^dagger pairs
+        # ---- Phi, Phi^dagger pairs: whole pairs between two events (value) ...
         for _ in range(W_steps):
             P.pr_phi_apply(h, x, yv)
             P.pr_phi_adjoint(h, y, xg)
         torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for _ in range(K_steps):
+            P.pr_phi_apply(h, x, yv)
+            P.pr_phi_adjoint(h, y, xg)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        t_pair = p0.elapsed_time(p1) / K_steps
+        # ... and each launch bracketed by events (stage times, roofline)
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K_steps)]
         for k in range(K_steps):
             e = ev[k]
@@ -411,7 +450,7 @@ def main():
         rep = P.pr_admm_solve(h, psi.handle, y, P.admm_params(eps, gamma, iters=K_steps, op_norm=op_norm),
                               torch.zeros((n, n), dtype=rdt, device=dev), ws, want_report=True)
         return dict(t_fzs=t_fzs, t_gw=t_gw, t_gwa=t_gwa, t_patch=t_patch, t_merge=t_merge, t_fzsa=t_fzsa,
-                    t_phi=t_phi, t_adj=t_adj,
+                    t_phi=t_phi, t_adj=t_adj, t_pair=t_pair,
                     t_admm=t_admm, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
                     eps=eps, resid=rep.resid_norm, nonfinite=rep.nonfinite, y_plan=yv, perm=perm,
                     plan=plan, x=x)
@@ -425,7 +464,7 @@ def main():
         r64 = run_prec(P.PR_F64)
         log(f"FP64: phi {r64['t_phi']:.3f} ms, adj {r64['t_adj']:.3f} ms, admm {r64['t_admm']:.3f} ms")
 
-    value = M / ((r32["t_phi"] + r32["t_adj"]) * 1e-3)
+    value = M / (r32["t_pair"] * 1e-3)
     copy_gbs = copy_bandwidth(dev)
     # dominant single-kernel stage of the operator pair: gridding patches or degridding
     vis_bytes = 20.0 * M            # u, v, w, y in FP32 per visibility, once per launch
@@ -454,7 +493,7 @@ def main():
         "config": {"workload": wl.name, "image": n, "grid": 2 * n, "visibilities": M, "J": J,
                    "table_samples_per_cell": D, "sara_levels": L, "dualfb_iters": 1,
                    "step": "one ADMM iteration (ms_per_step); value from (Phi, Phi^dagger) pairs"},
-        "phi_ms": r32["t_phi"], "phi_adjoint_ms": r32["t_adj"],
+        "phi_pair_ms": r32["t_pair"], "phi_ms": r32["t_phi"], "phi_adjoint_ms": r32["t_adj"],
         "stage_ms": {"fzs": r32["t_fzs"], "gw": r32["t_gw"], "grid_patches": r32["t_patch"],
                      "grid_merge": r32["t_merge"], "fzs_adjoint": r32["t_fzsa"]},
         "admm_iter_ms_fp32": r32["t_admm"],
@@ -464,7 +503,7 @@ def main():
         "work_items": r32["items"],
     }
     if r64 is not None:
-        res["fp64"] = {"value": M / ((r64["t_phi"] + r64["t_adj"]) * 1e-3), "phi_ms": r64["t_phi"],
+        res["fp64"] = {"value": M / (r64["t_pair"] * 1e-3), "phi_ms": r64["t_phi"],
                        "phi_adjoint_ms": r64["t_adj"], "admm_iter_ms": r64["t_admm"],
                        "stage_ms": {"fzs": r64["t_fzs"], "gw": r64["t_gw"], "grid_patches": r64["t_patch"],
                                     "grid_merge": r64["t_merge"], "fzs_adjoint": r64["t_fzsa"]}}
@@ -515,6 +554,9 @@ def main():
             res["fp64"]["phi_rel_err_vs_oracle"] = float(np.linalg.norm(y64 - y_ref[perm64]) / np.linalg.norm(y_ref))
     del r32, r64
     torch.cuda.empty_cache()
+    if not big:
+        log("first-order kernel lookup")
+        res["linear_lookup"] = run_linear(P, dev, n, J, D, uv32, x_true, K_steps, W_steps, not args.no_cpu_baseline)
     if not args.no_batch:
         log("batched channels")
         res["batch"] = run_batch(P, dev, args)

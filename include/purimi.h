@@ -84,6 +84,10 @@ typedef struct {
   int64_t M;          /* visibilities, 0 <= M < 2^31                        */
   int32_t prec;       /* PR_F32 or PR_F64                                    */
   int32_t tile;       /* tile side in grid cells: 0 = default, else 8/16/32  */
+  int32_t interp;     /* kernel lookup (Section "Kernel Pre-Sampling"):
+                         0 = nearest sample (zeroth order), 1 = linear
+                         between the two samples around the tap distance
+                         (first order)                                       */
 } pr_phi_desc;
 
 typedef struct pr_phi_plan_t* pr_phi_plan;
@@ -328,6 +332,7 @@ typedef struct {
   const void* w;        /* device Real[M] or NULL (ones)                      */
   const void* y;        /* device complex[M], user order                      */
   pr_admm_params params;/* iters = outer iterations; rel_tol ignored; x0 = 0  */
+  int32_t interp;       /* kernel lookup, as pr_phi_desc.interp              */
 } pr_job_desc;
 /* uv, w and y must stay valid until the job is running (state >= 1). */
 

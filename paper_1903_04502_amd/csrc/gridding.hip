@@ -65,7 +65,7 @@ struct GwArgs {
 
 constexpr int kDegridPer = 4;   // visibilities per thread per chunk
 
-template <typename R, int J, int MODE, bool TAB_LDS>
+template <typename R, int J, int MODE, bool TAB_LDS, bool LIN>
 __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   using C = cx_t<R>;
   const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
         R wu[J], wv[J];
 #pragma unroll
         for (int q = 0; q < J; ++q) {
-          wu[q] = tab[tap_index(xu, q, J, a.D)];
-          wv[q] = tab[tap_index(xv, q, J, a.D)];
+          wu[q] = tap_weight<LIN>(tab, xu, q, J, a.D, a.tlen);
+          wv[q] = tap_weight<LIN>(tab, xv, q, J, a.D, a.tlen);
         }
         R accr = 0, acci = 0;
 #pragma unroll
@@ -244,7 +244,7 @@ constexpr int kGridPer = 4;   // staged visibilities per thread: B <= kThreads *
 // moment is therefore a sum in a fixed order: deterministic, no atomics. The
 // next batch's inputs are loaded into registers while the current one is
 // accumulated.
-template <typename R, int J, int JA, int MODE, bool TAB_LDS>
+template <typename R, int J, int JA, int MODE, bool TAB_LDS, bool LIN>
 __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
   const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
@@ -373,8 +373,8 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
         st_yw[si] = val;
 #pragma unroll
         for (int q = 0; q < J; ++q) {
-          st_wu[q * B + si] = tab[tap_index(xu, q, J, a.D)];
-          st_wv[q * B + si] = tab[tap_index(xv, q, J, a.D)];
+          st_wu[q * B + si] = tap_weight<LIN>(tab, xu, q, J, a.D, a.tlen);
+          st_wv[q * B + si] = tap_weight<LIN>(tab, xv, q, J, a.D, a.tlen);
         }
       }
       __syncthreads();
@@ -571,7 +571,7 @@ struct WalkPrefetch {
 // whole sum in its side slot after the walk; the owner then adds, in segment
 // order, the side slots of the middle segments and the final part already in
 // the moments, and stores the total.
-template <typename R, int J, int MODE, bool TAB_LDS>
+template <typename R, int J, int MODE, bool TAB_LDS, bool LIN>
 __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
   const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
@@ -732,10 +732,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         }
         R wv[J];
 #pragma unroll
-        for (int b = 0; b < J; ++b) wv[b] = tab[tap_index(xv, b, J, a.D)];
+        for (int b = 0; b < J; ++b) wv[b] = tap_weight<LIN>(tab, xv, b, J, a.D, a.tlen);
 #pragma unroll
         for (int qq = 0; qq < J; ++qq) {
-          const R g = tab[tap_index(xu, qq, J, a.D)];
+          const R g = tap_weight<LIN>(tab, xu, qq, J, a.D, a.tlen);
           const R yr = val.x * g, yi = val.y * g;
 #pragma unroll
           for (int b = 0; b < J; ++b) {
@@ -901,7 +901,7 @@ int allow_lds(K kernel, size_t bytes) {
   return PR_OK;
 }
 
-template <typename R, int J, int MODE>
+template <typename R, int J, int MODE, bool LIN>
 int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
   using C = cx_t<R>;
   const size_t patch = align16(static_cast<size_t>(p->P) * p->P * sizeof(C));
@@ -910,10 +910,10 @@ int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
   if (MODE == 1 && lds < kThreads * sizeof(double)) lds = kThreads * sizeof(double);
   const int G = degrid_blocks(p);
   if (lds + tabb <= kLdsSoft) {
-    degrid_kernel<R, J, MODE, true><<<G, kThreads, lds + tabb, s>>>(a);
+    degrid_kernel<R, J, MODE, true, LIN><<<G, kThreads, lds + tabb, s>>>(a);
   } else if (lds <= kLdsHard) {
-    PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false>, lds));
-    degrid_kernel<R, J, MODE, false><<<G, kThreads, lds, s>>>(a);
+    PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false, LIN>, lds));
+    degrid_kernel<R, J, MODE, false, LIN><<<G, kThreads, lds, s>>>(a);
   } else {
     set_error("degridding patch of tile %d does not fit in LDS", p->T);
     return PR_EUNSUPPORTED;
@@ -946,7 +946,7 @@ bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
   return false;
 }
 
-template <typename R, int J, int MODE>
+template <typename R, int J, int MODE, bool LIN>
 int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) {
   using C = cx_t<R>;
   constexpr int JA = GridSplit<R, J>::JA;
@@ -961,11 +961,11 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
     const size_t bytes = tl ? with.total : without.total;
     if (bytes <= kLdsHard) {
       if (tl) {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true>, bytes));
-        grid_walk_kernel<R, J, MODE, true><<<G, kThreads, bytes, s>>>(a);
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LIN>, bytes));
+        grid_walk_kernel<R, J, MODE, true, LIN><<<G, kThreads, bytes, s>>>(a);
       } else {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false>, bytes));
-        grid_walk_kernel<R, J, MODE, false><<<G, kThreads, bytes, s>>>(a);
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LIN>, bytes));
+        grid_walk_kernel<R, J, MODE, false, LIN><<<G, kThreads, bytes, s>>>(a);
       }
       walked = true;
     }
@@ -980,11 +980,11 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
     }
     a.B = B;
     if (tab_lds) {
-      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true>, bytes));
-      grid_kernel<R, J, JA, MODE, true><<<G, kThreads, bytes, s>>>(a);
+      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true, LIN>, bytes));
+      grid_kernel<R, J, JA, MODE, true, LIN><<<G, kThreads, bytes, s>>>(a);
     } else {
-      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false>, bytes));
-      grid_kernel<R, J, JA, MODE, false><<<G, kThreads, bytes, s>>>(a);
+      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false, LIN>, bytes));
+      grid_kernel<R, J, JA, MODE, false, LIN><<<G, kThreads, bytes, s>>>(a);
     }
   }
   PR_TRY_LAUNCH();
@@ -996,33 +996,37 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
   return PR_OK;
 }
 
-template <typename R, int J, int MODE>
+template <typename R, int J, int MODE, bool LIN>
 int setup_mode() {
   constexpr int JA = GridSplit<R, J>::JA;
-  PR_TRY(allow_lds(degrid_kernel<R, J, MODE, true>, kLdsHard));
-  PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false>, kLdsHard));
+  PR_TRY((allow_lds(degrid_kernel<R, J, MODE, true, LIN>, kLdsHard)));
+  PR_TRY((allow_lds(degrid_kernel<R, J, MODE, false, LIN>, kLdsHard)));
   if constexpr (J <= 4) {
-    PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true>, kLdsHard));
-    PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false>, kLdsHard));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LIN>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LIN>, kLdsHard)));
   }
-  PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true>, kLdsHard));
-  PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false>, kLdsHard));
+  PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, true, LIN>, kLdsHard)));
+  PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, false, LIN>, kLdsHard)));
   return PR_OK;
 }
 
 template <typename R, int J>
-int setup_kernels() {
-  PR_TRY((setup_mode<R, J, 0>()));
-  return setup_mode<R, J, 1>();
+int setup_kernels(bool lin) {
+  if (lin) {
+    PR_TRY((setup_mode<R, J, 0, true>()));
+    return setup_mode<R, J, 1, true>();
+  }
+  PR_TRY((setup_mode<R, J, 0, false>()));
+  return setup_mode<R, J, 1, false>();
 }
 
 template <typename R>
-int setup_prec(int J) {
+int setup_prec(int J, bool lin) {
   switch (J) {
-    case 2: return setup_kernels<R, 2>();
-    case 4: return setup_kernels<R, 4>();
-    case 6: return setup_kernels<R, 6>();
-    case 8: return setup_kernels<R, 8>();
+    case 2: return setup_kernels<R, 2>(lin);
+    case 4: return setup_kernels<R, 4>(lin);
+    case 6: return setup_kernels<R, 6>(lin);
+    case 8: return setup_kernels<R, 8>(lin);
     default: set_error("J = %d unsupported", J); return PR_EUNSUPPORTED;
   }
 }
@@ -1076,7 +1080,7 @@ template <typename R>
 int gw_plain(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {
   GwArgs<R> a = gw_args<R>(p, scale);
   a.y_out = static_cast<cx_t<R>*>(y);
-#define CALL(JJ) launch_degrid<R, JJ, 0>(p, a, s)
+#define CALL(JJ) (p->interp ? launch_degrid<R, JJ, 0, true>(p, a, s) : launch_degrid<R, JJ, 0, false>(p, a, s))
   PR_DISPATCH_J(p->J, CALL)
 #undef CALL
 }
@@ -1090,7 +1094,7 @@ int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
   a.t_out = static_cast<cx_t<R>*>(v.t);
   a.partials = p->partials;
   int rc;
-#define CALL(JJ) launch_degrid<R, JJ, 1>(p, a, s)
+#define CALL(JJ) (p->interp ? launch_degrid<R, JJ, 1, true>(p, a, s) : launch_degrid<R, JJ, 1, false>(p, a, s))
   switch (p->J) {
     case 2: rc = CALL(2); break;
     case 4: rc = CALL(4); break;
@@ -1109,7 +1113,7 @@ template <typename R>
 int gwadj_plain(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s, int parts) {
   GwAdjArgs<R> a = gwadj_args<R>(p, scale);
   a.y_in = static_cast<const cx_t<R>*>(y);
-#define CALL(JJ) launch_grid<R, JJ, 0>(p, a, s, parts)
+#define CALL(JJ) (p->interp ? launch_grid<R, JJ, 0, true>(p, a, s, parts) : launch_grid<R, JJ, 0, false>(p, a, s, parts))
   PR_DISPATCH_J(p->J, CALL)
 #undef CALL
 }
@@ -1122,7 +1126,7 @@ int gwadj_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) 
   a.s_io = static_cast<cx_t<R>*>(v.s);
   a.scalars = v.sums;
   a.varrho = static_cast<R>(v.varrho);
-#define CALL(JJ) launch_grid<R, JJ, 1>(p, a, s)
+#define CALL(JJ) (p->interp ? launch_grid<R, JJ, 1, true>(p, a, s) : launch_grid<R, JJ, 1, false>(p, a, s))
   PR_DISPATCH_J(p->J, CALL)
 #undef CALL
 }
@@ -1137,7 +1141,7 @@ __global__ void zero_cx_kernel(cx_t<R>* a, int64_t n) {
 }  // namespace
 
 int phi_gridding_setup(pr_phi_plan_t* p) {
-  return p->prec == PR_F32 ? setup_prec<float>(p->J) : setup_prec<double>(p->J);
+  return p->prec == PR_F32 ? setup_prec<float>(p->J, p->interp != 0) : setup_prec<double>(p->J, p->interp != 0);
 }
 
 int phi_gw(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {

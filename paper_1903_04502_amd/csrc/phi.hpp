@@ -11,6 +11,7 @@ struct pr_phi_plan_t {
   int nT = 0;       // tiles per grid side
   int nTiles = 0;
   int prec = PR_F32;
+  int interp = 0;   // 0 nearest sample, 1 first-order (linear) lookup
   int64_t M = 0;
   int64_t nItems = 0, nItemsMax = 0;
   int chunk = 0;    // max visibilities per gridding work item

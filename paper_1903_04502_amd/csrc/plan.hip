@@ -315,6 +315,7 @@ int phi_validate(const pr_phi_desc* d) {
   if (d->D < 1 || d->D > 1000000) { set_error("D = %d: must be in [1, 1e6]", d->D); return PR_EINVAL; }
   if (d->M < 0 || d->M >= (int64_t(1) << 31)) { set_error("M = %lld out of range", static_cast<long long>(d->M)); return PR_EINVAL; }
   if (d->prec != PR_F32 && d->prec != PR_F64) { set_error("prec = %d", d->prec); return PR_EINVAL; }
+  if (d->interp != 0 && d->interp != 1) { set_error("interp = %d: must be 0 (nearest) or 1 (linear)", d->interp); return PR_EINVAL; }
   if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32) {
     set_error("tile = %d: must be 0, 8, 16 or 32", d->tile);
     return PR_EINVAL;
@@ -337,6 +338,7 @@ int phi_prepare(pr_phi_plan_t* p, const pr_phi_desc* d) {
   p->D = d->D;
   p->M = d->M;
   p->prec = d->prec;
+  p->interp = d->interp;
   p->T = d->tile ? d->tile : default_tile(d->J, d->prec, d->M, p->K);
   p->P = p->T + p->J - 1;
   p->nT = p->K / p->T;

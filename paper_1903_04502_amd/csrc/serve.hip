@@ -59,6 +59,7 @@ pr_phi_desc phi_desc_of(const pr_job_desc& d) {
   pd.M = d.M;
   pd.prec = d.prec;
   pd.tile = d.tile;
+  pd.interp = d.interp;
   return pd;
 }
 

@@ -1,14 +1,20 @@
 // Interpolation taps of the pre-sampled Kaiser-Bessel kernel (Section "Kernel
-// Pre-Sampling": the kernel is sampled on 0 <= |t| <= J/2 and read by
-// zeroth-order interpolation, i.e. the nearest sample).
+// Pre-Sampling": the kernel is sampled on 0 <= |t| <= J/2 and read either by
+// zeroth-order interpolation, the nearest sample, or by first-order
+// interpolation between the two samples around the tap distance).
 //
 // For a baseline coordinate u (radians per pixel) the continuous grid
 // coordinate is s = u * K / (2 pi), formed in FP64. Tap a (a = 0..J-1) sits
 // on cell floor(s) - J/2 + 1 + a at distance t_a = |s - cell|; it uses table
 // sample round(t_a * D) with ties to the larger distance. With
 // f = (s - floor(s)) * D and m = J/2 - 1 - a this is m*D + round_half_up(f)
-// for m >= 0 and |m|*D - round_half_down(f) for m < 0. All of it is FP64 with
-// FMA contraction disabled, so every caller picks exactly the same samples.
+// for m >= 0 and |m|*D - round_half_down(f) for m < 0. First order: the
+// distance in samples is m*D + f (m >= 0) or |m|*D - f (m < 0); with
+// i = floor of it and phi the rest, the weight is (1 - phi) T[i] + phi T[i+1],
+// i.e. i = m*D + floor(f), phi = f - floor(f) for m >= 0, and for m < 0
+// i = |m|*D - floor(f) - 1, phi = 1 - (f - floor(f)) unless f is whole
+// (then i = |m|*D - f, phi = 0). All of it is FP64 with FMA contraction
+// disabled, so every caller picks exactly the same samples.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +25,8 @@ struct AxisTaps {
   int j0;     // first tap cell, not reduced mod K
   int up;     // round_half_up(f)
   int dn;     // round_half_down(f)
+  int ff;     // floor(f)
+  double r;   // f - floor(f)
 };
 
 __device__ __forceinline__ AxisTaps axis_taps(double u, double kappa, int J, int D) {
@@ -33,6 +41,8 @@ __device__ __forceinline__ AxisTaps axis_taps(double u, double kappa, int J, int
   t.j0 = static_cast<int>(fl) - J / 2 + 1;
   t.up = static_cast<int>(ff) + (r >= 0.5 ? 1 : 0);
   t.dn = static_cast<int>(ff) + (r > 0.5 ? 1 : 0);
+  t.ff = static_cast<int>(ff);
+  t.r = r;
   return t;
 }
 
@@ -40,6 +50,32 @@ __device__ __forceinline__ AxisTaps axis_taps(double u, double kappa, int J, int
 __device__ __forceinline__ int tap_index(const AxisTaps& t, int a, int J, int D) {
   const int m = J / 2 - 1 - a;
   return m >= 0 ? m * D + t.up : (-m) * D - t.dn;
+}
+
+// Weight of tap a from the table (tlen samples): nearest sample, or the
+// first-order interpolation between samples i and i + 1 (i + 1 clamped to the
+// table; it is used only with phi = 0 there).
+template <bool LIN, typename R>
+__device__ __forceinline__ R tap_weight(const R* tab, const AxisTaps& t, int a, int J, int D, int tlen) {
+  if constexpr (!LIN) {
+    (void)tlen;
+    return tab[tap_index(t, a, J, D)];
+  } else {
+    const int m = J / 2 - 1 - a;
+    int i;
+    double ph;
+    if (m >= 0) {
+      i = m * D + t.ff;
+      ph = t.r;
+    } else {
+      const bool frac = t.r > 0.0;
+      i = (-m) * D - t.ff - (frac ? 1 : 0);
+      ph = frac ? 1.0 - t.r : 0.0;
+    }
+    const int i1 = i + 1 < tlen ? i + 1 : tlen - 1;
+    const R p = static_cast<R>(ph);
+    return (R(1) - p) * tab[i] + p * tab[i1];
+  }
 }
 
 __device__ __forceinline__ int mod_pos(int a, int K) {

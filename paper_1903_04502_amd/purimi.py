@@ -31,7 +31,7 @@ class PrError(RuntimeError):
 
 class pr_phi_desc(C.Structure):
     _fields_ = [("n", C.c_int32), ("oversample", C.c_int32), ("J", C.c_int32), ("D", C.c_int32),
-                ("M", C.c_int64), ("prec", C.c_int32), ("tile", C.c_int32)]
+                ("M", C.c_int64), ("prec", C.c_int32), ("tile", C.c_int32), ("interp", C.c_int32)]
 
 
 class pr_admm_params(C.Structure):
@@ -49,7 +49,8 @@ class pr_admm_report(C.Structure):
 class pr_job_desc(C.Structure):
     _fields_ = [("n", C.c_int32), ("J", C.c_int32), ("D", C.c_int32), ("tile", C.c_int32),
                 ("levels", C.c_int32), ("basis_mask", C.c_uint32), ("prec", C.c_int32), ("M", C.c_int64),
-                ("uv", C.c_void_p), ("w", C.c_void_p), ("y", C.c_void_p), ("params", pr_admm_params)]
+                ("uv", C.c_void_p), ("w", C.c_void_p), ("y", C.c_void_p), ("params", pr_admm_params),
+                ("interp", C.c_int32)]
 
 
 _VP, _I32, _I64, _U32, _D, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double, C.c_size_t
@@ -420,7 +421,7 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def tune_tile(n, uv, w=None, J=4, D=2000, oversample=2, prec=None, reps=3) -> int:
+def tune_tile(n, uv, w=None, J=4, D=2000, oversample=2, prec=None, reps=3, interp=0) -> int:
     """Fastest tile side for these baselines, measured by pr_phi_tune."""
     dev = uv.device
     prec = _prec_of(uv.dtype) if prec is None else prec
@@ -428,13 +429,13 @@ def tune_tile(n, uv, w=None, J=4, D=2000, oversample=2, prec=None, reps=3) -> in
     pb = sb = 0
     for T in (8, 16, 32):
         try:
-            p, s_ = pr_phi_plan_sizes(pr_phi_desc(n, oversample, J, D, M, prec, T))
+            p, s_ = pr_phi_plan_sizes(pr_phi_desc(n, oversample, J, D, M, prec, T, interp))
         except PrError:
             continue
         pb, sb = max(pb, p), max(sb, s_)
     cdt = torch.complex64 if prec == PR_F32 else torch.complex128
     vis = torch.empty(max(M, 1), dtype=cdt, device=dev)
-    t, _ = pr_phi_tune(pr_phi_desc(n, oversample, J, D, M, prec, 0), uv.contiguous(),
+    t, _ = pr_phi_tune(pr_phi_desc(n, oversample, J, D, M, prec, 0, interp), uv.contiguous(),
                        None if w is None else w.contiguous(), _workspace(pb, dev), _workspace(sb, dev), vis, reps,
                        _stream(dev))
     return t
@@ -442,17 +443,18 @@ def tune_tile(n, uv, w=None, J=4, D=2000, oversample=2, prec=None, reps=3) -> in
 
 class PhiPlan:
     """Measurement operator plan for one set of baselines (see pr_phi_plan_create).
-    tile: 0 = the library default, "auto" = measured by the autotuner."""
+    tile: 0 = the library default, "auto" = measured by the autotuner.
+    interp: 0 = nearest table sample, 1 = first-order (linear) lookup."""
 
-    def __init__(self, n, uv, w=None, J=4, D=2000, oversample=2, tile=0, prec=None):
+    def __init__(self, n, uv, w=None, J=4, D=2000, oversample=2, tile=0, prec=None, interp=0):
         dev = uv.device
         self.prec = _prec_of(uv.dtype) if prec is None else prec
         self.rdtype = torch.float32 if self.prec == PR_F32 else torch.float64
         self.cdtype = torch.complex64 if self.prec == PR_F32 else torch.complex128
         M = uv.shape[0]
         if tile == "auto":
-            tile = tune_tile(n, uv, w, J, D, oversample, self.prec)
-        self.desc = pr_phi_desc(n, oversample, J, D, M, self.prec, tile)
+            tile = tune_tile(n, uv, w, J, D, oversample, self.prec, interp=interp)
+        self.desc = pr_phi_desc(n, oversample, J, D, M, self.prec, tile, interp)
         self.n, self.M, self.device = n, M, dev
         pb, sb = pr_phi_plan_sizes(self.desc)
         self.persistent = _workspace(pb, dev)
@@ -569,9 +571,10 @@ class Batch:
             self.handle = None
 
 
-def job_desc(n, uv, y, params: pr_admm_params, w=None, J=4, D=2000, levels=3, mask=0x1FF, tile=0) -> pr_job_desc:
+def job_desc(n, uv, y, params: pr_admm_params, w=None, J=4, D=2000, levels=3, mask=0x1FF, tile=0,
+             interp=0) -> pr_job_desc:
     prec = _prec_of(uv.dtype)
-    return pr_job_desc(n, J, D, tile, levels, mask, prec, uv.shape[0], _ptr(uv), _ptr(w), _ptr(y), params)
+    return pr_job_desc(n, J, D, tile, levels, mask, prec, uv.shape[0], _ptr(uv), _ptr(w), _ptr(y), params, interp)
 
 
 class Server:

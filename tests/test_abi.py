@@ -113,3 +113,10 @@ def test_psi_and_admm_checks(P):
     rep = P.pr_admm_report()
     assert L.pr_admm_solve(None, None, None, C.byref(prm), None, None, C.byref(rep), None) == P.PR_EINVAL
     assert L.pr_psi_apply(None, 256, 256, None) == P.PR_EINVAL
+
+
+def test_interp_mode_is_validated(P):
+    assert P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0, 1))[0] > 0
+    with pytest.raises(P.PrError) as e:
+        P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0, 2))
+    assert e.value.code == P.PR_EINVAL
