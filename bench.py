@@ -449,9 +449,25 @@ def main():
         t_admm = a0.elapsed_time(a1) / K_steps
         rep = P.pr_admm_solve(h, psi.handle, y, P.admm_params(eps, gamma, iters=K_steps, op_norm=op_norm),
                               torch.zeros((n, n), dtype=rdt, device=dev), ws, want_report=True)
+        del ws
+        # ---- FISTA iterations (MAP problem, the same gamma, unit step)
+        fws = torch.empty(P.pr_fista_workspace_size(h, psi.handle), dtype=torch.uint8, device=dev)
+        xf = torch.zeros((n, n), dtype=rdt, device=dev)
+        P.pr_fista_solve(h, psi.handle, y, P.fista_params(gamma, 1.0, iters=W_steps, op_norm=op_norm), xf, fws,
+                         want_report=False)
+        xf.zero_()
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        P.pr_fista_solve(h, psi.handle, y, P.fista_params(gamma, 1.0, iters=K_steps, op_norm=op_norm), xf, fws,
+                         want_report=False)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        t_fista = f0.elapsed_time(f1) / K_steps
+        del fws
         return dict(t_fzs=t_fzs, t_gw=t_gw, t_gwa=t_gwa, t_patch=t_patch, t_merge=t_merge, t_fzsa=t_fzsa,
                     t_phi=t_phi, t_adj=t_adj, t_pair=t_pair,
-                    t_admm=t_admm, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
+                    t_admm=t_admm, t_fista=t_fista, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
                     eps=eps, resid=rep.resid_norm, nonfinite=rep.nonfinite, y_plan=yv, perm=perm,
                     plan=plan, x=x)
 
@@ -497,6 +513,7 @@ def main():
         "stage_ms": {"fzs": r32["t_fzs"], "gw": r32["t_gw"], "grid_patches": r32["t_patch"],
                      "grid_merge": r32["t_merge"], "fzs_adjoint": r32["t_fzsa"]},
         "admm_iter_ms_fp32": r32["t_admm"],
+        "fista_iter_ms_fp32": r32["t_fista"],
         "roofline": roof[dom],
         "copy_gbs": copy_gbs,
         "roofline_other": [v for k, v in roof.items() if k != dom],
@@ -505,6 +522,7 @@ def main():
     if r64 is not None:
         res["fp64"] = {"value": M / (r64["t_pair"] * 1e-3), "phi_ms": r64["t_phi"],
                        "phi_adjoint_ms": r64["t_adj"], "admm_iter_ms": r64["t_admm"],
+                       "fista_iter_ms": r64["t_fista"],
                        "stage_ms": {"fzs": r64["t_fzs"], "gw": r64["t_gw"], "grid_patches": r64["t_patch"],
                                     "grid_merge": r64["t_merge"], "fzs_adjoint": r64["t_fzsa"]}}
     if not args.no_cpu_baseline and big:

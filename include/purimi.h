@@ -264,6 +264,46 @@ int pr_admm_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
                   pr_admm_report* rep, void* stream);
 
 /* ------------------------------------------------------------------------
+ * FISTA (Section "Forward-Backward Splitting", Algorithm "FISTA") for the
+ * unconstrained MAP problem
+ *   min gamma (||Psi^dagger x||_1 + iota_{R+}(x)) + 1/2 ||y - Phi x / ||Phi||||^2:
+ * x_0 = xh_0 = x (input), theta_0 = 1; each iteration
+ *   z = xh - lambda Re Phi^dagger (Phi xh / ||Phi|| - y) / ||Phi||;
+ *   x_new = DualFB(z, gamma lambda) (the prox, as in Algorithm 1, d carried);
+ *   theta' = (1 + sqrt(1 + 4 theta^2)) / 2;
+ *   xh = x_new + (theta - 1) / theta' (x_new - x); x = x_new; theta = theta'.
+ * lambda <= 1 keeps the step below 1 / L for the normalised operator (L = 1).
+ * The kernels are those of pr_admm_solve (degridding with the residual
+ * epilogue, gridding, adjoint FFT with the gradient step, DualFB) plus one
+ * momentum pass per iteration.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t iters;       /* iterations (>= 0)                                  */
+  int32_t inner_iters; /* DualFB iterations per prox (>= 1)                  */
+  double gamma;        /* regularisation weight (> 0), or <= 0 with
+                          gamma_factor > 0 (formed on the device as for
+                          pr_admm_params)                                    */
+  double lambda;       /* gradient step (> 0)                                */
+  double eta;          /* DualFB step (> 0)                                  */
+  double op_norm;      /* ||Phi||; <= 0: power method on the device          */
+  double gamma_factor;
+  int32_t norm_iters;  /* power-method steps when op_norm <= 0 (<= 0: 100)   */
+} pr_fista_params;
+
+/* Device workspace bytes for pr_fista_solve on these plans. */
+int pr_fista_workspace_size(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes);
+
+/* Run FISTA. y: complex[M], plan order; x: real[n*n], in: x_0, out: the last
+ * x_k, in place (normalised-operator units, as for pr_admm_solve). rep: if
+ * not NULL, filled on return (resid_norm = ||Phi xh / ||Phi|| - y|| of the last
+ * gradient, rel_var = ||x_k - x_{k-1}|| / ||x_k||) and the call synchronises;
+ * if NULL the call is asynchronous. Errors: PR_EINVAL for NULL arguments or
+ * parameters out of range, PR_EWORKSPACE for a NULL or unaligned workspace. */
+int pr_fista_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
+                   const pr_fista_params* params, void* x, void* workspace,
+                   pr_admm_report* rep, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched solves: many independent solves of Algorithm 1 (frequency channels
  * or imaging jobs of different n and M) stepped together, each one the
  * problem above with its own data (the per-channel / per-node split of the

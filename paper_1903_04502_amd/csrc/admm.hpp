@@ -12,6 +12,7 @@ constexpr int kSumVar = 8;       // 8: ||x_t - x_{t-1}||^2, 9: ||x_t||^2
 constexpr int kSumL1 = 12;       // ||Psi^dagger x||_1
 constexpr int kSumScale = 16;    // 1 / ||Phi|| when kept on the device
 constexpr int kSumGamma = 17;    // gamma when kept on the device
+constexpr int kSumGammaStep = 18; // gamma * step, the FISTA prox threshold, on the device
 constexpr int kSumSlots = 32;
 
 struct AdmmWs {

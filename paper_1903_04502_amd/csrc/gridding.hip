@@ -55,7 +55,7 @@ struct GwArgs {
   int K, T, P, nT, lognT, D, tlen;
   double kappa;
   R scale;
-  const double* scale_dev; // when set, the scale is read from device memory (MODE 1)
+  const double* scale_dev; // when set, the scale is read from device memory
   cx_t<R>* y_out;          // MODE 0
   const cx_t<R>* y_obs;    // MODE 1
   const cx_t<R>* s_in;
@@ -68,7 +68,7 @@ constexpr int kDegridPer = 4;   // visibilities per thread per chunk
 template <typename R, int J, int MODE, bool TAB_LDS, bool LIN>
 __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   using C = cx_t<R>;
-  const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
+  const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int CH = kThreads * kDegridPer;
   extern __shared__ char smem_raw[];
   const int tid = threadIdx.x;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
         if (MODE == 0) {
           a.y_out[k] = yk;
         } else {
-          const C yo = a.y_obs[k], sk = a.s_in[k];
+          const C yo = a.y_obs[k], sk = a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0));
           const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
           a.t_out[k] = t;
           const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
@@ -189,7 +189,7 @@ struct GwAdjArgs {
   int K, T, P, nT, lognT, D, tlen, B;
   double kappa;
   R scale;
-  const double* scale_dev;   // when set, the scale is read from device memory (MODE 1)
+  const double* scale_dev;   // when set, the scale is read from device memory
   const cx_t<R>* y_in;       // MODE 0
   const cx_t<R>* t_in;       // MODE 1: t = v + s - y
   cx_t<R>* s_io;             // MODE 1: multiplier, updated
@@ -247,7 +247,7 @@ constexpr int kGridPer = 4;   // staged visibilities per thread: B <= kThreads *
 template <typename R, int J, int JA, int MODE, bool TAB_LDS, bool LIN>
 __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
-  const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
+  const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int TPC = (J + JA - 1) / JA;
   constexpr int NS = kThreads / (TPC == 3 ? 4 : TPC);
@@ -574,7 +574,7 @@ struct WalkPrefetch {
 template <typename R, int J, int MODE, bool TAB_LDS, bool LIN>
 __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
-  const R scale = (MODE == 1 && a.scale_dev) ? static_cast<R>(*a.scale_dev) : a.scale;
+  const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int WC = WalkChunk<R>::value;
   constexpr int CB = kStagePitch * WC;
@@ -1110,9 +1110,11 @@ int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
 }
 
 template <typename R>
-int gwadj_plain(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s, int parts) {
+int gwadj_plain(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s, int parts,
+                const double* scale_dev = nullptr) {
   GwAdjArgs<R> a = gwadj_args<R>(p, scale);
   a.y_in = static_cast<const cx_t<R>*>(y);
+  a.scale_dev = scale_dev;
 #define CALL(JJ) (p->interp ? launch_grid<R, JJ, 0, true>(p, a, s, parts) : launch_grid<R, JJ, 0, false>(p, a, s, parts))
   PR_DISPATCH_J(p->J, CALL)
 #undef CALL
@@ -1151,6 +1153,12 @@ int phi_gw(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {
 
 int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s) {
   return phi_gw_adjoint_parts(p, y, scale, 3, s);
+}
+
+int phi_gw_adjoint_dev(pr_phi_plan_t* p, const void* y, const double* scale_dev, hipStream_t s) {
+  if (p->nItems == 0) return phi_gw_adjoint_parts(p, y, 1.0, 3, s);
+  return p->prec == PR_F32 ? gwadj_plain<float>(p, y, 1.0, s, 3, scale_dev)
+                           : gwadj_plain<double>(p, y, 1.0, s, 3, scale_dev);
 }
 
 int phi_gw_adjoint_parts(pr_phi_plan_t* p, const void* y, double scale, int parts, hipStream_t s) {

@@ -63,6 +63,8 @@ int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s)
 // The two launches of phi_gw_adjoint: parts bit 0 = per-item patches from the
 // visibilities, bit 1 = merge of the patches into the grid.
 int phi_gw_adjoint_parts(pr_phi_plan_t* p, const void* y, double scale, int parts, hipStream_t s);
+// Gridding with the scale read from device memory (1 / ||Phi|| of a solve).
+int phi_gw_adjoint_dev(pr_phi_plan_t* p, const void* y, const double* scale_dev, hipStream_t s);
 int phi_norm(pr_phi_plan_t* p, int iters, void* vis, double* norm, hipStream_t s);
 
 // Fused ADMM stages (defined with the operator kernels).

@@ -41,6 +41,12 @@ class pr_admm_params(C.Structure):
                 ("gamma_factor", C.c_double), ("norm_iters", C.c_int32)]
 
 
+class pr_fista_params(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("inner_iters", C.c_int32), ("gamma", C.c_double),
+                ("lambda_", C.c_double), ("eta", C.c_double), ("op_norm", C.c_double),
+                ("gamma_factor", C.c_double), ("norm_iters", C.c_int32)]
+
+
 class pr_admm_report(C.Structure):
     _fields_ = [("iters_done", C.c_int32), ("rel_var", C.c_double), ("resid_norm", C.c_double),
                 ("l1_norm", C.c_double), ("op_norm", C.c_double), ("nonfinite", C.c_int32)]
@@ -85,6 +91,9 @@ _SIGS = {
     "pr_admm_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
     "pr_admm_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_admm_params), _VP, _VP,
                                 C.POINTER(pr_admm_report), _VP]),
+    "pr_fista_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
+    "pr_fista_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_fista_params), _VP, _VP,
+                                 C.POINTER(pr_admm_report), _VP]),
     "pr_phi_tune": (C.c_int, [C.POINTER(pr_phi_desc), _VP, _VP, _VP, _VP, _VP, _I32, _VP, C.POINTER(_I32),
                               C.POINTER(_D)]),
     "pr_batch_create": (C.c_int, [_I32, _I32, C.POINTER(_VP)]),
@@ -521,6 +530,19 @@ class PsiPlan:
             self.handle = None
 
 
+def pr_fista_workspace_size(phi, psi) -> int:
+    v = _SZ()
+    _check(lib().pr_fista_workspace_size(phi, psi, C.byref(v)))
+    return v.value
+
+
+def pr_fista_solve(phi, psi, y, params: "pr_fista_params", x, workspace, want_report=True, stream=None):
+    rep = pr_admm_report()
+    _check(lib().pr_fista_solve(phi, psi, _ptr(y), C.byref(params), _ptr(x), _ptr(workspace),
+                                C.byref(rep) if want_report else None, stream if stream is not None else _stream()))
+    return rep if want_report else None
+
+
 def admm_params(eps, gamma, iters=50, inner_iters=1, rho=0.5, varrho=1.0, eta=1.0, rel_tol=0.0, op_norm=0.0,
                 gamma_factor=0.0, norm_iters=0):
     return pr_admm_params(iters, inner_iters, eps, gamma, rho, varrho, eta, rel_tol, op_norm, gamma_factor,
@@ -532,6 +554,18 @@ def admm_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_admm_params, x0=None, w
     ws = _workspace(pr_admm_workspace_size(phi.handle, psi.handle), phi.device)
     x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
     rep = pr_admm_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
+    return x, rep
+
+
+def fista_params(gamma, lam, iters=50, inner_iters=1, eta=1.0, op_norm=0.0, gamma_factor=0.0, norm_iters=0):
+    return pr_fista_params(iters, inner_iters, gamma, lam, eta, op_norm, gamma_factor, norm_iters)
+
+
+def fista_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_fista_params, x0=None, want_report=True):
+    """Run FISTA for the MAP problem; returns (x, report). x is in normalised-operator units."""
+    ws = _workspace(pr_fista_workspace_size(phi.handle, psi.handle), phi.device)
+    x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
+    rep = pr_fista_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
     return x, rep
 
 

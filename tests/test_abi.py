@@ -120,3 +120,13 @@ def test_interp_mode_is_validated(P):
     with pytest.raises(P.PrError) as e:
         P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0, 2))
     assert e.value.code == P.PR_EINVAL
+
+
+def test_fista_argument_checks(P):
+    L = P.lib()
+    rep = P.pr_admm_report()
+    good = P.fista_params(0.1, 1.0)
+    assert L.pr_fista_solve(None, None, None, C.byref(good), None, None, C.byref(rep), None) == P.PR_EINVAL
+    sz = C.c_size_t()
+    assert L.pr_fista_workspace_size(None, None, C.byref(sz)) == P.PR_EINVAL
+    assert P.pr_fista_params._fields_[3][0] == "lambda_"
