@@ -465,9 +465,23 @@ def main():
         torch.cuda.synchronize()
         t_fista = f0.elapsed_time(f1) / K_steps
         del fws
+        # ---- Primal-Dual iterations (the constrained problem: the same eps and gamma)
+        pws = torch.empty(P.pr_pd_workspace_size(h, psi.handle), dtype=torch.uint8, device=dev)
+        xp = torch.zeros((n, n), dtype=rdt, device=dev)
+        P.pr_pd_solve(h, psi.handle, y, P.pd_params(gamma, iters=W_steps, eps=eps, op_norm=op_norm), xp, pws,
+                      want_report=False)
+        xp.zero_()
+        torch.cuda.synchronize()
+        f0.record(stream)
+        P.pr_pd_solve(h, psi.handle, y, P.pd_params(gamma, iters=K_steps, eps=eps, op_norm=op_norm), xp, pws,
+                      want_report=False)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        t_pd = f0.elapsed_time(f1) / K_steps
+        del pws
         return dict(t_fzs=t_fzs, t_gw=t_gw, t_gwa=t_gwa, t_patch=t_patch, t_merge=t_merge, t_fzsa=t_fzsa,
                     t_phi=t_phi, t_adj=t_adj, t_pair=t_pair,
-                    t_admm=t_admm, t_fista=t_fista, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
+                    t_admm=t_admm, t_fista=t_fista, t_pd=t_pd, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
                     eps=eps, resid=rep.resid_norm, nonfinite=rep.nonfinite, y_plan=yv, perm=perm,
                     plan=plan, x=x)
 
@@ -514,6 +528,7 @@ def main():
                      "grid_merge": r32["t_merge"], "fzs_adjoint": r32["t_fzsa"]},
         "admm_iter_ms_fp32": r32["t_admm"],
         "fista_iter_ms_fp32": r32["t_fista"],
+        "primal_dual_iter_ms_fp32": r32["t_pd"],
         "roofline": roof[dom],
         "copy_gbs": copy_gbs,
         "roofline_other": [v for k, v in roof.items() if k != dom],
@@ -522,7 +537,7 @@ def main():
     if r64 is not None:
         res["fp64"] = {"value": M / (r64["t_pair"] * 1e-3), "phi_ms": r64["t_phi"],
                        "phi_adjoint_ms": r64["t_adj"], "admm_iter_ms": r64["t_admm"],
-                       "fista_iter_ms": r64["t_fista"],
+                       "fista_iter_ms": r64["t_fista"], "primal_dual_iter_ms": r64["t_pd"],
                        "stage_ms": {"fzs": r64["t_fzs"], "gw": r64["t_gw"], "grid_patches": r64["t_patch"],
                                     "grid_merge": r64["t_merge"], "fzs_adjoint": r64["t_fzsa"]}}
     if not args.no_cpu_baseline and big:

@@ -304,6 +304,53 @@ int pr_fista_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
                    pr_admm_report* rep, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Primal-Dual splitting (Section "Primal-Dual Splitting", Algorithm
+ * "Primal-Dual Algorithm") for
+ *   min f(Phi x / ||Phi||) + gamma ||Psi^dagger x||_1 + iota_{R+}(x),
+ * f = iota of {v : ||v - y|| <= eps} (PR_PD_BALL, the constrained problem of
+ * Algorithm 1) or f = 1/2 ||v - y||^2 (PR_PD_L2, the MAP problem):
+ *   z' = prox_{sigma f*}(z + sigma Phi xh)   (Moreau's decomposition);
+ *   x' = DualFB(x - tau Phi^dagger z', tau gamma) (d carried, as in Algorithm 1);
+ *   xh = x' + theta (x' - x).
+ * x_0 = xh_0 = x (input), z_0 = 0. tau sigma < 1 is the usual step
+ * condition for the normalised operator. The kernels are those of
+ * pr_admm_solve (the multiplier update reads kappa from the ball or, for
+ * PR_PD_L2, uses sigma / (1 + sigma)), plus one extrapolation pass.
+ * ---------------------------------------------------------------------- */
+enum { PR_PD_BALL = 0, PR_PD_L2 = 1 };
+
+typedef struct {
+  int32_t iters;       /* iterations (>= 0)                                  */
+  int32_t inner_iters; /* DualFB iterations per prox (>= 1)                  */
+  int32_t misfit;      /* PR_PD_BALL or PR_PD_L2                             */
+  double eps;          /* l2-ball radius (PR_PD_BALL, >= 0)                  */
+  double gamma;        /* regularisation weight (> 0), or <= 0 with
+                          gamma_factor > 0 (formed on the device as for
+                          pr_admm_params)                                    */
+  double tau;          /* primal step (> 0)                                  */
+  double sigma;        /* dual step (> 0)                                    */
+  double theta;        /* extrapolation, in [0, 1]                           */
+  double eta;          /* DualFB step (> 0)                                  */
+  double op_norm;      /* ||Phi||; <= 0: power method on the device          */
+  double gamma_factor;
+  int32_t norm_iters;  /* power-method steps when op_norm <= 0 (<= 0: 100)   */
+} pr_pd_params;
+
+/* Device workspace bytes for pr_pd_solve on these plans. */
+int pr_pd_workspace_size(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes);
+
+/* Run the Primal-Dual algorithm. y: complex[M], plan order; x: real[n*n],
+ * in: x_0, out: the last x_k, in place (normalised-operator units). rep: if
+ * not NULL, filled on return (resid_norm = ||Phi xh / ||Phi|| - y|| of the
+ * last iteration, rel_var = ||x_k - x_{k-1}|| / ||x_k||) and the call
+ * synchronises; if NULL the call is asynchronous. Errors: PR_EINVAL for NULL
+ * arguments or parameters out of range, PR_EWORKSPACE for a NULL or
+ * unaligned workspace. */
+int pr_pd_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
+                const pr_pd_params* params, void* x, void* workspace,
+                pr_admm_report* rep, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched solves: many independent solves of Algorithm 1 (frequency channels
  * or imaging jobs of different n and M) stepped together, each one the
  * problem above with its own data (the per-channel / per-node split of the

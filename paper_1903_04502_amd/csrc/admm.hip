@@ -83,6 +83,14 @@ size_t admm_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws,
   return c.bytes();
 }
 
+size_t accel_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws, AdmmWs* out, void** xh) {
+  const size_t base = admm_layout(phi, psi, ws, out);
+  const size_t rs = phi->prec == PR_F32 ? 4 : 8;
+  const size_t extra = (static_cast<size_t>(phi->n) * phi->n * rs + 255) & ~size_t(255);
+  if (xh) *xh = ws ? static_cast<char*>(ws) + base : nullptr;
+  return base + extra;
+}
+
 int admm_job_init(AdmmJob* j, pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, void* x, void* ws,
                   const pr_admm_params& prm, hipStream_t s) {
   j->phi = phi;

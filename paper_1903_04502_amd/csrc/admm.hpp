@@ -41,6 +41,9 @@ struct AdmmJob {
 int admm_check_plans(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi);
 int admm_check_params(const pr_admm_params* prm);
 size_t admm_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws, AdmmWs* out);
+// Workspace of the accelerated solvers (FISTA, primal-dual): the solver's
+// layout followed by the extrapolated image xh (real n*n).
+size_t accel_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws, AdmmWs* out, void** xh);
 // Bind the job and clear its state (s = 0, d = 0, scalars = 0) on the stream.
 int admm_job_init(AdmmJob* j, pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, void* x, void* ws,
                   const pr_admm_params& prm, hipStream_t s);

@@ -8,7 +8,7 @@
 // Algorithm 1. Each iteration runs the solver's kernels: the degridding with
 // the residual epilogue (t = Phi xh - y, FP64 ||t||^2), plain gridding of t,
 // the adjoint FFT with the gradient-step epilogue, the DualFB launches, then
-// one momentum epilogue. 1 / ||Phi|| and gamma stay on the device.
+// one extrapolation pass. 1 / ||Phi|| and gamma stay on the device.
 #include <cmath>
 
 #include "admm.hpp"
@@ -16,27 +16,6 @@
 
 namespace pr {
 namespace {
-
-// x_new from xb; xh = x_new + c (x_new - x); x = x_new (each element read
-// before it is written).
-template <typename R>
-__global__ void momentum_kernel(R* x, const R* __restrict__ xb, R* __restrict__ xh, int64_t n2, R c) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n2;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const R xn = xb[i], xo = x[i];
-    xh[i] = xn + c * (xn - xo);
-    x[i] = xn;
-  }
-}
-
-template <typename R>
-__global__ void copy_kernel(R* dst, const R* __restrict__ src, int64_t n) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    dst[i] = src[i];
-}
-
-__global__ void scale_slot_kernel(const double* src, double f, double* dst) { *dst = *src * f; }
 
 pr_admm_params as_admm(const pr_fista_params& f) {
   pr_admm_params p{};
@@ -54,16 +33,6 @@ pr_admm_params as_admm(const pr_fista_params& f) {
   return p;
 }
 
-}  // namespace
-
-size_t fista_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws, AdmmWs* w, void** xh) {
-  const size_t base = admm_layout(phi, psi, ws, w);
-  const size_t rs = phi->prec == PR_F32 ? 4 : 8;
-  const size_t extra = (static_cast<size_t>(phi->n) * phi->n * rs + 255) & ~size_t(255);
-  if (xh) *xh = ws ? static_cast<char*>(ws) + base : nullptr;
-  return base + extra;
-}
-
 int fista_check_params(const pr_fista_params* p) {
   if (p->iters < 0) { set_error("iters < 0"); return PR_EINVAL; }
   if (p->inner_iters < 1) { set_error("inner_iters < 1"); return PR_EINVAL; }
@@ -77,26 +46,21 @@ int fista_check_params(const pr_fista_params* p) {
 
 int fista_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_fista_params& fp, void* x, void* ws,
                 pr_admm_report* rep, hipStream_t s) {
-  const pr_admm_params prm = as_admm(fp);
   AdmmJob j;
   void* xh = nullptr;
-  PR_TRY(admm_job_init(&j, phi, psi, y, x, ws, prm, s));
-  fista_layout(phi, psi, ws, &j.w, &xh);
+  PR_TRY(admm_job_init(&j, phi, psi, y, x, ws, as_admm(fp), s));
+  accel_layout(phi, psi, ws, &j.w, &xh);
   PR_TRY(admm_device_setup(&j, s));
   const int prec = phi->prec;
   const int64_t n2 = static_cast<int64_t>(phi->n) * phi->n;
-  const int G = grid_for(n2, 256, 4096);
   double* sums = j.w.sums;
-  // prox threshold gamma * lambda (device when gamma is)
+  // prox threshold gamma * lambda (on the device when gamma is)
   const double* thr_dev = nullptr;
   if (j.device_gamma) {
-    scale_slot_kernel<<<1, 1, 0, s>>>(sums + kSumGamma, fp.lambda, sums + kSumGammaStep);
-    PR_TRY_LAUNCH();
+    PR_TRY(scale_scalar(sums + kSumGamma, fp.lambda, sums + kSumGammaStep, s));
     thr_dev = sums + kSumGammaStep;
   }
-  if (prec == PR_F32) copy_kernel<float><<<G, 256, 0, s>>>(static_cast<float*>(xh), static_cast<const float*>(x), n2);
-  else copy_kernel<double><<<G, 256, 0, s>>>(static_cast<double*>(xh), static_cast<const double*>(x), n2);
-  PR_TRY_LAUNCH();
+  PR_TRY(copy_real(xh, x, n2, prec, s));
   AdmmVis av{};
   av.y = y;
   av.s = nullptr;               // t = Phi xh - y
@@ -106,7 +70,6 @@ int fista_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_
   av.varrho = 1.0;
   av.scale_dev = sums + kSumScale;
   double theta = 1.0;
-  int done = 0;
   for (int it = 0; it < fp.iters; ++it) {
     PR_TRY(phi_fzs(phi, xh, s));
     PR_TRY(phi_gw_admm(phi, av, 1.0, s));
@@ -115,26 +78,19 @@ int fista_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_
     for (int k = 0; k < fp.inner_iters; ++k) {
       PR_TRY(psi_dual_update(psi, j.w.zbar, 0, j.w.d, fp.gamma * fp.lambda, fp.eta, s, thr_dev));
       const bool last = k == fp.inner_iters - 1;
-      void* out = last ? j.w.xb : j.w.zbar;
-      PR_TRY(psi_synthesis_step(psi, j.w.d, j.w.xt, out, last ? x : nullptr, j.w.partials, sums + kSumVar, s));
+      PR_TRY(psi_synthesis_step(psi, j.w.d, j.w.xt, last ? j.w.xb : j.w.zbar, last ? x : nullptr, j.w.partials,
+                                sums + kSumVar, s));
     }
     const double theta_new = (1.0 + std::sqrt(1.0 + 4.0 * theta * theta)) / 2.0;
-    const double c = (theta - 1.0) / theta_new;
-    if (prec == PR_F32)
-      momentum_kernel<float><<<G, 256, 0, s>>>(static_cast<float*>(x), static_cast<const float*>(j.w.xb),
-                                               static_cast<float*>(xh), n2, static_cast<float>(c));
-    else
-      momentum_kernel<double><<<G, 256, 0, s>>>(static_cast<double*>(x), static_cast<const double*>(j.w.xb),
-                                                static_cast<double*>(xh), n2, c);
-    PR_TRY_LAUNCH();
+    PR_TRY(extrapolate(x, j.w.xb, xh, n2, prec, (theta - 1.0) / theta_new, s));
     theta = theta_new;
-    ++done;
+    ++j.iters_done;
   }
-  j.iters_done = done;
   if (rep) PR_TRY(admm_report(&j, rep, s));
   return PR_OK;
 }
 
+}  // namespace
 }  // namespace pr
 
 using namespace pr;
@@ -147,7 +103,7 @@ int pr_fista_workspace_size(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes) {
   PR_NONNULL(psi);
   PR_NONNULL(bytes);
   PR_TRY(admm_check_plans(phi, psi));
-  *bytes = fista_layout(phi, psi, nullptr, nullptr, nullptr);
+  *bytes = accel_layout(phi, psi, nullptr, nullptr, nullptr);
   return PR_OK;
 }
 

@@ -195,6 +195,7 @@ struct GwAdjArgs {
   cx_t<R>* s_io;             // MODE 1: multiplier, updated
   const double* scalars;     // MODE 1: ball scale at kSlotKappa
   R varrho;
+  R vr_coef;                 // MODE 1: gridded q = vr_coef (v - r) + s' (1 Algorithm 1, 0 primal-dual)
   cx_t<R>* patches;
 };
 
@@ -353,13 +354,13 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
           val = ry[j];
         } else {
           // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
-          // r = y + kappa t, s' = s + varrho (v - r), q = v - r + s'
+          // r = y + kappa t, s' = s + varrho (v - r), q = vr_coef (v - r) + s'
           const C t = ry[j], sk = rs[j];
           const R omk = R(1) - kappa_ball;
           const C vr = cmk<C>(omk * t.x - sk.x, omk * t.y - sk.y);   // v - r
           const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
           a.s_io[k] = sn;
-          val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
+          val = cmk<C>(a.vr_coef * vr.x + sn.x, a.vr_coef * vr.y + sn.y);
         }
         const R ws = rw[j] * scale;
         val = cmk<C>(val.x * ws, val.y * ws);
@@ -640,12 +641,12 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         val = pf.val[r];
       } else {
         // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
-        // r = y + kappa t, s' = s + varrho (v - r), q = v - r + s'
+        // r = y + kappa t, s' = s + varrho (v - r), q = vr_coef (v - r) + s'
         const C tt = pf.val[r], sk = pf.s[MODE == 1 ? r : 0];
         const R omk = R(1) - kappa_ball;
         const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
         sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
-        val = cmk<C>(vr.x + sn.x, vr.y + sn.y);
+        val = cmk<C>(a.vr_coef * vr.x + sn.x, a.vr_coef * vr.y + sn.y);
       }
       const R ws = pf.w[r] * scale;
       const C uvr = pf.uv[r];
@@ -858,7 +859,8 @@ __global__ void merge_patches_kernel(const cx_t<R>* __restrict__ patches, const 
 }
 
 // Sum the ADMM degridding partials in a fixed order and form the ball scale.
-__global__ void ball_scale_kernel(const double* partials, int nblocks, double eps, double* scalars) {
+__global__ void ball_scale_kernel(const double* partials, int nblocks, double eps, double kappa_fixed,
+                                  double* scalars) {
   __shared__ double sh[kThreads];
   double t2 = 0, r2 = 0;
   for (int i = threadIdx.x; i < nblocks; i += kThreads) {
@@ -871,7 +873,7 @@ __global__ void ball_scale_kernel(const double* partials, int nblocks, double ep
     const double nt = sqrt(t2);
     scalars[kSlotT2] = t2;
     scalars[kSlotR2] = r2;
-    scalars[kSlotKappa] = nt <= eps ? 1.0 : eps / nt;
+    scalars[kSlotKappa] = kappa_fixed >= 0.0 ? kappa_fixed : (nt <= eps ? 1.0 : eps / nt);
     if (!isfinite(t2) || !isfinite(r2)) scalars[kSlotNonfinite] = 1.0;
   }
 }
@@ -1104,7 +1106,7 @@ int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
   }
 #undef CALL
   if (rc != PR_OK) return rc;
-  ball_scale_kernel<<<1, kThreads, 0, s>>>(p->partials, degrid_blocks(p), v.eps, v.sums);
+  ball_scale_kernel<<<1, kThreads, 0, s>>>(p->partials, degrid_blocks(p), v.eps, v.kappa_fixed, v.sums);
   PR_TRY_LAUNCH();
   return PR_OK;
 }
@@ -1128,6 +1130,7 @@ int gwadj_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) 
   a.s_io = static_cast<cx_t<R>*>(v.s);
   a.scalars = v.sums;
   a.varrho = static_cast<R>(v.varrho);
+  a.vr_coef = static_cast<R>(v.vr_coef);
 #define CALL(JJ) (p->interp ? launch_grid<R, JJ, 1, true>(p, a, s) : launch_grid<R, JJ, 1, false>(p, a, s))
   PR_DISPATCH_J(p->J, CALL)
 #undef CALL

@@ -121,6 +121,26 @@ __global__ void fill_kernel(R* a, int64_t len, R v) {
     a[i] = v;
 }
 
+template <typename R>
+__global__ void copy_kernel(R* dst, const R* __restrict__ src, int64_t len) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+// xh = xb + c (xb - x); x = xb
+template <typename R>
+__global__ void extrapolate_kernel(R* x, const R* __restrict__ xb, R* __restrict__ xh, int64_t len, R c) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const R xn = xb[i], xo = x[i];
+    xh[i] = xn + c * (xn - xo);
+    x[i] = xn;
+  }
+}
+
+__global__ void scale_scalar_kernel(const double* src, double f, double* dst) { *dst = *src * f; }
+
 // a = b / sqrt(*s2)
 template <typename R>
 __global__ void normalise_kernel(R* a, const R* b, int64_t len, const double* s2) {
@@ -237,6 +257,34 @@ int normalise(void* a, const void* b, int64_t len, int prec, const double* s2, h
     normalise_kernel<float><<<G, kThreads, 0, s>>>(static_cast<float*>(a), static_cast<const float*>(b), len, s2);
   else
     normalise_kernel<double><<<G, kThreads, 0, s>>>(static_cast<double*>(a), static_cast<const double*>(b), len, s2);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int copy_real(void* dst, const void* src, int64_t len, int prec, hipStream_t s) {
+  const int G = grid_for(len, kThreads, 8192);
+  if (prec == PR_F32)
+    copy_kernel<float><<<G, kThreads, 0, s>>>(static_cast<float*>(dst), static_cast<const float*>(src), len);
+  else
+    copy_kernel<double><<<G, kThreads, 0, s>>>(static_cast<double*>(dst), static_cast<const double*>(src), len);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int extrapolate(void* x, const void* xb, void* xh, int64_t len, int prec, double c, hipStream_t s) {
+  const int G = grid_for(len, kThreads, 8192);
+  if (prec == PR_F32)
+    extrapolate_kernel<float><<<G, kThreads, 0, s>>>(static_cast<float*>(x), static_cast<const float*>(xb),
+                                                     static_cast<float*>(xh), len, static_cast<float>(c));
+  else
+    extrapolate_kernel<double><<<G, kThreads, 0, s>>>(static_cast<double*>(x), static_cast<const double*>(xb),
+                                                      static_cast<double*>(xh), len, c);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int scale_scalar(const double* src, double f, double* dst, hipStream_t s) {
+  scale_scalar_kernel<<<1, 1, 0, s>>>(src, f, dst);
   PR_TRY_LAUNCH();
   return PR_OK;
 }

@@ -25,5 +25,12 @@ int normalise(void* a, const void* b, int64_t len, int prec, const double* s2, h
 // Power method of the plan (iters applications of Phi^dagger Phi from the
 // constant image) leaving 1 / ||Phi|| in device memory; no host read-back.
 int phi_norm_device(pr_phi_plan_t* p, int iters, void* vis, double* inv_norm, hipStream_t s);
+// dst = src over len real values.
+int copy_real(void* dst, const void* src, int64_t len, int prec, hipStream_t s);
+// Extrapolation of an accelerated iteration: xh = xb + c (xb - x), then x = xb
+// (each element of x read before it is written).
+int extrapolate(void* x, const void* xb, void* xh, int64_t len, int prec, double c, hipStream_t s);
+// *dst = *src * f (device scalars).
+int scale_scalar(const double* src, double f, double* dst, hipStream_t s);
 
 }  // namespace pr

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpurimi.so")
 
 PR_OK, PR_EINVAL, PR_EWORKSPACE, PR_EHIP, PR_EUNSUPPORTED = 0, 1, 2, 3, 4
 PR_F32, PR_F64 = 0, 1
+PR_PD_BALL, PR_PD_L2 = 0, 1
 
 
 class PrError(RuntimeError):
@@ -45,6 +46,13 @@ class pr_fista_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("inner_iters", C.c_int32), ("gamma", C.c_double),
                 ("lambda_", C.c_double), ("eta", C.c_double), ("op_norm", C.c_double),
                 ("gamma_factor", C.c_double), ("norm_iters", C.c_int32)]
+
+
+class pr_pd_params(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("inner_iters", C.c_int32), ("misfit", C.c_int32), ("eps", C.c_double),
+                ("gamma", C.c_double), ("tau", C.c_double), ("sigma", C.c_double), ("theta", C.c_double),
+                ("eta", C.c_double), ("op_norm", C.c_double), ("gamma_factor", C.c_double),
+                ("norm_iters", C.c_int32)]
 
 
 class pr_admm_report(C.Structure):
@@ -94,6 +102,8 @@ _SIGS = {
     "pr_fista_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
     "pr_fista_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_fista_params), _VP, _VP,
                                  C.POINTER(pr_admm_report), _VP]),
+    "pr_pd_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
+    "pr_pd_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_pd_params), _VP, _VP, C.POINTER(pr_admm_report), _VP]),
     "pr_phi_tune": (C.c_int, [C.POINTER(pr_phi_desc), _VP, _VP, _VP, _VP, _VP, _I32, _VP, C.POINTER(_I32),
                               C.POINTER(_D)]),
     "pr_batch_create": (C.c_int, [_I32, _I32, C.POINTER(_VP)]),
@@ -543,6 +553,19 @@ def pr_fista_solve(phi, psi, y, params: "pr_fista_params", x, workspace, want_re
     return rep if want_report else None
 
 
+def pr_pd_workspace_size(phi, psi) -> int:
+    v = _SZ()
+    _check(lib().pr_pd_workspace_size(phi, psi, C.byref(v)))
+    return v.value
+
+
+def pr_pd_solve(phi, psi, y, params: "pr_pd_params", x, workspace, want_report=True, stream=None):
+    rep = pr_admm_report()
+    _check(lib().pr_pd_solve(phi, psi, _ptr(y), C.byref(params), _ptr(x), _ptr(workspace),
+                             C.byref(rep) if want_report else None, stream if stream is not None else _stream()))
+    return rep if want_report else None
+
+
 def admm_params(eps, gamma, iters=50, inner_iters=1, rho=0.5, varrho=1.0, eta=1.0, rel_tol=0.0, op_norm=0.0,
                 gamma_factor=0.0, norm_iters=0):
     return pr_admm_params(iters, inner_iters, eps, gamma, rho, varrho, eta, rel_tol, op_norm, gamma_factor,
@@ -566,6 +589,21 @@ def fista_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_fista_params, x0=None,
     ws = _workspace(pr_fista_workspace_size(phi.handle, psi.handle), phi.device)
     x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
     rep = pr_fista_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
+    return x, rep
+
+
+def pd_params(gamma, tau=0.5, sigma=1.0, theta=1.0, iters=50, misfit=None, eps=0.0, inner_iters=1, eta=1.0,
+              op_norm=0.0, gamma_factor=0.0, norm_iters=0):
+    """misfit: PR_PD_BALL (default) or PR_PD_L2."""
+    return pr_pd_params(iters, inner_iters, PR_PD_BALL if misfit is None else misfit, eps, gamma, tau, sigma, theta,
+                        eta, op_norm, gamma_factor, norm_iters)
+
+
+def pd_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_pd_params, x0=None, want_report=True):
+    """Run the Primal-Dual algorithm; returns (x, report). x is in normalised-operator units."""
+    ws = _workspace(pr_pd_workspace_size(phi.handle, psi.handle), phi.device)
+    x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
+    rep = pr_pd_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
     return x, rep
 
 
