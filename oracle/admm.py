@@ -13,6 +13,10 @@ DualFB starts from zbar = P_C(z) and repeats
   d <- (1/eta) (I - S_gamma)(eta d + Psi^dagger zbar); zbar = P_C(z - Psi d),
 returning zbar. d is carried over between outer iterations (warm start).
 
+Local variant (Section "Local Fidelity Constraint ADMM", eq. proj-L2-local):
+the visibilities are split into sections y_j with radii epsilon_j and the r
+step projects each section onto its own ball; the rest is unchanged.
+
 Readings: the DualFB update of zbar subtracts Psi d from the fixed input z
 (the distributed versions, Algorithms 2 and 3, write plain z there); initial
 x = 0, s = 0, d = 0; the objective line of the distributed prox section is
@@ -32,7 +36,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .prox import clip_magnitude, proj_l2ball, proj_positive, l2_distance
+from .prox import clip_magnitude, proj_l2ball, proj_l2balls_local, proj_positive, l2_distance
 
 
 @dataclass
@@ -63,11 +67,14 @@ def dual_fb(z, d, gamma: float, eta: float, psi, psi_adj, inner_iters: int,
     return zbar, d
 
 
-def admm(y, phi, phi_adj, psi, psi_adj, eps: float, p: AdmmParams, x0, d0=None):
+def admm(y, phi, phi_adj, psi, psi_adj, eps, p: AdmmParams, x0, d0=None, sections=None):
     """Run ``p.iters`` outer iterations; returns (x, s, d, report).
 
     phi / phi_adj are the (normalised) measurement operator and its real-image
-    adjoint; psi / psi_adj the dictionary synthesis and analysis.
+    adjoint; psi / psi_adj the dictionary synthesis and analysis. With
+    ``sections`` (the section of each visibility) ``eps`` holds one radius per
+    section and r is the independent projection onto each section's ball
+    (Section "Local Fidelity Constraint ADMM"); otherwise one global ball.
     """
     x = np.array(x0, dtype=np.float64, copy=True)
     y = np.asarray(y, dtype=np.complex128)
@@ -76,7 +83,7 @@ def admm(y, phi, phi_adj, psi, psi_adj, eps: float, p: AdmmParams, x0, d0=None):
     rep = AdmmReport()
     for _ in range(p.iters):
         v = phi(x)
-        r = proj_l2ball(v + s, y, eps)
+        r = proj_l2ball(v + s, y, eps) if sections is None else proj_l2balls_local(v + s, y, eps, sections)
         s = s + p.varrho * (v - r)
         xt = x - p.rho * phi_adj(v - r + s)
         x_new, d = dual_fb(xt, d, p.gamma, p.eta, psi, psi_adj, p.inner_iters)

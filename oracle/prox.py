@@ -50,3 +50,18 @@ def proj_l2ball(x, z, eps: float):
     if dist <= eps:
         return x.copy()
     return z + (eps / dist) * (x - z)
+
+
+def proj_l2balls_local(x, z, eps_j, sections):
+    """Independent projections onto the balls ||x_j - z_j|| <= eps_j of the
+    sections j (eq. proj-L2-local, Section "Local Fidelity Constraint ADMM");
+    ``sections[k]`` is the section of element k."""
+    x = np.asarray(x)
+    z = np.asarray(z)
+    sections = np.asarray(sections)
+    out = x.copy()
+    for j, e in enumerate(np.asarray(eps_j, dtype=np.float64)):
+        idx = np.nonzero(sections == j)[0]
+        if idx.size:
+            out[idx] = proj_l2ball(x[idx], z[idx], float(e))
+    return out

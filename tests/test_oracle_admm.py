@@ -95,3 +95,72 @@ def test_c0_sized_run_invariants():
     # the reconstruction (in physical units x / ||Phi||) is closer to the sky than the zero image
     err = np.linalg.norm(x / nrm - x_true) / np.linalg.norm(x_true)
     assert err < 0.5
+
+
+def test_local_ball_projection_is_the_nearest_point_of_the_product_of_balls():
+    rng = np.random.default_rng(21)
+    M, nsec = 40, 4
+    sec = rng.integers(0, nsec, M)
+    eps_j = rng.uniform(0.3, 1.5, nsec)
+    z = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    x = z + 2.0 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    p = prox.proj_l2balls_local(x, z, eps_j, sec)
+    for j in range(nsec):
+        idx = sec == j
+        assert np.linalg.norm(p[idx] - z[idx]) <= eps_j[j] * (1 + 1e-14)
+    # brute force: no sampled point of the product set is closer to x
+    best = np.linalg.norm(p - x)
+    for _ in range(2000):
+        q = z.copy()
+        for j in range(nsec):
+            idx = np.nonzero(sec == j)[0]
+            d = rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)
+            q[idx] = z[idx] + d * (eps_j[j] * rng.uniform() ** (1.0 / (2 * idx.size)) / np.linalg.norm(d))
+        assert np.linalg.norm(q - x) >= best - 1e-12
+
+
+def test_admm_local_balls_identity_operator_closed_form():
+    # min ||x||_1 s.t. ||x_j - y_j|| <= eps_j per section, x >= 0: separable,
+    # x_j = max(y_j - tau_j, 0) with ||x_j - y_j|| = eps_j
+    rng = np.random.default_rng(22)
+    N, nsec = 64, 3
+    y = rng.uniform(0.2, 2.0, N)
+    sec = rng.integers(0, nsec, N)
+    eps_j = np.array([0.6, 1.0, 0.8])
+    xstar = np.zeros(N)
+    for j in range(nsec):
+        idx = sec == j
+        xstar[idx] = np.maximum(y[idx] - _bisect_tau(y[idx], eps_j[j]), 0.0)
+    ident = lambda x: x.astype(complex)
+    p = admm.AdmmParams(gamma=0.1, iters=600, inner_iters=1)
+    x, s, d, rep = admm.admm(y.astype(complex), ident, np.real, lambda a: a[0], lambda x: x[None],
+                             eps_j, p, np.zeros(N), sections=sec)
+    assert np.max(np.abs(x - xstar)) < 1e-6
+    for j in range(nsec):
+        assert np.linalg.norm((x - y)[sec == j]) == pytest.approx(eps_j[j], rel=1e-6)
+
+
+def test_admm_local_balls_are_invariant_to_the_visibility_order():
+    rng = np.random.default_rng(23)
+    M, N, nsec = 30, 6, 3
+    A = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
+    A /= np.linalg.norm(A, 2)
+    y = A @ np.abs(rng.standard_normal(N)) + 0.05 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    sec = rng.integers(0, nsec, M)
+    eps_j = np.array([0.05, 0.1, 0.08])
+    ident = lambda v: np.array(v, dtype=np.float64)
+    p = admm.AdmmParams(gamma=0.01, iters=40)
+
+    def run(perm):
+        Ap = A[perm]
+        return admm.admm(y[perm], lambda v: Ap @ v, lambda r: np.real(Ap.conj().T @ r), ident, ident,
+                         eps_j, p, np.zeros(N), sections=sec[perm])[0]
+
+    x0 = run(np.arange(M))
+    x1 = run(rng.permutation(M))
+    assert np.max(np.abs(x0 - x1)) < 1e-12
+    # one section equals the global ball
+    xg = admm.admm(y, lambda v: A @ v, lambda r: np.real(A.conj().T @ r), ident, ident, 0.1, p, np.zeros(N))[0]
+    xl = admm.admm(y, lambda v: A @ v, lambda r: np.real(A.conj().T @ r), ident, ident, [0.1], p, np.zeros(N),
+                   sections=np.zeros(M, dtype=int))[0]
+    assert np.array_equal(xg, xl)
