@@ -264,6 +264,44 @@ int pr_admm_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
                   pr_admm_report* rep, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Local l2-ball constraints (Section "Local Fidelity Constraint ADMM",
+ * eq. proj-L2-local): the visibilities are split into nsec sections, each
+ * with its own ball ||Phi_j x / ||Phi|| - y_j|| <= eps_j, and the r step of
+ * Algorithm 1 projects every section on its own ball (the paper's sections
+ * are equal-count bins of baseline length; any assignment is accepted).
+ * A pr_balls object holds the sections' order and the per-section state.
+ * section: int32[M] on the device, plan order (see pr_phi_plan_perm), values
+ * in [0, nsec); it is copied into the persistent workspace.
+ * Workspaces: persistent (kept) and scratch (used during create only), both
+ * caller-owned and 256-byte aligned, sizes from pr_balls_sizes. One solve at
+ * a time per object (the radii and the section norms live in it).
+ * ---------------------------------------------------------------------- */
+typedef struct pr_balls_t* pr_balls;
+
+/* M in [0, 2^31), nsec in [1, 2^24]. */
+int pr_balls_sizes(int64_t M, int32_t nsec, size_t* persistent_bytes, size_t* scratch_bytes);
+/* Sorts the plan positions by section (stable) and synchronises `stream`.
+ * PR_EINVAL if a section id is out of range, PR_EWORKSPACE for a bad
+ * workspace. */
+int pr_balls_create(int64_t M, int32_t nsec, const int32_t* section, void* persistent,
+                    size_t persistent_bytes, void* scratch, size_t scratch_bytes,
+                    void* stream, pr_balls* out);
+int pr_balls_destroy(pr_balls b);
+/* ||t_j|| = ||v_j + s_j - y_j|| of the last iteration of the last solve, per
+ * section, into the HOST array norms[nsec] (synchronises `stream`). */
+int pr_balls_norms(pr_balls b, double* norms, void* stream);
+
+/* Algorithm 1 with the local balls: as pr_admm_solve (same workspace size,
+ * pr_admm_workspace_size) with params->eps ignored and eps: HOST double[nsec],
+ * the radii (copied to the device; the call synchronises once at the start).
+ * Per iteration the degridding forms t, a fixed-order FP64 reduction gives
+ * ||t_j|| per section, one pass applies the projections and the multiplier
+ * update, and the plain gridding grids the result. */
+int pr_admm_local_solve(pr_phi_plan phi, pr_psi_plan psi, pr_balls balls, const void* y,
+                        const pr_admm_params* params, const double* eps, void* x,
+                        void* workspace, pr_admm_report* rep, void* stream);
+
+/* ------------------------------------------------------------------------
  * FISTA (Section "Forward-Backward Splitting", Algorithm "FISTA") for the
  * unconstrained MAP problem
  *   min gamma (||Psi^dagger x||_1 + iota_{R+}(x)) + 1/2 ||y - Phi x / ||Phi||||^2:

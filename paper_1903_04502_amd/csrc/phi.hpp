@@ -55,6 +55,13 @@ int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s);
 // device), so that later launches, also under stream capture, set nothing.
 int phi_gridding_setup(pr_phi_plan_t* p);
 
+// Stable LSD radix sort of M (key, value) pairs on the low `bits` bits of the
+// keys, ping-ponging between (k0, v0) and (k1, v1); *kout / *vout name the
+// pair holding the result. tmp: sort_tmp_words(M) words.
+size_t sort_tmp_words(int64_t M);
+int sort_pairs_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* tmp, int64_t M, int bits,
+                   hipStream_t s, uint32_t** kout, uint32_t** vout);
+
 // Operator stages.
 int phi_fzs(pr_phi_plan_t* p, const void* x, hipStream_t s);
 int phi_fzs_adjoint(pr_phi_plan_t* p, void* x, hipStream_t s);

@@ -223,6 +223,35 @@ static int scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t
   return PR_OK;
 }
 
+size_t sort_tmp_words(int64_t M) {
+  const int64_t m = M > 0 ? M : 1;
+  const int64_t hn = 256 * ((m + kSortChunk - 1) / kSortChunk);
+  // histogram (rounded up to 64 words), then the scan's scratch and its slack
+  return static_cast<size_t>(hn + 64 + scan_tmp_words(hn) + 64);
+}
+
+int sort_pairs_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* tmp, int64_t M, int bits,
+                   hipStream_t s, uint32_t** kout, uint32_t** vout) {
+  const int nblocks = static_cast<int>((M + kSortChunk - 1) / kSortChunk);
+  uint32_t* hist = tmp;
+  uint32_t* scan_tmp = tmp + ((int64_t(256) * nblocks + 63) / 64) * 64;
+  uint32_t *kin = k0, *ko = k1, *vin = v0, *vo = v1;
+  if (M > 0) {
+    for (int shift = 0; shift < bits; shift += 8) {
+      radix_upsweep<<<nblocks, kSortThreads, 0, s>>>(kin, M, shift, nblocks, hist);
+      PR_TRY_LAUNCH();
+      PR_TRY(scan_exclusive(hist, hist, int64_t(256) * nblocks, scan_tmp, s));
+      radix_downsweep<<<nblocks, kSortThreads, 0, s>>>(kin, vin, ko, vo, hist, M, shift, nblocks);
+      PR_TRY_LAUNCH();
+      std::swap(kin, ko);
+      std::swap(vin, vo);
+    }
+  }
+  *kout = kin;
+  *vout = vin;
+  return PR_OK;
+}
+
 // ---------------------------------------------------------------------------
 // work list
 // ---------------------------------------------------------------------------

@@ -14,6 +14,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -104,6 +105,12 @@ _SIGS = {
                                  C.POINTER(pr_admm_report), _VP]),
     "pr_pd_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
     "pr_pd_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_pd_params), _VP, _VP, C.POINTER(pr_admm_report), _VP]),
+    "pr_balls_sizes": (C.c_int, [C.c_int64, _I32, C.POINTER(_SZ), C.POINTER(_SZ)]),
+    "pr_balls_create": (C.c_int, [C.c_int64, _I32, _VP, _VP, _SZ, _VP, _SZ, _VP, C.POINTER(_VP)]),
+    "pr_balls_destroy": (C.c_int, [_VP]),
+    "pr_balls_norms": (C.c_int, [_VP, C.POINTER(_D), _VP]),
+    "pr_admm_local_solve": (C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(pr_admm_params), C.POINTER(_D), _VP, _VP,
+                                      C.POINTER(pr_admm_report), _VP]),
     "pr_phi_tune": (C.c_int, [C.POINTER(pr_phi_desc), _VP, _VP, _VP, _VP, _VP, _I32, _VP, C.POINTER(_I32),
                               C.POINTER(_D)]),
     "pr_batch_create": (C.c_int, [_I32, _I32, C.POINTER(_VP)]),
@@ -605,6 +612,49 @@ def pd_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_pd_params, x0=None, want_
     x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
     rep = pr_pd_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
     return x, rep
+
+
+class Balls:
+    """Sections of a plan's visibilities for the local l2-ball constraints.
+    section: int32 device tensor [M] in plan order (copied by the library)."""
+
+    def __init__(self, phi: PhiPlan, section, nsec: int):
+        L = lib()
+        assert section.dtype == torch.int32 and section.numel() == phi.M and section.is_contiguous()
+        pb, sb = _SZ(), _SZ()
+        _check(L.pr_balls_sizes(phi.M, nsec, C.byref(pb), C.byref(sb)))
+        self.persistent = _workspace(pb.value, phi.device)
+        scratch = _workspace(sb.value, phi.device)
+        self.nsec, self.M = nsec, phi.M
+        h = _VP()
+        _check(L.pr_balls_create(phi.M, nsec, _ptr(section), _ptr(self.persistent), pb.value, _ptr(scratch),
+                                 sb.value, _stream(), C.byref(h)))
+        self.handle = h.value
+
+    def norms(self):
+        out = (_D * self.nsec)()
+        _check(lib().pr_balls_norms(self.handle, out, _stream()))
+        return np.array(out[:], dtype=np.float64)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.pr_balls_destroy(h)
+            self.handle = None
+
+
+def admm_local_solve(phi: PhiPlan, psi: PsiPlan, balls: Balls, y, params: pr_admm_params, eps, x0=None,
+                     want_report=True):
+    """Algorithm 1 with one l2 ball per section (radii ``eps``, one per section); returns (x, report)."""
+    ws = _workspace(pr_admm_workspace_size(phi.handle, psi.handle), phi.device)
+    x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    assert e.size == balls.nsec
+    rep = pr_admm_report()
+    _check(lib().pr_admm_local_solve(phi.handle, psi.handle, balls.handle, _ptr(y), C.byref(params),
+                                     e.ctypes.data_as(C.POINTER(_D)), _ptr(x), _ptr(ws),
+                                     C.byref(rep) if want_report else None, _stream()))
+    return x, (rep if want_report else None)
 
 
 class Batch:

@@ -130,3 +130,19 @@ def test_fista_argument_checks(P):
     sz = C.c_size_t()
     assert L.pr_fista_workspace_size(None, None, C.byref(sz)) == P.PR_EINVAL
     assert P.pr_fista_params._fields_[3][0] == "lambda_"
+
+
+def test_balls_argument_checks(P):
+    L = P.lib()
+    pb, sb = C.c_size_t(), C.c_size_t()
+    assert L.pr_balls_sizes(1000, 0, C.byref(pb), C.byref(sb)) == P.PR_EINVAL
+    assert L.pr_balls_sizes(-1, 4, C.byref(pb), C.byref(sb)) == P.PR_EINVAL
+    assert L.pr_balls_sizes(1 << 31, 4, C.byref(pb), C.byref(sb)) == P.PR_EINVAL
+    assert L.pr_balls_sizes(1000, 4, C.byref(pb), C.byref(sb)) == P.PR_OK
+    assert pb.value >= 8 * 1000 and sb.value >= 16 * 1000
+    h = C.c_void_p()
+    assert L.pr_balls_create(1000, 4, 256, None, pb.value, 256, sb.value, None, C.byref(h)) == P.PR_EWORKSPACE
+    assert L.pr_balls_create(1000, 4, 256, 256, pb.value - 256, 256, sb.value, None, C.byref(h)) == P.PR_EWORKSPACE
+    assert L.pr_balls_create(1000, 4, None, 256, pb.value, 256, sb.value, None, C.byref(h)) == P.PR_EINVAL
+    rep = P.pr_admm_report()
+    assert L.pr_admm_local_solve(None, None, None, None, None, None, None, None, C.byref(rep), None) == P.PR_EINVAL
