@@ -479,9 +479,35 @@ def main():
         torch.cuda.synchronize()
         t_pd = f0.elapsed_time(f1) / K_steps
         del pws
+        # ---- local l2 balls: 4 equal-count baseline-length sections, eps_j = sigma sqrt(M_j + 2 sqrt(M_j))
+        nsec = 4
+        r_len = torch.hypot(uv[:, 0].float(), uv[:, 1].float())
+        cuts = torch.sort(r_len).values[[(M * j) // nsec for j in range(1, nsec)]]
+        sec_user = torch.bucketize(r_len, cuts, right=True).to(torch.int32)
+        del r_len
+        sec_plan = sec_user[perm.long()].contiguous()
+        cnt = torch.bincount(sec_user, minlength=nsec).double().cpu().numpy()
+        del sec_user
+        eps_j = sigma * np.sqrt(cnt + 2.0 * np.sqrt(cnt))
+        balls = P.Balls(plan, sec_plan, nsec)
+        del sec_plan
+        lws = torch.empty(P.pr_admm_workspace_size(h, psi.handle), dtype=torch.uint8, device=dev)
+        xl = torch.zeros((n, n), dtype=rdt, device=dev)
+        P.pr_admm_local_solve(h, psi.handle, balls.handle, y, P.admm_params(0.0, gamma, iters=W_steps, op_norm=op_norm),
+                              eps_j, xl, lws, want_report=False)
+        xl.zero_()
+        torch.cuda.synchronize()
+        lprm = P.admm_params(0.0, gamma, iters=K_steps, op_norm=op_norm)
+        f0.record(stream)
+        # (the call copies the radii and synchronises once before its first kernel)
+        P.pr_admm_local_solve(h, psi.handle, balls.handle, y, lprm, eps_j, xl, lws, want_report=False)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        t_local = f0.elapsed_time(f1) / K_steps
+        del lws, balls
         return dict(t_fzs=t_fzs, t_gw=t_gw, t_gwa=t_gwa, t_patch=t_patch, t_merge=t_merge, t_fzsa=t_fzsa,
                     t_phi=t_phi, t_adj=t_adj, t_pair=t_pair,
-                    t_admm=t_admm, t_fista=t_fista, t_pd=t_pd, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
+                    t_admm=t_admm, t_fista=t_fista, t_pd=t_pd, t_local=t_local, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
                     eps=eps, resid=rep.resid_norm, nonfinite=rep.nonfinite, y_plan=yv, perm=perm,
                     plan=plan, x=x)
 
@@ -529,6 +555,7 @@ def main():
         "admm_iter_ms_fp32": r32["t_admm"],
         "fista_iter_ms_fp32": r32["t_fista"],
         "primal_dual_iter_ms_fp32": r32["t_pd"],
+        "admm_local_balls_iter_ms_fp32": r32["t_local"],
         "roofline": roof[dom],
         "copy_gbs": copy_gbs,
         "roofline_other": [v for k, v in roof.items() if k != dom],
@@ -538,6 +565,7 @@ def main():
         res["fp64"] = {"value": M / (r64["t_pair"] * 1e-3), "phi_ms": r64["t_phi"],
                        "phi_adjoint_ms": r64["t_adj"], "admm_iter_ms": r64["t_admm"],
                        "fista_iter_ms": r64["t_fista"], "primal_dual_iter_ms": r64["t_pd"],
+                       "admm_local_balls_iter_ms": r64["t_local"],
                        "stage_ms": {"fzs": r64["t_fzs"], "gw": r64["t_gw"], "grid_patches": r64["t_patch"],
                                     "grid_merge": r64["t_merge"], "fzs_adjoint": r64["t_fzsa"]}}
     if not args.no_cpu_baseline and big:

@@ -643,18 +643,24 @@ class Balls:
             self.handle = None
 
 
+def pr_admm_local_solve(phi, psi, balls, y, params: pr_admm_params, eps, x, workspace, want_report=True,
+                        stream=None):
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    rep = pr_admm_report()
+    _check(lib().pr_admm_local_solve(phi, psi, balls, _ptr(y), C.byref(params), e.ctypes.data_as(C.POINTER(_D)),
+                                     _ptr(x), _ptr(workspace), C.byref(rep) if want_report else None,
+                                     stream if stream is not None else _stream()))
+    return rep if want_report else None
+
+
 def admm_local_solve(phi: PhiPlan, psi: PsiPlan, balls: Balls, y, params: pr_admm_params, eps, x0=None,
                      want_report=True):
     """Algorithm 1 with one l2 ball per section (radii ``eps``, one per section); returns (x, report)."""
     ws = _workspace(pr_admm_workspace_size(phi.handle, psi.handle), phi.device)
     x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
-    e = np.ascontiguousarray(eps, dtype=np.float64)
-    assert e.size == balls.nsec
-    rep = pr_admm_report()
-    _check(lib().pr_admm_local_solve(phi.handle, psi.handle, balls.handle, _ptr(y), C.byref(params),
-                                     e.ctypes.data_as(C.POINTER(_D)), _ptr(x), _ptr(ws),
-                                     C.byref(rep) if want_report else None, _stream()))
-    return x, (rep if want_report else None)
+    assert np.size(eps) == balls.nsec
+    rep = pr_admm_local_solve(phi.handle, psi.handle, balls.handle, y, params, eps, x, ws, want_report)
+    return x, rep
 
 
 class Batch:
