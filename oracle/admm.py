@@ -57,17 +57,20 @@ class AdmmReport:
 
 
 def dual_fb(z, d, gamma: float, eta: float, psi, psi_adj, inner_iters: int,
-            positivity: bool = True):
-    """DualFB of Algorithm 1; ``positivity=False`` drops P_C (used by a pin only)."""
+            positivity: bool = True, weights=None):
+    """DualFB of Algorithm 1; ``positivity=False`` drops P_C (used by a pin only).
+    ``weights`` (coefficient-shaped) turn the l1 norm into the weighted
+    sum_i w_i |[Psi^dagger x]_i|: the threshold of coefficient i is gamma w_i."""
     proj = proj_positive if positivity else (lambda v: np.real(v))
+    thr = gamma if weights is None else gamma * np.asarray(weights, dtype=np.float64)
     zbar = proj(z)
     for _ in range(inner_iters):
-        d = (1.0 / eta) * clip_magnitude(eta * d + psi_adj(zbar), gamma)
+        d = (1.0 / eta) * clip_magnitude(eta * d + psi_adj(zbar), thr)
         zbar = proj(z - psi(d))
     return zbar, d
 
 
-def admm(y, phi, phi_adj, psi, psi_adj, eps, p: AdmmParams, x0, d0=None, sections=None):
+def admm(y, phi, phi_adj, psi, psi_adj, eps, p: AdmmParams, x0, d0=None, sections=None, weights=None):
     """Run ``p.iters`` outer iterations; returns (x, s, d, report).
 
     phi / phi_adj are the (normalised) measurement operator and its real-image
@@ -86,7 +89,7 @@ def admm(y, phi, phi_adj, psi, psi_adj, eps, p: AdmmParams, x0, d0=None, section
         r = proj_l2ball(v + s, y, eps) if sections is None else proj_l2balls_local(v + s, y, eps, sections)
         s = s + p.varrho * (v - r)
         xt = x - p.rho * phi_adj(v - r + s)
-        x_new, d = dual_fb(xt, d, p.gamma, p.eta, psi, psi_adj, p.inner_iters)
+        x_new, d = dual_fb(xt, d, p.gamma, p.eta, psi, psi_adj, p.inner_iters, weights=weights)
         nx = float(np.sqrt(np.sum(x_new * x_new)))
         rep.rel_var.append(l2_distance(x_new, x) / nx if nx > 0 else math.inf)
         rep.resid.append(l2_distance(v, y))
