@@ -264,6 +264,34 @@ int pr_admm_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
                   pr_admm_report* rep, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Reweighted analysis l1 (SARA reweighting; Section "Sparse Regularization"
+ * names the reweighted re-solves, without a weight rule). Round 0 is
+ * pr_admm_solve; each further round r sets
+ *   w_i = delta / (delta + |[Psi^dagger x]_i|),  delta = delta0 beta^(r-1),
+ * from the current x and runs params->iters iterations of Algorithm 1 with
+ * the weighted norm sum_i w_i |[Psi^dagger x]_i| (DualFB thresholds gamma w_i),
+ * restarting from the current x with s = 0 and d = 0. 1 / ||Phi|| and gamma
+ * are formed once (as for pr_admm_solve) and kept across rounds.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t rounds;      /* reweighted rounds after the first solve (>= 0)    */
+  double delta0;       /* delta of the first reweighting (> 0)              */
+  double beta;         /* decay of delta per round, in (0, 1]               */
+} pr_reweight_params;
+
+/* Device workspace bytes: the pr_admm_solve workspace plus one weight per
+ * coefficient (nb * n * n reals). */
+int pr_reweight_workspace_size(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes);
+
+/* y, x, workspace and stream as for pr_admm_solve; params->rel_tol must be 0.
+ * rep (if not NULL; the call then synchronises) describes the last round:
+ * iters_done counts the iterations of all rounds, l1_norm is the unweighted
+ * ||Psi^dagger x||_1. PR_EINVAL for parameters out of range. */
+int pr_admm_reweighted_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
+                             const pr_admm_params* params, const pr_reweight_params* rw,
+                             void* x, void* workspace, pr_admm_report* rep, void* stream);
+
+/* ------------------------------------------------------------------------
  * Local l2-ball constraints (Section "Local Fidelity Constraint ADMM",
  * eq. proj-L2-local): the visibilities are split into nsec sections, each
  * with its own ball ||Phi_j x / ||Phi|| - y_j|| <= eps_j, and the r step of

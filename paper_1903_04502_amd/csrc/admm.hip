@@ -110,6 +110,13 @@ int admm_job_init(AdmmJob* j, pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void
   return PR_OK;
 }
 
+int admm_job_restart(AdmmJob* j, hipStream_t s) {
+  const int64_t n2 = static_cast<int64_t>(j->phi->n) * j->phi->n;
+  PR_TRY(zero_real(j->w.s, 2 * j->phi->M, j->phi->prec, s));
+  PR_TRY(zero_real(j->w.d, j->psi->nb * n2, j->phi->prec, s));
+  return PR_OK;
+}
+
 int admm_step(AdmmJob* j, hipStream_t s) {
   pr_phi_plan_t* phi = j->phi;
   pr_psi_plan_t* psi = j->psi;
@@ -129,7 +136,7 @@ int admm_step(AdmmJob* j, hipStream_t s) {
   PR_TRY(phi_gw_adjoint_admm(phi, av, j->scale, s));
   PR_TRY(phi_fzs_adjoint_step(phi, j->x, prm.rho, w.xt, w.zbar, s));
   for (int k = 0; k < prm.inner_iters; ++k) {
-    PR_TRY(psi_dual_update(psi, w.zbar, 0, w.d, prm.gamma, prm.eta, s, gamma_dev));
+    PR_TRY(psi_dual_update(psi, w.zbar, 0, w.d, prm.gamma, prm.eta, s, gamma_dev, j->l1_weights));
     const bool last = k == prm.inner_iters - 1;
     // the last synthesis writes the new iterate over x (read before written)
     void* out = last ? j->x : w.zbar;

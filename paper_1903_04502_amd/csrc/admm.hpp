@@ -36,6 +36,7 @@ struct AdmmJob {
   bool device_scale = false;
   bool device_gamma = false;
   int iters_done = 0;
+  const void* l1_weights = nullptr;   // per-coefficient weights of the l1 term (null: all 1)
 };
 
 int admm_check_plans(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi);
@@ -47,6 +48,9 @@ size_t accel_layout(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi, void* ws
 // Bind the job and clear its state (s = 0, d = 0, scalars = 0) on the stream.
 int admm_job_init(AdmmJob* j, pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, void* x, void* ws,
                   const pr_admm_params& prm, hipStream_t s);
+// Restart the iteration from the current x: s = 0, d = 0 (1 / ||Phi|| and
+// gamma stay in the device slots).
+int admm_job_restart(AdmmJob* j, hipStream_t s);
 // One outer iteration (with prm.inner_iters DualFB iterations), x in place.
 int admm_step(AdmmJob* j, hipStream_t s);
 // FP64 diagnostics of the current iterate (synchronises the stream).

@@ -139,6 +139,13 @@ __global__ void extrapolate_kernel(R* x, const R* __restrict__ xb, R* __restrict
   }
 }
 
+template <typename R>
+__global__ void l1_weights_kernel(const R* __restrict__ alpha, int64_t len, R delta, R* __restrict__ w) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    w[i] = delta / (delta + fabs(alpha[i]));
+}
+
 __global__ void scale_scalar_kernel(const double* src, double f, double* dst) { *dst = *src * f; }
 
 // a = b / sqrt(*s2)
@@ -279,6 +286,18 @@ int extrapolate(void* x, const void* xb, void* xh, int64_t len, int prec, double
   else
     extrapolate_kernel<double><<<G, kThreads, 0, s>>>(static_cast<double*>(x), static_cast<const double*>(xb),
                                                       static_cast<double*>(xh), len, c);
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
+int l1_weights(const void* alpha, int64_t len, int prec, double delta, void* w, hipStream_t s) {
+  const int G = grid_for(len, kThreads, 8192);
+  if (prec == PR_F32)
+    l1_weights_kernel<float><<<G, kThreads, 0, s>>>(static_cast<const float*>(alpha), len, static_cast<float>(delta),
+                                                    static_cast<float*>(w));
+  else
+    l1_weights_kernel<double><<<G, kThreads, 0, s>>>(static_cast<const double*>(alpha), len, delta,
+                                                     static_cast<double*>(w));
   PR_TRY_LAUNCH();
   return PR_OK;
 }

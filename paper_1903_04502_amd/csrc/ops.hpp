@@ -30,6 +30,8 @@ int copy_real(void* dst, const void* src, int64_t len, int prec, hipStream_t s);
 // Extrapolation of an accelerated iteration: xh = xb + c (xb - x), then x = xb
 // (each element of x read before it is written).
 int extrapolate(void* x, const void* xb, void* xh, int64_t len, int prec, double c, hipStream_t s);
+// Reweighting of the analysis l1 norm: w_i = delta / (delta + |alpha_i|).
+int l1_weights(const void* alpha, int64_t len, int prec, double delta, void* w, hipStream_t s);
 // *dst = *src * f (device scalars).
 int scale_scalar(const double* src, double f, double* dst, hipStream_t s);
 

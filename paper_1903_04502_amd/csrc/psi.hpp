@@ -41,8 +41,10 @@ int psi_synthesis(pr_psi_plan_t* p, const void* alpha, void* x, hipStream_t s);
 // d <- (1/eta) clip_gamma(eta d + Psi^dagger zbar), with zbar = max(z, 0) on
 // load when `positive_in` is set.
 // gamma_dev, when set, holds gamma in device memory and overrides `gamma`.
+// weights, when set, hold one real weight per coefficient (the coefficient
+// layout): the threshold of coefficient i is gamma * weights[i] (weighted l1).
 int psi_dual_update(pr_psi_plan_t* p, const void* zbar, int positive_in, void* d, double gamma, double eta,
-                    hipStream_t s, const double* gamma_dev = nullptr);
+                    hipStream_t s, const double* gamma_dev = nullptr, const void* weights = nullptr);
 // zbar = max(z - Psi d, 0); optional FP64 partials of ||zbar - xprev||^2 and
 // ||zbar||^2 into sums[0], sums[1] (device) when xprev is not null. zbar may
 // be xprev (the iterate updated in place).

@@ -67,12 +67,13 @@ __global__ void dwt_rows_kernel(const R* __restrict__ src, int64_t src_basis_str
 template <typename R, int MODE>
 __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, int n, R* __restrict__ ll_out,
                                 int last, R* __restrict__ coef, const Filt<R>* __restrict__ filt, R scale,
-                                R gamma_h, const double* __restrict__ gamma_dev, R eta) {
+                                R gamma_h, const double* __restrict__ gamma_dev, R eta, const R* __restrict__ wts) {
   const R gamma = (MODE == 1 && gamma_dev) ? static_cast<R>(*gamma_dev) : gamma_h;
   const int bi = blockIdx.y;
   const Filt<R>& f = filt[bi];
   const R* in = rows + bi * n2;
   R* cb = coef + bi * n2;
+  const R* wb = wts ? wts + bi * n2 : nullptr;   // per-coefficient l1 weights (MODE 1)
   R* llb = ll_out ? ll_out + bi * (n2 / 4) : nullptr;
   const int half = L >> 1;
   const int64_t total = static_cast<int64_t>(half) * L;
@@ -94,22 +95,22 @@ __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, i
     } else {
       const int64_t o = static_cast<int64_t>(m) * n + c;
       if (MODE == 0) cb[o] = lo * scale;
-      else cb[o] = dual_clip(cb[o], lo * scale, gamma, eta);
+      else cb[o] = dual_clip(cb[o], lo * scale, wb ? gamma * wb[o] : gamma, eta);
     }
     const int64_t o = static_cast<int64_t>(half + m) * n + c;
     if (MODE == 0) cb[o] = hi * scale;
-    else cb[o] = dual_clip(cb[o], hi * scale, gamma, eta);
+    else cb[o] = dual_clip(cb[o], hi * scale, wb ? gamma * wb[o] : gamma, eta);
   }
 }
 
 template <typename R, int MODE>
 __global__ void dirac_analysis_kernel(const R* __restrict__ x, R* __restrict__ coef, int64_t n2, R scale, R gamma_h,
-                                      const double* __restrict__ gamma_dev, R eta) {
+                                      const double* __restrict__ gamma_dev, R eta, const R* __restrict__ wts) {
   const R gamma = (MODE == 1 && gamma_dev) ? static_cast<R>(*gamma_dev) : gamma_h;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n2;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
     if (MODE == 0) coef[i] = x[i] * scale;
-    else coef[i] = dual_clip(coef[i], x[i] * scale, gamma, eta);
+    else coef[i] = dual_clip(coef[i], x[i] * scale, wts ? gamma * wts[i] : gamma, eta);
   }
 }
 
@@ -223,17 +224,18 @@ __global__ void combine_finish_kernel(const double* partials, int nblocks, doubl
 
 template <typename R>
 int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma, const double* gamma_dev, double eta,
-                  hipStream_t s) {
+                  hipStream_t s, const R* wts = nullptr) {
   const int n = p->n;
   const int64_t n2 = static_cast<int64_t>(n) * n;
   const R scale = static_cast<R>(p->scale);
   R* wave = coef + (p->has_dirac ? n2 : 0);
+  const R* wwave = wts ? wts + (p->has_dirac ? n2 : 0) : nullptr;
   if (p->has_dirac) {
     const int G = grid_for(n2, kThreads, 4096);
     if (mode == 0)
-      dirac_analysis_kernel<R, 0><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), gamma_dev, R(eta));
+      dirac_analysis_kernel<R, 0><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), gamma_dev, R(eta), nullptr);
     else
-      dirac_analysis_kernel<R, 1><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), gamma_dev, R(eta));
+      dirac_analysis_kernel<R, 1><<<G, kThreads, 0, s>>>(x, coef, n2, scale, R(gamma), gamma_dev, R(eta), wts);
     PR_TRY_LAUNCH();
   }
   if (p->ndb == 0) return PR_OK;
@@ -253,9 +255,11 @@ int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma,
     const int last = lev == p->levels;
     R* llout = last ? nullptr : (lev & 1 ? lla : llb);
     if (mode == 0)
-      dwt_cols_kernel<R, 0><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev, R(eta));
+      dwt_cols_kernel<R, 0><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
+                                                      R(eta), nullptr);
     else
-      dwt_cols_kernel<R, 1><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev, R(eta));
+      dwt_cols_kernel<R, 1><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
+                                                      R(eta), wwave);
     PR_TRY_LAUNCH();
   }
   return PR_OK;
@@ -395,12 +399,13 @@ int psi_synthesis(pr_psi_plan_t* p, const void* alpha, void* x, hipStream_t s) {
 }
 
 int psi_dual_update(pr_psi_plan_t* p, const void* zbar, int positive_in, void* d, double gamma, double eta,
-                    hipStream_t s, const double* gamma_dev) {
+                    hipStream_t s, const double* gamma_dev, const void* weights) {
   (void)positive_in;
   if (p->prec == PR_F32)
-    return analysis_impl<float>(p, static_cast<const float*>(zbar), static_cast<float*>(d), 1, gamma, gamma_dev, eta, s);
+    return analysis_impl<float>(p, static_cast<const float*>(zbar), static_cast<float*>(d), 1, gamma, gamma_dev, eta, s,
+                                static_cast<const float*>(weights));
   return analysis_impl<double>(p, static_cast<const double*>(zbar), static_cast<double*>(d), 1, gamma, gamma_dev, eta,
-                               s);
+                               s, static_cast<const double*>(weights));
 }
 
 int psi_synthesis_step(pr_psi_plan_t* p, const void* d, const void* z, void* zbar, const void* xprev,

@@ -56,6 +56,10 @@ class pr_pd_params(C.Structure):
                 ("norm_iters", C.c_int32)]
 
 
+class pr_reweight_params(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("delta0", C.c_double), ("beta", C.c_double)]
+
+
 class pr_admm_report(C.Structure):
     _fields_ = [("iters_done", C.c_int32), ("rel_var", C.c_double), ("resid_norm", C.c_double),
                 ("l1_norm", C.c_double), ("op_norm", C.c_double), ("nonfinite", C.c_int32)]
@@ -111,6 +115,9 @@ _SIGS = {
     "pr_balls_norms": (C.c_int, [_VP, C.POINTER(_D), _VP]),
     "pr_admm_local_solve": (C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(pr_admm_params), C.POINTER(_D), _VP, _VP,
                                       C.POINTER(pr_admm_report), _VP]),
+    "pr_reweight_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
+    "pr_admm_reweighted_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_admm_params), C.POINTER(pr_reweight_params),
+                                           _VP, _VP, C.POINTER(pr_admm_report), _VP]),
     "pr_phi_tune": (C.c_int, [C.POINTER(pr_phi_desc), _VP, _VP, _VP, _VP, _VP, _I32, _VP, C.POINTER(_I32),
                               C.POINTER(_D)]),
     "pr_batch_create": (C.c_int, [_I32, _I32, C.POINTER(_VP)]),
@@ -611,6 +618,31 @@ def pd_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_pd_params, x0=None, want_
     ws = _workspace(pr_pd_workspace_size(phi.handle, psi.handle), phi.device)
     x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
     rep = pr_pd_solve(phi.handle, psi.handle, y, params, x, ws, want_report)
+    return x, rep
+
+
+def pr_reweight_workspace_size(phi, psi) -> int:
+    v = _SZ()
+    _check(lib().pr_reweight_workspace_size(phi, psi, C.byref(v)))
+    return v.value
+
+
+def pr_admm_reweighted_solve(phi, psi, y, params: pr_admm_params, rw: pr_reweight_params, x, workspace,
+                             want_report=True, stream=None):
+    rep = pr_admm_report()
+    _check(lib().pr_admm_reweighted_solve(phi, psi, _ptr(y), C.byref(params), C.byref(rw), _ptr(x), _ptr(workspace),
+                                          C.byref(rep) if want_report else None,
+                                          stream if stream is not None else _stream()))
+    return rep if want_report else None
+
+
+def admm_reweighted_solve(phi: PhiPlan, psi: PsiPlan, y, params: pr_admm_params, rounds: int, delta0: float,
+                          beta: float, x0=None, want_report=True):
+    """Reweighted analysis l1 around Algorithm 1; returns (x, report of the last round)."""
+    ws = _workspace(pr_reweight_workspace_size(phi.handle, psi.handle), phi.device)
+    x = torch.zeros((phi.n, phi.n), dtype=phi.rdtype, device=phi.device) if x0 is None else x0.clone()
+    rep = pr_admm_reweighted_solve(phi.handle, psi.handle, y, params, pr_reweight_params(rounds, delta0, beta), x, ws,
+                                   want_report)
     return x, rep
 
 
