@@ -14,7 +14,11 @@ Modules
   wavelets       Daubechies filters, periodic 2-D DWT, the SARA dictionary
   prox           soft thresholding, positivity and l2-ball projections
                  (Section "Proximal Operators")
-  admm           Dual Forward-Backward ADMM (Algorithm 1)
+  admm           Dual Forward-Backward ADMM (Algorithm 1), with the local l2 balls
+                 (Section "Local Fidelity Constraint ADMM") and a weighted l1
+  fista          FISTA for the MAP problem (Algorithm "FISTA")
+  primal_dual    Primal-Dual splitting (Algorithm "Primal-Dual Algorithm")
+  reweight       the reweighted analysis l1 loop (Section "Sparse Regularization")
   nudft          the direct non-uniform DFT the NUFFT approximates
 
 Parity status of each function is stated in its module header.
