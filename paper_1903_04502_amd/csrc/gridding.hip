@@ -34,8 +34,6 @@ constexpr int kSlotNonfinite = 3;
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kDegridBlocks = 2048;   // persistent degridding blocks (8 per CU); <= kPartialsMax
-constexpr int kGridBlocks = 512;      // persistent gridding blocks (2 per CU, bound by LDS)
 constexpr size_t kLdsSoft = 81920;    // two blocks per CU
 constexpr size_t kLdsHard = 163840;   // per-workgroup limit on gfx950
 
@@ -50,7 +48,8 @@ struct GwArgs {
   const R* table;
   const R* uv;
   const R* w;
-  const int4* items;
+  const int4* items;         // this launch's schedule: (tile, begin, end, item index); block b takes
+  const int32_t* sched_off;  // entries [sched_off[b], sched_off[b + 1])
   int64_t nItems;
   int K, T, P, nT, lognT, D, tlen;
   double kappa;
@@ -94,8 +93,9 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       }
     }
   };
-  for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
-    const int4 it = a.items[item];
+  const int kend = a.sched_off[blockIdx.x + 1];
+  for (int ks = a.sched_off[blockIdx.x]; ks < kend; ++ks) {
+    const int4 it = a.items[ks];
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
     load(it.y, it.z, cu_, cv_, cw_);
     __syncthreads();
@@ -184,7 +184,8 @@ struct GwAdjArgs {
   const R* table;
   const R* uv;
   const R* w;
-  const int4* items;
+  const int4* items;         // this launch's schedule: (tile, begin, end, item index); block b takes
+  const int32_t* sched_off;  // entries [sched_off[b], sched_off[b + 1])
   int64_t nItems;
   int K, T, P, nT, lognT, D, tlen, B;
   double kappa;
@@ -317,8 +318,10 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
     }
   };
 
-  for (int64_t item = blockIdx.x; item < a.nItems; item += gridDim.x) {
-    const int4 it = a.items[item];
+  const int kend = a.sched_off[blockIdx.x + 1];
+  for (int ks = a.sched_off[blockIdx.x]; ks < kend; ++ks) {
+    const int4 it = a.items[ks];
+    const int64_t item = it.w;
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
     const int begin = it.y, end = it.z;
     load_raw(begin, min(B, end - begin));
@@ -666,17 +669,18 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   };
   auto seg_len = [](const int4& it) { return (it.z - it.y + kThreads - 1) / kThreads; };
 
-  int64_t item = blockIdx.x;
+  const int kbeg = a.sched_off[blockIdx.x], kend = a.sched_off[blockIdx.x + 1];
   int4 it = make_int4(0, 0, 0, 0);
   int L = 0;
-  if (item < a.nItems) {
-    it = a.items[item];
+  if (kbeg < kend) {
+    it = a.items[kbeg];
     L = seg_len(it);
     issue(it, L, 0);
   }
-  for (; item < a.nItems; item += gridDim.x) {
-    const int64_t nxt = item + gridDim.x;
-    const int4 itn = nxt < a.nItems ? a.items[nxt] : make_int4(0, 0, 0, 0);
+  for (int ks = kbeg; ks < kend; ++ks) {
+    const int64_t item = it.w;
+    const bool has_next = ks + 1 < kend;
+    const int4 itn = has_next ? a.items[ks + 1] : make_int4(0, 0, 0, 0);
     const int Ln = seg_len(itn);
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
     const int segn = max(0, min(L, it.z - (it.y + tid * L)));   // this thread's positions
@@ -699,7 +703,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       {
         // one call site for both prefetch targets (next chunk, or next item's first)
         const bool more = q0 + WC < L;
-        if (more || nxt < a.nItems) issue(more ? it : itn, more ? L : Ln, more ? q0 + WC : 0);
+        if (more || has_next) issue(more ? it : itn, more ? L : Ln, more ? q0 + WC : 0);
       }
       __syncthreads();
       const int qn = min(WC, segn - q0);
@@ -1040,7 +1044,8 @@ GwArgs<R> gw_args(pr_phi_plan_t* p, double scale) {
   a.table = static_cast<const R*>(p->table);
   a.uv = static_cast<const R*>(p->uv);
   a.w = static_cast<const R*>(p->w);
-  a.items = p->items;
+  a.items = p->sched_d;
+  a.sched_off = p->sched_d_off;
   a.nItems = p->nItems;
   a.K = p->K; a.T = p->T; a.P = p->P; a.nT = p->nT; a.D = p->D;
   a.lognT = 0;
@@ -1057,7 +1062,8 @@ GwAdjArgs<R> gwadj_args(pr_phi_plan_t* p, double scale) {
   a.table = static_cast<const R*>(p->table);
   a.uv = static_cast<const R*>(p->uv);
   a.w = static_cast<const R*>(p->w);
-  a.items = p->items;
+  a.items = p->sched_g;
+  a.sched_off = p->sched_g_off;
   a.nItems = p->nItems;
   a.K = p->K; a.T = p->T; a.P = p->P; a.nT = p->nT; a.D = p->D;
   a.lognT = 0;

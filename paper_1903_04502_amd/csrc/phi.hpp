@@ -24,6 +24,13 @@ struct pr_phi_plan_t {
   int32_t* perm = nullptr;     // plan position -> user index
   int32_t* item_off = nullptr; // per tile first work item, [nTiles + 1]
   int4* items = nullptr;       // (tile, begin, end, 0)
+  // Static block schedules of the work items: the items in schedule order,
+  // each with its own index in .w; block b of a launch takes entries
+  // [off[b], off[b+1]).
+  int4* sched_d = nullptr;         // degridding, [nItemsMax]
+  int32_t* sched_d_off = nullptr;  // [kDegridBlocks + 1]
+  int4* sched_g = nullptr;         // gridding, [nItemsMax]
+  int32_t* sched_g_off = nullptr;  // [kGridBlocks + 1]
   void* table = nullptr;       // Real[J*D/2 + 1]
   void* corr = nullptr;        // Real[n]
   void* tw = nullptr;          // complex[K], e^{-2 pi i m / K}
@@ -41,6 +48,8 @@ struct pr_phi_plan_t {
 namespace pr {
 
 constexpr int kPartialsMax = 4096;     // per-block partials, per quantity slot
+constexpr int kDegridBlocks = 2048;    // persistent degridding blocks (8 per CU); <= kPartialsMax
+constexpr int kGridBlocks = 512;       // persistent gridding blocks (2 per CU, bound by LDS)
 constexpr int kPartialSlots = 4;
 constexpr int kScalars = 64;
 

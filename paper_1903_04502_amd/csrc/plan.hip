@@ -6,7 +6,11 @@
 // visibility's footprint starts in, so each tile's visibilities are contiguous.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
+#include <functional>
+#include <queue>
 #include <utility>
+#include <vector>
 
 #include "phi.hpp"
 #include "taps.hpp"
@@ -421,6 +425,10 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   p->perm = a.take<int32_t>(M);
   p->item_off = a.take<int32_t>(p->nTiles + 1);
   p->items = a.take<int4>(p->nItemsMax);
+  p->sched_d = a.take<int4>(p->nItemsMax);
+  p->sched_d_off = a.take<int32_t>(kDegridBlocks + 1);
+  p->sched_g = a.take<int4>(p->nItemsMax);
+  p->sched_g_off = a.take<int32_t>(kGridBlocks + 1);
   p->table = a.take<char>((p->J * static_cast<int64_t>(p->D) / 2 + 1) * rs);
   p->corr = a.take<char>(p->n * rs);
   p->tw = a.take<char>(p->K * 2 * rs);
@@ -440,6 +448,70 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   carve_create(p, c);
   size_t cr = c.bytes();
   if (scratch_bytes) *scratch_bytes = op > cr ? op : cr;
+  return PR_OK;
+}
+
+// Block schedule of the work items over G blocks, fixed at plan time (so
+// every launch, and its floating-point summation order, is the same).
+// With few items per block, longest-processing-time: items in decreasing cost
+// (visibilities plus a per-item overhead, ties by index) each go to the block
+// with the least load so far (ties to the lower block). With many items per
+// block the loads even out by themselves and block b takes items b, b + G,
+// b + 2G, ...: the blocks running at one time then read neighbouring parts of
+// the visibility arrays (address-translation locality).
+static void lpt_schedule(const std::vector<int4>& items, int G, int64_t overhead, std::vector<int4>& sched,
+                         std::vector<int32_t>& off) {
+  auto entry = [&](int64_t i) { return make_int4(items[i].x, items[i].y, items[i].z, static_cast<int>(i)); };
+  const int64_t n = static_cast<int64_t>(items.size());
+  if (n >= 8 * static_cast<int64_t>(G)) {
+    sched.clear();
+    off.assign(static_cast<size_t>(G) + 1, 0);
+    for (int b = 0; b < G; ++b) {
+      for (int64_t i = b; i < n; i += G) sched.push_back(entry(i));
+      off[b + 1] = static_cast<int32_t>(sched.size());
+    }
+    return;
+  }
+  std::vector<int32_t> order(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) order[i] = static_cast<int32_t>(i);
+  auto cost = [&](int32_t i) { return static_cast<int64_t>(items[i].z - items[i].y) + overhead; };
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+  using Load = std::pair<int64_t, int>;
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int b = 0; b < G; ++b) heap.push(Load(0, b));
+  std::vector<std::vector<int32_t>> per(static_cast<size_t>(G));
+  for (int32_t i : order) {
+    Load l = heap.top();
+    heap.pop();
+    per[l.second].push_back(i);
+    heap.push(Load(l.first + cost(i), l.second));
+  }
+  sched.clear();
+  off.assign(static_cast<size_t>(G) + 1, 0);
+  for (int b = 0; b < G; ++b) {
+    for (int32_t i : per[b]) sched.push_back(entry(i));
+    off[b + 1] = static_cast<int32_t>(sched.size());
+  }
+}
+
+static int build_schedules(pr_phi_plan_t* p, hipStream_t s) {
+  const int64_t n = p->nItems;
+  if (n == 0) return PR_OK;
+  std::vector<int4> items(static_cast<size_t>(n));
+  PR_TRY_HIP(hipMemcpyAsync(items.data(), p->items, n * sizeof(int4), hipMemcpyDeviceToHost, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));
+  const int64_t P2 = static_cast<int64_t>(p->P) * p->P;
+  std::vector<int4> sd, sg;
+  std::vector<int32_t> sdo, sgo;
+  const int Gd = static_cast<int>(n < kDegridBlocks ? n : kDegridBlocks);
+  const int Gg = static_cast<int>(n < kGridBlocks ? n : kGridBlocks);
+  lpt_schedule(items, Gd, P2 / 2, sd, sdo);     // per item: the patch load
+  lpt_schedule(items, Gg, P2, sg, sgo);         // per item: clearing, assembly, patch store
+  PR_TRY_HIP(hipMemcpyAsync(p->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  PR_TRY_HIP(hipMemcpyAsync(p->sched_d_off, sdo.data(), sdo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  PR_TRY_HIP(hipMemcpyAsync(p->sched_g, sg.data(), sg.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  PR_TRY_HIP(hipMemcpyAsync(p->sched_g_off, sgo.data(), sgo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
   return PR_OK;
 }
 
@@ -497,7 +569,7 @@ static int create_impl(pr_phi_plan_t* p, const R* uv, const R* w, hipStream_t s)
               static_cast<long long>(p->nItemsMax));
     return PR_EINVAL;
   }
-  return PR_OK;
+  return build_schedules(p, s);
 }
 
 int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s) {
