@@ -21,6 +21,10 @@ Timed, after W warm-up passes, on torch's current stream with HIP events:
     the channel law plus 5% 2048^2 / 5e7-visibility jobs through the
     continuous-batching server, FP32 and FP64: solves/s, p50/p99 latency and
     the final image error against the true sky.
+  * `large_workload`: the 2048^2 image / 4096^2 grid / 5e8 ring-plus-core
+    visibility workload (FP32, 5 timed steps) run by this script in a child
+    process (`--workload c2`), its pair rate, stage times, solver iteration
+    times and roofline; `--no-large` skips it.
 `roofline` is the slower of the two single-launch visibility kernels
 (gridding patches or degridding): 20 algorithmic bytes per visibility (u, v,
 w, y in FP32) over its event-timed duration, against the 8 TB/s HBM peak;
@@ -334,6 +338,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200, help="timed requests per precision")
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2048^2 / 5e8-visibility sub-run reported under `large_workload`")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run the kernels counted by the rocprofv3 --pmc passes (see profiles/)")
     args = ap.parse_args()
@@ -629,7 +635,33 @@ def main():
             torch.cuda.empty_cache()
         s32, s64 = res["serving"]["fp32"], res["serving"]["fp64"]
         s32["img_err_gap_vs_fp64"] = abs(s32["img_err_median"] - s64["img_err_median"])
+    if not big and not args.no_large:
+        res["large_workload"] = run_large(args)
     print(json.dumps(res))
+
+
+def run_large(args):
+    """The 2048^2 / 5e8-visibility workload (one GPU's share of the paper's
+    largest run), measured by this script in a child process after the
+    device memory of the main run is released: its own JSON line is kept."""
+    import subprocess
+    import torch
+    torch.cuda.empty_cache()
+    log("large workload: 2048^2 image, 5e8 visibilities (child process)")
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "c2", "--steps", "5", "--warmup", "1"]
+    if args.no_cpu_baseline:
+        cmd.append("--no-cpu-baseline")
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    sys.stderr.write(r.stderr[-2000:])
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"child exited with {r.returncode}"}
+    child = json.loads(lines[-1])
+    keep = ("value", "unit", "ms_per_step", "phi_pair_ms", "phi_ms", "phi_adjoint_ms", "stage_ms",
+            "admm_iter_ms_fp32", "fista_iter_ms_fp32", "primal_dual_iter_ms_fp32",
+            "admm_local_balls_iter_ms_fp32", "roofline", "roofline_other", "copy_gbs", "config",
+            "cpu_baseline", "phi_rel_err_fp32_vs_oracle_sample", "steps", "warmup")
+    return {k: child[k] for k in keep if k in child}
 
 
 if __name__ == "__main__":
