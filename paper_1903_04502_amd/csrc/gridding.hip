@@ -516,7 +516,7 @@ constexpr int kStagePitch = kThreads + 1;
 
 template <typename R, int J>
 struct WalkLds {
-  size_t tab, mom, stage, fcell, lcell, total;
+  size_t tab, mom, stage, fcell, lcell, masks, total;
   int borrow;   // table entries under the cell lists (0: lists have their own space)
   __host__ __device__ WalkLds(int T, int tlen, bool tab_lds) {
     using C = cx_t<R>;
@@ -538,6 +538,7 @@ struct WalkLds {
       borrow = 0;
     }
     lcell = fcell + lists / 2;
+    masks = o;  o += align16(static_cast<size_t>(2 * (kThreads / 64)) * sizeof(unsigned long long));
     total = o;
   }
 };
@@ -591,6 +592,9 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   C* side = reinterpret_cast<C*>(smem_raw + lay.stage);          // after the walk
   int* fcell = reinterpret_cast<int*>(smem_raw + lay.fcell);
   int* lcell = reinterpret_cast<int*>(smem_raw + lay.lcell);
+  int* helper = fcell;            // after the middles are known: helper assignments
+  unsigned long long* nonmid = reinterpret_cast<unsigned long long*>(smem_raw + lay.masks);   // per wave
+  unsigned long long* helpmask = nonmid + kThreads / 64;                                       // per wave
   const int tid = threadIdx.x;
   const R* tab = a.table;
   if (TAB_LDS) {
@@ -761,21 +765,68 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 #pragma unroll
       for (int e = 0; e < JJ; ++e) side[e * kThreads + tid] = cmk<C>(ar[e], ai[e]);
     }
-    // owner of the last run: middle segments are [tid + 1, jend); a final
-    // segment, if any, has already stored its part in the moments of cur
-    int jend = tid + 1;
-    const bool owner = nruns > 0 && !middle;
-    if (owner) {
-      while (jend < kThreads && fcell[jend] == cur && lcell[jend] == cur) ++jend;
+    helper[tid] = -1;               // the cell lists are not read again
+    {
+      const unsigned long long bal = __ballot(!middle);
+      if ((tid & 63) == 0) nonmid[tid >> 6] = bal;
     }
-    __syncthreads();   // side slots written; cell lists no longer read
+    __syncthreads();   // side slots and the non-middle masks written
+    // owner of the last run: its middle segments are [tid + 1, jend), jend the
+    // next segment that is not a middle one; a final segment, if any, has
+    // already stored its part in the moments of cur
+    const bool owner = nruns > 0 && !middle;
+    int jend = tid + 1;
     if (owner) {
-      for (int j = tid + 1; j < jend; ++j) {
+      const int w = tid >> 6, lane = tid & 63;
+      unsigned long long m = lane == 63 ? 0ull : (nonmid[w] & (~0ull << (lane + 1)));
+      int ww = w;
+      while (m == 0ull && ww + 1 < kThreads / 64) m = nonmid[++ww];
+      jend = m ? ww * 64 + __builtin_ctzll(m) : kThreads;
+    }
+    // long runs: JJ middle threads each sum one moment over the run's middle
+    // segments (in segment order) for the owner
+    const bool helped = owner && jend - tid - 1 >= JJ;
+    if (helped) {
+      for (int e = 0; e < JJ; ++e) helper[tid + 1 + e] = (tid << 9) | jend;
+    }
+    {
+      const unsigned long long bal = __ballot(helped);
+      if ((tid & 63) == 0) helpmask[tid >> 6] = bal;
+    }
+    __syncthreads();   // helper assignments and the per-wave flags written
+    unsigned long long anyhelp = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) anyhelp |= helpmask[w];
+    if (anyhelp) {
+      const int hv = helper[tid];
+      if (hv >= 0) {
+        const int o = hv >> 9, je = hv & 511, e = tid - o - 1;
+        R sr = 0, si = 0;
+        for (int j = o + 1; j < je; ++j) {
+          const C d = side[e * kThreads + j];
+          sr += d.x;
+          si += d.y;
+        }
+        side[e * kThreads + o + 1] = cmk<C>(sr, si);
+      }
+      __syncthreads();   // the helpers' totals are in the first middle slot of each run
+    }
+    if (owner) {
+      if (helped) {
 #pragma unroll
         for (int e = 0; e < JJ; ++e) {
-          const C d = side[e * kThreads + j];
+          const C d = side[e * kThreads + tid + 1];
           ar[e] += d.x;
           ai[e] += d.y;
+        }
+      } else {
+        for (int j = tid + 1; j < jend; ++j) {
+#pragma unroll
+          for (int e = 0; e < JJ; ++e) {
+            const C d = side[e * kThreads + j];
+            ar[e] += d.x;
+            ai[e] += d.y;
+          }
         }
       }
 #pragma unroll
