@@ -902,8 +902,21 @@ __global__ void merge_patches_kernel(const cx_t<R>* __restrict__ patches, const 
         const int pu = lu + du * T;
         const int src = tvv * nT + tuu;
         const int i0 = item_off[src], i1 = item_off[src + 1];
-        for (int itm = i0; itm < i1; ++itm) {
-          const C v = patches[itm * P2 + pv * P + pu];
+        const C* col = patches + pv * P + pu;
+        int itm = i0;
+        // eight loads in flight, summed in item order
+        for (; itm + 8 <= i1; itm += 8) {
+          C v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = col[(itm + k) * P2];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            sr += v[k].x;
+            si += v[k].y;
+          }
+        }
+        for (; itm < i1; ++itm) {
+          const C v = col[itm * P2];
           sr += v.x;
           si += v.y;
         }
