@@ -23,7 +23,7 @@ Timed, after W warm-up passes, on torch's current stream with HIP events:
     the final image error against the true sky.
   * `large_workload`: the 2048^2 image / 4096^2 grid / 5e8 ring-plus-core
     visibility workload (FP32, 5 timed steps) run by this script in a child
-    process (`--workload c2`), its pair rate, stage times, solver iteration
+    process (`--workload share2048`), its pair rate, stage times, solver iteration
     times and roofline; `--no-large` skips it.
 `roofline` is the slower of the two single-launch visibility kernels
 (gridding patches or degridding): 20 algorithmic bytes per visibility (u, v,
@@ -203,7 +203,7 @@ def run_batch(P, dev, args):
         out["graph" if use_graph else "streams"] = e0.elapsed_time(e1) / K
     rep = [b.report(m["slot"]) for m in members[:4]]
     sum_m = int(sum(m["M"] for m in members))
-    return {"workload": "c3-64ch-n128..1024-M1e4..5e6-J4-sara3", "channels": len(members), "visibilities": sum_m,
+    return {"workload": "channels-64ch-n128..1024-M1e4..5e6-J4-sara3", "channels": len(members), "visibilities": sum_m,
             "tiles_from_autotuner": {str(k): v for k, v in sorted(tiles.items())},
             "phi_pair_ms": t_pair, "vis_per_s": sum_m / (t_pair * 1e-3),
             "admm_step_ms_graph": out["graph"], "admm_step_ms_streams": out["streams"],
@@ -217,7 +217,7 @@ _SERVE_POOL = {}
 
 
 def serve_pool(n_small=24):
-    """Host data of the request pool: C3-law jobs plus two 2048^2 / 5e7 jobs."""
+    """Host data of the request pool: channel-law jobs plus two 2048^2 / 5e7 jobs."""
     import workloads as W
     if "pool" in _SERVE_POOL:
         return _SERVE_POOL["pool"]
@@ -290,7 +290,7 @@ def run_serve(P, dev, args, prec):
     last = max(v[2] for v in timed) if timed else 0.0
     e = np.array([errs[j] for j in lat if lat[j][0] >= args.serve_warmup])
     nbig = int(big[args.serve_warmup:].sum())
-    return {"workload": "c4-poisson-c3law+5pct-2048sq-M5e7-30iters", "rate_req_s": args.serve_rate,
+    return {"workload": "serving-poisson-channel-law+5pct-2048sq-M5e7-30iters", "rate_req_s": args.serve_rate,
             "requests": len(timed), "warmup_requests": args.serve_warmup, "big_jobs": nbig,
             "solves_per_s": len(timed) / (last - first) if timed else 0.0,
             "p50_ms": float(np.percentile(l_ms, 50)) if timed else None,
@@ -301,11 +301,11 @@ def run_serve(P, dev, args, prec):
 
 
 def pmc_probe(P, dev):
-    """The kernels the counter passes read: C1 gridding and degridding, and a
+    """The kernels the counter passes read: 256^2 / 1e6 gridding and degridding, and a
     plain 512 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate bytes."""
     import torch
     import workloads as W
-    wl = W.CONFIGS["c1"]
+    wl = W.CONFIGS["op256"]
     rng = W.rng_for(wl.index)
     x = W.make_sky(wl, rng)
     uv = W.make_uv(wl, rng)
@@ -329,8 +329,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c1j6", "c2"],
-                    help="c2: 2048^2 image, 5e8 ring-plus-core visibilities, FP32 (FP64 scalars) only")
+    ap.add_argument("--workload", default="op256", choices=["op256", "op256j6", "share2048"],
+                    help="share2048: 2048^2 image, 5e8 ring-plus-core visibilities, FP32 (FP64 scalars) only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -344,7 +344,7 @@ def main():
                     help="only run the kernels counted by the rocprofv3 --pmc passes (see profiles/)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -363,7 +363,7 @@ def main():
     rng = W.rng_for(wl.index)
     log(f"workload {wl.name}: generating inputs")
     x_true = W.make_sky(wl, rng)
-    big = args.workload == "c2"
+    big = args.workload == "share2048"
     if big:
         # 5e8 baselines and noise drawn on the device (seeded torch generator)
         args.no_fp64 = True
@@ -648,7 +648,7 @@ def run_large(args):
     import torch
     torch.cuda.empty_cache()
     log("large workload: 2048^2 image, 5e8 visibilities (child process)")
-    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "c2", "--steps", "5", "--warmup", "1"]
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "share2048", "--steps", "5", "--warmup", "1"]
     if args.no_cpu_baseline:
         cmd.append("--no-cpu-baseline")
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)

@@ -48,7 +48,7 @@ extern "C" {
 #define PR_EINVAL 1        /* invalid argument (shape, null pointer, range)  */
 #define PR_EWORKSPACE 2    /* workspace pointer missing or misaligned         */
 #define PR_EHIP 3          /* a HIP runtime call failed                        */
-#define PR_EUNSUPPORTED 4  /* valid request outside what this build supports  */
+#define PR_EUNSUPPORTED 4  /* valid request outside what this library supports */
 
 #define PR_F32 0
 #define PR_F64 1

@@ -22,7 +22,7 @@ def P():
 
 
 def c0_problem(iters):
-    w = W.CONFIGS["c0"]
+    w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)                        # float32 baselines
@@ -45,8 +45,8 @@ def oracle_run(w, uv64, spec, y, eps, iters, norm_iters=100):
 
 
 @pytest.mark.parametrize("prec,tol,iters", [("f64", 1e-10, 50), ("f32", 1e-4, 50), ("f64", 1e-10, 3)])
-def test_admm_parity_c0(P, prec, tol, iters):
-    say(f"admm c0 {prec} iters={iters}")
+def test_admm_parity_admm64(P, prec, tol, iters):
+    say(f"admm admm64 {prec} iters={iters}")
     w, x_true, uv, uv64, spec, y, eps = c0_problem(iters)
     x_ref, rep_ref, gamma, nrm_ref = oracle_run(w, uv64, spec, y, eps, iters)
     uv_dev = uv if prec == "f32" else uv64

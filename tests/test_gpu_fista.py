@@ -22,7 +22,7 @@ def P():
 
 
 def c0_data():
-    w = W.CONFIGS["c0"]
+    w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)
@@ -55,8 +55,8 @@ def run_gpu(P, w, uv, uv64, y, prec, prm):
 
 @pytest.mark.parametrize("prec,tol,iters,inner", [
     ("f64", 1e-10, 50, 1), ("f32", 1e-4, 50, 1), ("f64", 1e-10, 10, 3), ("f64", 1e-10, 1, 1)])
-def test_fista_parity_c0(P, prec, tol, iters, inner):
-    say(f"fista c0 {prec} iters={iters} inner={inner}")
+def test_fista_parity_admm64(P, prec, tol, iters, inner):
+    say(f"fista admm64 {prec} iters={iters} inner={inner}")
     w, uv, uv64, spec, y = c0_data()
     lam = 1.0
     x_ref, rep_ref, gamma, nrm, _ = oracle_fista(w, uv64, spec, y, iters, lam, inner)
@@ -71,7 +71,7 @@ def test_fista_parity_c0(P, prec, tol, iters, inner):
 
 
 def test_fista_device_norm_and_gamma(P):
-    say("fista c0 f64 device norm and gamma")
+    say("fista admm64 f64 device norm and gamma")
     w, uv, uv64, spec, y = c0_data()
     x_ref, rep_ref, gamma, nrm, _ = oracle_fista(w, uv64, spec, y, 20, 0.9)
     _, (x, rep) = run_gpu(P, w, uv, uv64, y, "f64",
@@ -81,7 +81,7 @@ def test_fista_device_norm_and_gamma(P):
 
 
 def test_fista_reaches_the_oracle_objective(P):
-    say("fista c0 f32 objective")
+    say("fista admm64 f32 objective")
     w, uv, uv64, spec, y = c0_data()
     x_ref, _, gamma, nrm, obj_ref = oracle_fista(w, uv64, spec, y, 100, 1.0)
     _, (x, _) = run_gpu(P, w, uv, uv64, y, "f32", P.fista_params(gamma, 1.0, iters=100, op_norm=nrm))

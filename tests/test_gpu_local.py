@@ -25,7 +25,7 @@ def P():
 
 
 def c0_data():
-    w = W.CONFIGS["c0"]
+    w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)
@@ -70,8 +70,8 @@ def gpu_local(P, w, uv, uv64, y, sec, nsec, eps_j, prec, prm):
 
 
 @pytest.mark.parametrize("prec,tol,iters,nsec", [("f64", 1e-10, 50, 4), ("f32", 1e-4, 50, 4), ("f64", 1e-10, 10, 16)])
-def test_local_balls_parity_c0(P, prec, tol, iters, nsec):
-    say(f"local balls c0 {prec} iters={iters} nsec={nsec}")
+def test_local_balls_parity_admm64(P, prec, tol, iters, nsec):
+    say(f"local balls admm64 {prec} iters={iters} nsec={nsec}")
     w, uv, uv64, spec, y, sigma, _ = c0_data()
     sec = length_sections(uv64, nsec)
     eps_j = radii(sec, nsec, sigma)

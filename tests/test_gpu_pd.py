@@ -23,7 +23,7 @@ def P():
 
 
 def c0_data(J=None):
-    w = W.CONFIGS["c0"]
+    w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)
@@ -62,8 +62,8 @@ def run_gpu(P, w, J, uv, uv64, y, prec, prm):
     ("l2", "f64", 1e-10, 10, 0.5, 1, 6),
     ("ball", "f64", 1e-10, 10, 1.0, 1, 6),
 ])
-def test_pd_parity_c0(P, misfit, prec, tol, iters, theta, inner, J):
-    say(f"pd c0 {misfit} {prec} iters={iters} theta={theta} inner={inner} J={J}")
+def test_pd_parity_admm64(P, misfit, prec, tol, iters, theta, inner, J):
+    say(f"pd admm64 {misfit} {prec} iters={iters} theta={theta} inner={inner} J={J}")
     w, J, uv, uv64, spec, y, eps = c0_data(J)
     tau, sigma = 0.5, 1.0
     x_ref, rep_ref, gamma, nrm = oracle_pd(w, uv64, spec, y, eps, misfit, iters, tau, sigma, theta, inner)
@@ -81,7 +81,7 @@ def test_pd_parity_c0(P, misfit, prec, tol, iters, theta, inner, J):
 
 
 def test_pd_device_norm_and_gamma(P):
-    say("pd c0 f64 device norm and gamma")
+    say("pd admm64 f64 device norm and gamma")
     w, J, uv, uv64, spec, y, eps = c0_data()
     x_ref, _, gamma, nrm = oracle_pd(w, uv64, spec, y, eps, "ball", 20, 0.5, 1.0, 1.0)
     x, rep = run_gpu(P, w, J, uv, uv64, y, "f64",

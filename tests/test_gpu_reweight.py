@@ -19,7 +19,7 @@ def P():
 
 
 def c0_data():
-    w = W.CONFIGS["c0"]
+    w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)
@@ -49,8 +49,8 @@ def run_gpu(P, w, uv, uv64, y, prec, prm, rounds, delta0, beta):
 
 
 @pytest.mark.parametrize("prec,tol,iters,rounds", [("f64", 1e-10, 20, 2), ("f32", 1e-4, 20, 2), ("f64", 1e-10, 5, 0)])
-def test_reweighted_parity_c0(P, prec, tol, iters, rounds):
-    say(f"reweighted c0 {prec} iters={iters} rounds={rounds}")
+def test_reweighted_parity_admm64(P, prec, tol, iters, rounds):
+    say(f"reweighted admm64 {prec} iters={iters} rounds={rounds}")
     w, uv, uv64, spec, y, eps = c0_data()
     delta0, beta = 1e-3, 0.5
     x_ref, reps, gamma, nrm = oracle_rw(w, uv64, spec, y, eps, iters, rounds, delta0, beta)

@@ -142,8 +142,8 @@ def test_oversize_request_is_refused(P):
 
 
 def test_served_fp64_job_matches_oracle(P):
-    say("serve c0 fp64 vs oracle")
-    w = W.CONFIGS["c0"]
+    say("serve admm64 fp64 vs oracle")
+    w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)

@@ -25,13 +25,13 @@ def P():
 
 
 @pytest.fixture(scope="module")
-def c2(P):
-    wl = W.CONFIGS["c2"]
-    say("c2 full size: generating 5e8 baselines on the device")
+def big(P):
+    wl = W.CONFIGS["share2048"]
+    say("big full size: generating 5e8 baselines on the device")
     gen = W.torch_generator(wl.index, DEV)
     uv = W.uv_ring_core_torch(wl.M, gen, DEV)
     x = W.make_sky(wl, W.rng_for(wl.index))
-    say("c2 full size: plan")
+    say("big full size: plan")
     plan = P.PhiPlan(wl.n, uv, None, J=wl.J, D=wl.D)
     return dict(wl=wl, uv=uv, x=x, plan=plan, gen=gen)
 
@@ -44,10 +44,10 @@ def inner_f64(a, b, chunk=1 << 26):
     return acc
 
 
-def test_c2_phi_sampled_vs_oracle(P, c2):
-    wl, plan = c2["wl"], c2["plan"]
-    say("c2 phi")
-    y = plan.apply(torch.as_tensor(c2["x"], dtype=torch.float32, device=DEV))
+def test_share2048_phi_sampled_vs_oracle(P, big):
+    wl, plan = big["wl"], big["plan"]
+    say("big phi")
+    y = plan.apply(torch.as_tensor(big["x"], dtype=torch.float32, device=DEV))
     perm = plan.perm()
     # 20000 visibilities spread over the plan order (every tile region), plus
     # the ends; integer arithmetic (a float32 linspace rounds M - 1 up to M)
@@ -56,18 +56,18 @@ def test_c2_phi_sampled_vs_oracle(P, c2):
     assert int(pos.min()) >= 0 and int(pos.max()) < wl.M
     pos = pos.to(DEV)
     idx = perm[pos]
-    uv_s = c2["uv"][idx].double().cpu().numpy()
+    uv_s = big["uv"][idx].double().cpu().numpy()
     spec = ms.PhiSpec(wl.n, wl.K, wl.J, wl.D)
-    y_ref = ms.phi(c2["x"], uv_s, None, spec)
+    y_ref = ms.phi(big["x"], uv_s, None, spec)
     y_gpu = y[pos].cpu().numpy().astype(np.complex128)
     err = np.linalg.norm(y_gpu - y_ref) / np.linalg.norm(y_ref)
-    say(f"c2 phi sampled rel err {err:.3e}")
+    say(f"big phi sampled rel err {err:.3e}")
     assert err <= 1e-5
 
 
-def test_c2_adjoint_identity(P, c2):
-    wl, plan = c2["wl"], c2["plan"]
-    say("c2 adjoint identity")
+def test_share2048_adjoint_identity(P, big):
+    wl, plan = big["wl"], big["plan"]
+    say("big adjoint identity")
     g = torch.Generator(device=DEV)
     g.manual_seed(77)
     x = torch.rand((wl.n, wl.n), generator=g, device=DEV)
@@ -76,16 +76,16 @@ def test_c2_adjoint_identity(P, c2):
     av = plan.adjoint(v)
     lhs = inner_f64(ax, v)
     rhs = float((x.double() * av.double()).sum())
-    say(f"c2 <Phi x, v> = {lhs:.9e}, <x, Phi^H v> = {rhs:.9e}")
+    say(f"big <Phi x, v> = {lhs:.9e}, <x, Phi^H v> = {rhs:.9e}")
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
-def test_c2_admm_invariants(P, c2):
-    wl, plan = c2["wl"], c2["plan"]
-    say("c2 admm 2 iterations")
+def test_share2048_admm_invariants(P, big):
+    wl, plan = big["wl"], big["plan"]
+    say("big admm 2 iterations")
     psi = P.PsiPlan(wl.n, wl.levels, 0x1FF, P.PR_F32, DEV)
-    y = plan.apply(torch.as_tensor(c2["x"], dtype=torch.float32, device=DEV))
-    y, _, eps = W.add_noise_torch(y, W.unit_complex_noise_torch(wl.M, c2["gen"], DEV), wl.snr_db)
+    y = plan.apply(torch.as_tensor(big["x"], dtype=torch.float32, device=DEV))
+    y, _, eps = W.add_noise_torch(y, W.unit_complex_noise_torch(wl.M, big["gen"], DEV), wl.snr_db)
     prm = P.admm_params(eps, 0.0, iters=2, gamma_factor=1e-3, norm_iters=10)
     a, ra = P.admm_solve(plan, psi, y, prm)
     b, rb = P.admm_solve(plan, psi, y, prm)

@@ -1,7 +1,7 @@
 """Pins of the oracle's DualFB and ADMM (CPU only).
 
 The full SARA problem has no closed form ("parity unpinned" beyond its parts);
-these special cases reduce it to closed forms, and the C0-sized run is checked
+these special cases reduce it to closed forms, and the 64^2 / 8192-visibility run is checked
 against invariants of the method.
 """
 import math
@@ -73,7 +73,7 @@ def test_local_balls_imply_global_ball():
 
 
 def test_c0_sized_run_invariants():
-    w = W.CONFIGS["c0"]
+    w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng).astype(np.float64)

@@ -9,7 +9,7 @@ Workload shapes follow the paper's benchmark description (Section "Benchmark
 Timings" and "Application to Big-Data"): a random Gaussian density of
 baselines spanning +-pi on each axis, a Kaiser-Bessel kernel with J = 4, and a
 sky made of compact and extended sources. The sizes are the five workload
-configurations C0..C4 listed in ``CONFIGS``.
+workload configurations listed in ``CONFIGS``.
 
 Conventions shared with every consumer:
   * image ``x`` is real, shape (n, n), row index = v axis, column = u axis;
@@ -164,12 +164,12 @@ class Workload:
 
 CONFIGS = {
     # plain FP64 ADMM, seconds on a CPU
-    "c0": Workload("c0-64sq-M8192-J4-fp64", 0, 64, 2, 8192, 4, 2000, 3, 50),
+    "admm64": Workload("admm-64sq-M8192-J4-fp64", 0, 64, 2, 8192, 4, 2000, 3, 50),
     # single-operator throughput, J in {4, 6}
-    "c1": Workload("c1-256sq-M1e6-J4", 1, 256, 2, 1_000_000, 4, 2000, 4, 1),
-    "c1j6": Workload("c1-256sq-M1e6-J6", 1, 256, 2, 1_000_000, 6, 2000, 4, 1),
+    "op256": Workload("op-256sq-M1e6-J4", 1, 256, 2, 1_000_000, 4, 2000, 4, 1),
+    "op256j6": Workload("op-256sq-M1e6-J6", 1, 256, 2, 1_000_000, 6, 2000, 4, 1),
     # one GPU's share of the large distributed run
-    "c2": Workload("c2-2048sq-M5e8-J4-ringcore", 2, 2048, 2, 500_000_000, 4, 2000, 4, 20,
+    "share2048": Workload("share-2048sq-M5e8-J4-ringcore", 2, 2048, 2, 500_000_000, 4, 2000, 4, 20,
                    uv_law="ringcore"),
 }
 
