@@ -104,7 +104,7 @@ template <> struct FftCfg<double> { static constexpr int PB4 = 4; };
 
 inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
 
-// Lines per block: a power of two that fits 64 KB of LDS at stride K + 1
+// Lines per block: a power of two that fits 128 KB of LDS at stride K + 1
 // (the pad spreads column accesses over banks; a single line uses stride K),
 // small enough to give at least 256 blocks when there are enough lines. The
 // block has W * K / 4 threads (one radix-4 butterfly each), clamped to
@@ -113,7 +113,7 @@ template <typename R>
 inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
   const size_t per = static_cast<size_t>(K + 1) * sizeof(cx_t<R>);
   int w = 1;
-  while (static_cast<size_t>(2 * w) * per <= 65536 && 2 * w <= nlines && nlines / (2 * w) >= 256) w *= 2;
+  while (static_cast<size_t>(2 * w) * per <= 131072 && 2 * w <= nlines && nlines / (2 * w) >= 256) w *= 2;
   *W = w;
   *LS = w > 1 ? K + 1 : K;
   int t = w * K / 4;
