@@ -47,11 +47,11 @@ def problem(n, M, J=4, D=2000, seed=0, prec="f32", weights=False, uv_law="gaussi
     return x, uv, w, spec
 
 
-def make_plan(P, n, uv, w, J, D, prec="f32", tile=0):
+def make_plan(P, n, uv, w, J, D, prec="f32", tile=0, interp=0):
     rdt = torch.float32 if prec == "f32" else torch.float64
     uv_d = to_dev(uv, rdt)
     w_d = None if w is None else to_dev(w, rdt)
-    plan = P.PhiPlan(n, uv_d, w_d, J=J, D=D, tile=tile, prec=P.PR_F32 if prec == "f32" else P.PR_F64)
+    plan = P.PhiPlan(n, uv_d, w_d, J=J, D=D, tile=tile, prec=P.PR_F32 if prec == "f32" else P.PR_F64, interp=interp)
     perm = plan.perm().cpu().numpy() if uv.shape[0] else np.zeros(0, dtype=np.int64)
     return plan, perm
 

@@ -21,12 +21,12 @@ def P():
     return purimi()
 
 
-def c0_data():
+def c0_data(interp="nearest"):
     w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)
-    spec = ms.PhiSpec(w.n, w.K, w.J, w.D)
+    spec = ms.PhiSpec(w.n, w.K, w.J, w.D, interp)
     uv64 = uv.astype(np.float64)
     y0 = ms.phi(x_true, uv64, None, spec)
     y, _, _ = W.add_noise(y0, W.unit_complex_noise(w.M, rng), w.snr_db)
@@ -45,8 +45,8 @@ def oracle_fista(w, uv64, spec, y, iters, lam, inner_iters=1, norm_iters=100):
     return x, rep, gamma, nrm, obj
 
 
-def run_gpu(P, w, uv, uv64, y, prec, prm):
-    plan, perm = make_plan(P, w.n, uv if prec == "f32" else uv64, None, w.J, w.D, prec)
+def run_gpu(P, w, uv, uv64, y, prec, prm, interp=0):
+    plan, perm = make_plan(P, w.n, uv if prec == "f32" else uv64, None, w.J, w.D, prec, interp=interp)
     psi = P.PsiPlan(w.n, w.levels, 0x1FF, P.PR_F32 if prec == "f32" else P.PR_F64, DEV)
     cdt = torch.complex64 if prec == "f32" else torch.complex128
     y_plan = to_dev(y[perm], cdt)
@@ -104,3 +104,13 @@ def test_fista_zero_iterations_and_determinism(P):
     a, _ = P.fista_solve(plan, psi, y_plan, prm)
     b, _ = P.fista_solve(plan, psi, y_plan, prm)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_fista_first_order_lookup(P, prec, tol):
+    say(f"fista admm64 first-order lookup {prec}")
+    w, uv, uv64, spec, y = c0_data("linear")
+    x_ref, _, gamma, nrm, _ = oracle_fista(w, uv64, spec, y, 20, 1.0)
+    _, (x, rep) = run_gpu(P, w, uv, uv64, y, prec, P.fista_params(gamma, 1.0, iters=20, op_norm=nrm), interp=1)
+    assert rep.nonfinite == 0
+    assert rel_l2(x.cpu().numpy(), x_ref) <= tol

@@ -24,12 +24,12 @@ def P():
     return purimi()
 
 
-def c0_data():
+def c0_data(J=None):
     w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)
-    spec = ms.PhiSpec(w.n, w.K, w.J, w.D)
+    spec = ms.PhiSpec(w.n, w.K, w.J if J is None else J, w.D)
     uv64 = uv.astype(np.float64)
     y0 = ms.phi(x_true, uv64, None, spec)
     y, sigma, eps = W.add_noise(y0, W.unit_complex_noise(w.M, rng), w.snr_db)
@@ -60,8 +60,8 @@ def oracle_local(w, uv64, spec, y, sec, eps_j, iters):
     return x, rep, gamma, nrm
 
 
-def gpu_local(P, w, uv, uv64, y, sec, nsec, eps_j, prec, prm):
-    plan, perm = make_plan(P, w.n, uv if prec == "f32" else uv64, None, w.J, w.D, prec)
+def gpu_local(P, w, uv, uv64, y, sec, nsec, eps_j, prec, prm, J=None):
+    plan, perm = make_plan(P, w.n, uv if prec == "f32" else uv64, None, w.J if J is None else J, w.D, prec)
     psi = P.PsiPlan(w.n, w.levels, 0x1FF, P.PR_F32 if prec == "f32" else P.PR_F64, DEV)
     y_plan = to_dev(y[perm], torch.complex64 if prec == "f32" else torch.complex128)
     balls = P.Balls(plan, torch.as_tensor(sec[perm]).to(DEV), nsec)
@@ -129,3 +129,15 @@ def test_bad_section_ids_are_refused_and_solves_repeat(P):
     a, _ = P.admm_local_solve(plan, psi, balls, y_plan, prm, radii(sec, 4, sigma))
     b, _ = P.admm_local_solve(plan, psi, balls, y_plan, prm, radii(sec, 4, sigma))
     assert torch.equal(a, b)
+
+
+def test_local_balls_with_the_j_lane_gridding(P):
+    say("local balls admm64 J=6 f64")
+    w, uv, uv64, spec, y, sigma, _ = c0_data(J=6)
+    sec = length_sections(uv64, 4)
+    eps_j = radii(sec, 4, sigma)
+    x_ref, _, gamma, nrm = oracle_local(w, uv64, spec, y, sec, eps_j, 10)
+    x, rep, *_ = gpu_local(P, w, uv, uv64, y, sec, 4, eps_j, "f64", P.admm_params(0.0, gamma, iters=10, op_norm=nrm),
+                           J=6)
+    assert rep.nonfinite == 0
+    assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-10

@@ -22,13 +22,13 @@ def P():
     return purimi()
 
 
-def c0_data(J=None):
+def c0_data(J=None, interp="nearest"):
     w = W.CONFIGS["admm64"]
     rng = W.rng_for(w.index)
     x_true = W.make_sky(w, rng)
     uv = W.make_uv(w, rng)
     J = w.J if J is None else J
-    spec = ms.PhiSpec(w.n, w.K, J, w.D)
+    spec = ms.PhiSpec(w.n, w.K, J, w.D, interp)
     uv64 = uv.astype(np.float64)
     y0 = ms.phi(x_true, uv64, None, spec)
     y, _, eps = W.add_noise(y0, W.unit_complex_noise(w.M, rng), w.snr_db)
@@ -46,8 +46,8 @@ def oracle_pd(w, uv64, spec, y, eps, misfit, iters, tau, sigma, theta, inner=1):
     return x, rep, gamma, nrm
 
 
-def run_gpu(P, w, J, uv, uv64, y, prec, prm):
-    plan, perm = make_plan(P, w.n, uv if prec == "f32" else uv64, None, J, w.D, prec)
+def run_gpu(P, w, J, uv, uv64, y, prec, prm, interp=0):
+    plan, perm = make_plan(P, w.n, uv if prec == "f32" else uv64, None, J, w.D, prec, interp=interp)
     psi = P.PsiPlan(w.n, w.levels, 0x1FF, P.PR_F32 if prec == "f32" else P.PR_F64, DEV)
     y_plan = to_dev(y[perm], torch.complex64 if prec == "f32" else torch.complex128)
     return P.pd_solve(plan, psi, y_plan, prm)
@@ -107,3 +107,15 @@ def test_pd_parameter_checks_and_determinism(P):
     a, _ = P.pd_solve(plan, psi, y_plan, prm)
     b, _ = P.pd_solve(plan, psi, y_plan, prm)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("misfit", ["ball", "l2"])
+def test_pd_first_order_lookup(P, misfit):
+    say(f"pd admm64 first-order lookup {misfit} f64")
+    w, J, uv, uv64, spec, y, eps = c0_data(interp="linear")
+    x_ref, _, gamma, nrm = oracle_pd(w, uv64, spec, y, eps, misfit, 10, 0.5, 1.0, 1.0)
+    mis = P.PR_PD_BALL if misfit == "ball" else P.PR_PD_L2
+    x, rep = run_gpu(P, w, J, uv, uv64, y, "f64",
+                     P.pd_params(gamma, 0.5, 1.0, 1.0, iters=10, misfit=mis, eps=eps, op_norm=nrm), interp=1)
+    assert rep.nonfinite == 0
+    assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-10
