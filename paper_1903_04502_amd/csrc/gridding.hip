@@ -72,12 +72,6 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   extern __shared__ char smem_raw[];
   const int tid = threadIdx.x;
   C* patch = reinterpret_cast<C*>(smem_raw);
-  const R* tab = a.table;
-  if (TAB_LDS) {
-    R* t = reinterpret_cast<R*>(smem_raw + align16(static_cast<size_t>(a.P) * a.P * sizeof(C)));
-    for (int i = tid; i < a.tlen; i += kThreads) t[i] = a.table[i];
-    tab = t;
-  }
   const int P = a.P, T = a.T, K = a.K;
   double sum_t = 0.0, sum_r = 0.0;
   // inputs of this thread's visibilities for the current and the next chunk
@@ -93,11 +87,22 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       }
     }
   };
-  const int kend = a.sched_off[blockIdx.x + 1];
-  for (int ks = a.sched_off[blockIdx.x]; ks < kend; ++ks) {
+  const int kbeg = a.sched_off[blockIdx.x], kend = a.sched_off[blockIdx.x + 1];
+  // the first item's visibilities are in flight while the table is copied
+  if (kbeg < kend) {
+    const int4 it0 = a.items[kbeg];
+    load(it0.y, it0.z, cu_, cv_, cw_);
+  }
+  const R* tab = a.table;
+  if (TAB_LDS) {
+    R* t = reinterpret_cast<R*>(smem_raw + align16(static_cast<size_t>(a.P) * a.P * sizeof(C)));
+    for (int i = tid; i < a.tlen; i += kThreads) t[i] = a.table[i];
+    tab = t;
+  }
+  for (int ks = kbeg; ks < kend; ++ks) {
     const int4 it = a.items[ks];
     const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
-    load(it.y, it.z, cu_, cv_, cw_);
+    if (ks > kbeg) load(it.y, it.z, cu_, cv_, cw_);
     __syncthreads();
     const float invP = 1.0f / P;
     for (int i = tid; i < P * P; i += kThreads) {
@@ -597,11 +602,6 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   unsigned long long* helpmask = nonmid + kThreads / 64;                                       // per wave
   const int tid = threadIdx.x;
   const R* tab = a.table;
-  if (TAB_LDS) {
-    R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
-    for (int i = tid; i < a.tlen; i += kThreads) t[i] = a.table[i];
-    tab = t;
-  }
   const int T = a.T, P = a.P, K = a.K;
   const int TT = T * T;
   R kappa_ball = 1;
@@ -680,6 +680,12 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     it = a.items[kbeg];
     L = seg_len(it);
     issue(it, L, 0);
+  }
+  // the table copy overlaps the first chunk's loads
+  if (TAB_LDS) {
+    R* t = reinterpret_cast<R*>(smem_raw + lay.tab);
+    for (int i = tid; i < a.tlen; i += kThreads) t[i] = a.table[i];
+    tab = t;
   }
   for (int ks = kbeg; ks < kend; ++ks) {
     const int64_t item = it.w;
