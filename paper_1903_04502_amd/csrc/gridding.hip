@@ -129,11 +129,8 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
           continue;
         }
         R wu[J], wv[J];
-#pragma unroll
-        for (int q = 0; q < J; ++q) {
-          wu[q] = tap_weight<LIN>(tab, xu, q, J, a.D, a.tlen);
-          wv[q] = tap_weight<LIN>(tab, xv, q, J, a.D, a.tlen);
-        }
+        axis_weights<LIN, J>(tab, xu, a.D, a.tlen, wu);
+        axis_weights<LIN, J>(tab, xv, a.D, a.tlen, wv);
         R accr = 0, acci = 0;
 #pragma unroll
         for (int b = 0; b < J; ++b) {
@@ -380,10 +377,13 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
         const int si = (i & (L - 1)) * NS + (i >> lgL);
         st_cell[si] = lv * T + lu;
         st_yw[si] = val;
+        R wu_[J], wv_[J];
+        axis_weights<LIN, J>(tab, xu, a.D, a.tlen, wu_);
+        axis_weights<LIN, J>(tab, xv, a.D, a.tlen, wv_);
 #pragma unroll
         for (int q = 0; q < J; ++q) {
-          st_wu[q * B + si] = tap_weight<LIN>(tab, xu, q, J, a.D, a.tlen);
-          st_wv[q * B + si] = tap_weight<LIN>(tab, xv, q, J, a.D, a.tlen);
+          st_wu[q * B + si] = wu_[q];
+          st_wv[q * B + si] = wv_[q];
         }
       }
       __syncthreads();
@@ -745,12 +745,12 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 #pragma unroll
           for (int e = 0; e < JJ; ++e) ar[e] = ai[e] = R(0);
         }
-        R wv[J];
-#pragma unroll
-        for (int b = 0; b < J; ++b) wv[b] = tap_weight<LIN>(tab, xv, b, J, a.D, a.tlen);
+        R wv[J], wu[J];
+        axis_weights<LIN, J>(tab, xv, a.D, a.tlen, wv);
+        axis_weights<LIN, J>(tab, xu, a.D, a.tlen, wu);
 #pragma unroll
         for (int qq = 0; qq < J; ++qq) {
-          const R g = tap_weight<LIN>(tab, xu, qq, J, a.D, a.tlen);
+          const R g = wu[qq];
           const R yr = val.x * g, yi = val.y * g;
 #pragma unroll
           for (int b = 0; b < J; ++b) {
@@ -1121,6 +1121,10 @@ GwArgs<R> gw_args(pr_phi_plan_t* p, double scale) {
   a.lognT = 0;
   while ((1 << a.lognT) < p->nT) ++a.lognT;
   a.tlen = p->J * p->D / 2 + 1;
+  if (p->J == 4 && !p->interp) {   // nearest sample, J = 4: the paired table
+    a.table = static_cast<const R*>(p->table2);
+    a.tlen = 2 * p->D + 2;
+  }
   a.kappa = p->kappa;
   a.scale = static_cast<R>(scale);
   return a;
@@ -1139,6 +1143,10 @@ GwAdjArgs<R> gwadj_args(pr_phi_plan_t* p, double scale) {
   a.lognT = 0;
   while ((1 << a.lognT) < p->nT) ++a.lognT;
   a.tlen = p->J * p->D / 2 + 1;
+  if (p->J == 4 && !p->interp) {   // nearest sample, J = 4: the paired table
+    a.table = static_cast<const R*>(p->table2);
+    a.tlen = 2 * p->D + 2;
+  }
   a.kappa = p->kappa;
   a.scale = static_cast<R>(scale);
   a.patches = static_cast<cx_t<R>*>(p->patches);

@@ -32,6 +32,7 @@ struct pr_phi_plan_t {
   int4* sched_g = nullptr;         // gridding, [nItemsMax]
   int32_t* sched_g_off = nullptr;  // [kGridBlocks + 1]
   void* table = nullptr;       // Real[J*D/2 + 1]
+  void* table2 = nullptr;      // J = 4: pairs (T[i], T[D + i]), i = 0..D (Real[2D + 2]); else unused
   void* corr = nullptr;        // Real[n]
   void* tw = nullptr;          // complex[K], e^{-2 pi i m / K}
 

@@ -66,6 +66,17 @@ __global__ void build_tables_kernel(R* table, int table_len, R* corr, cx_t<R>* t
   }
 }
 
+// J = 4: the four nearest-sample taps of an axis read T[up], T[D + up],
+// T[D - dn] and T[2D - dn]; stored as pairs (T[i], T[D + i]) they take two
+// loads, T2[up] and T2[D - dn].
+template <typename R>
+__global__ void pair_table_kernel(const R* table, int D, R* table2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > D) return;
+  table2[2 * i] = table[i];
+  table2[2 * i + 1] = table[D + i];
+}
+
 // ---------------------------------------------------------------------------
 // keys, radix sort, scan
 // ---------------------------------------------------------------------------
@@ -430,6 +441,7 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   p->sched_g = a.take<int4>(p->nItemsMax);
   p->sched_g_off = a.take<int32_t>(kGridBlocks + 1);
   p->table = a.take<char>((p->J * static_cast<int64_t>(p->D) / 2 + 1) * rs);
+  p->table2 = a.take<char>(p->J == 4 ? (2 * static_cast<int64_t>(p->D) + 2) * rs : 0);
   p->corr = a.take<char>(p->n * rs);
   p->tw = a.take<char>(p->K * 2 * rs);
   if (persistent_bytes) *persistent_bytes = a.bytes();
@@ -524,6 +536,11 @@ static int create_impl(pr_phi_plan_t* p, const R* uv, const R* w, hipStream_t s)
       static_cast<R*>(p->table), tlen, static_cast<R*>(p->corr), static_cast<cx_t<R>*>(p->tw), p->n, p->K,
       p->J, p->D, p->beta);
   PR_TRY_LAUNCH();
+  if (p->J == 4) {
+    pair_table_kernel<R><<<(p->D + 1 + 255) / 256, 256, 0, s>>>(static_cast<const R*>(p->table), p->D,
+                                                                 static_cast<R*>(p->table2));
+    PR_TRY_LAUNCH();
+  }
 
   Carver c(p->grid);  // plan-time scratch aliases the operator scratch
   CreateScratch cs = carve_create(p, c);

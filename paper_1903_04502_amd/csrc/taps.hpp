@@ -19,6 +19,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace pr {
 
 struct AxisTaps {
@@ -75,6 +77,26 @@ __device__ __forceinline__ R tap_weight(const R* tab, const AxisTaps& t, int a, 
     const int i1 = i + 1 < tlen ? i + 1 : tlen - 1;
     const R p = static_cast<R>(ph);
     return (R(1) - p) * tab[i] + p * tab[i1];
+  }
+}
+
+// All J weights of an axis. J = 4 with the nearest sample reads the paired
+// table (T[i], T[D + i]) (see the plan): two loads instead of four.
+template <bool LIN, int J, typename R>
+__device__ __forceinline__ void axis_weights(const R* tab, const AxisTaps& t, int D, int tlen, R* w) {
+  if constexpr (J == 4 && !LIN) {
+    (void)tlen;
+    using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+    const R2* t2 = reinterpret_cast<const R2*>(tab);
+    const R2 p0 = t2[t.up];        // (T[up], T[D + up]): taps m = 0, 1
+    const R2 p1 = t2[D - t.dn];    // (T[D - dn], T[2D - dn]): taps m = -1, -2
+    w[0] = p0.y;
+    w[1] = p0.x;
+    w[2] = p1.x;
+    w[3] = p1.y;
+  } else {
+#pragma unroll
+    for (int a = 0; a < J; ++a) w[a] = tap_weight<LIN>(tab, t, a, J, D, tlen);
   }
 }
 
