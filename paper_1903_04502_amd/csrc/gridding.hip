@@ -587,13 +587,14 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int WC = WalkChunk<R>::value;
-  constexpr int CB = kStagePitch * WC;
   constexpr int kSegStride = kThreads / WC;
   extern __shared__ char smem_raw[];
   const WalkLds<R, J> lay(a.T, a.tlen, TAB_LDS);
   C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
-  C* st_uv = reinterpret_cast<C*>(smem_raw + lay.stage);        // (u, v)
-  C* st_val = st_uv + CB;                                         // weighted value
+  // staged position: (u, v) and the weighted value side by side (one 16-byte
+  // LDS access in FP32)
+  struct Staged { C uv, val; };
+  Staged* st = reinterpret_cast<Staged*>(smem_raw + lay.stage);
   C* side = reinterpret_cast<C*>(smem_raw + lay.stage);          // after the walk
   int* fcell = reinterpret_cast<int*>(smem_raw + lay.fcell);
   int* lcell = reinterpret_cast<int*>(smem_raw + lay.lcell);
@@ -661,8 +662,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       if (ok) {
         if (MODE == 1) a.s_io[it.y + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
         const int slot = lane_q * kStagePitch + lane_t + r * kSegStride;
-        st_uv[slot] = uvr;
-        st_val[slot] = wv;
+        st[slot] = Staged{uvr, wv};
       }
     }
     // every prefetched load has landed (the values above needed them): say so
@@ -718,8 +718,9 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       __syncthreads();
       const int qn = min(WC, segn - q0);
       for (int i = 0; i < qn; ++i) {
-        const C uv = st_uv[i * kStagePitch + tid];
-        C val = st_val[i * kStagePitch + tid];
+        const Staged sp = st[i * kStagePitch + tid];
+        const C uv = sp.uv;
+        C val = sp.val;
         const AxisTaps xu = axis_taps(static_cast<double>(uv.x), a.kappa, J, a.D);
         const AxisTaps xv = axis_taps(static_cast<double>(uv.y), a.kappa, J, a.D);
         int lu = mod_pow2(xu.j0, K) - tu * T;
