@@ -46,8 +46,8 @@ template <typename R>
 struct GwArgs {
   const cx_t<R>* grid;
   const R* table;
-  const R* uv;
-  const R* w;
+  const R* uv;               // (u, v, w) triples, plan order
+  const R* w;                // unused
   const int4* items;         // this launch's schedule: (tile, begin, end, item index); block b takes
   const int32_t* sched_off;  // entries [sched_off[b], sched_off[b + 1])
   int64_t nItems;
@@ -81,9 +81,9 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
     for (int j = 0; j < kDegridPer; ++j) {
       const int64_t k = c0 + tid + j * kThreads;
       if (k < cend) {
-        u[j] = a.uv[2 * k];
-        v[j] = a.uv[2 * k + 1];
-        w[j] = a.w[k];
+        u[j] = a.uv[3 * k];
+        v[j] = a.uv[3 * k + 1];
+        w[j] = a.uv[3 * k + 2];
       }
     }
   };
@@ -184,8 +184,8 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
 template <typename R>
 struct GwAdjArgs {
   const R* table;
-  const R* uv;
-  const R* w;
+  const R* uv;               // (u, v, w) triples, plan order
+  const R* w;                // unused
   const int4* items;         // this launch's schedule: (tile, begin, end, item index); block b takes
   const int32_t* sched_off;  // entries [sched_off[b], sched_off[b + 1])
   int64_t nItems;
@@ -307,9 +307,9 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
       const int i = tid + j * kThreads;
       if (i < n0) {
         const int64_t k = b0 + i;
-        ru[j] = a.uv[2 * k];
-        rv[j] = a.uv[2 * k + 1];
-        rw[j] = a.w[k];
+        ru[j] = a.uv[3 * k];
+        rv[j] = a.uv[3 * k + 1];
+        rw[j] = a.uv[3 * k + 2];
         if (MODE == 0) {
           ry[j] = a.y_in[k];
         } else {
@@ -607,7 +607,6 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   const int TT = T * T;
   R kappa_ball = 1;
   if (MODE == 1) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
-  const C* uv2 = reinterpret_cast<const C*>(a.uv);
   const int lane_q = tid & (WC - 1);      // position within the chunk this thread loads
   const int lane_t = tid / WC;            // first segment this thread loads for
 
@@ -625,8 +624,8 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       const bool ok = q < L && pos < it.z;
       pf.ok |= static_cast<unsigned>(ok) << r;
       const int pc = ok ? pos : it.y;
-      pf.uv[r] = uv2[pc];
-      pf.w[r] = a.w[pc];
+      pf.uv[r] = cmk<C>(a.uv[3 * pc], a.uv[3 * pc + 1]);
+      pf.w[r] = a.uv[3 * pc + 2];
       if (MODE == 0) {
         pf.val[r] = a.y_in[pc];
       } else {

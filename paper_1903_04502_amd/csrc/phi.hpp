@@ -19,8 +19,8 @@ struct pr_phi_plan_t {
   double beta = 0;  // Kaiser-Bessel shape
 
   // persistent workspace
-  void* uv = nullptr;          // sorted (u, v) pairs, Real[2M]
-  void* w = nullptr;           // sorted weights, Real[M]
+  void* uv = nullptr;          // sorted (u, v, w) triples, Real[3M] (one load per visibility)
+  void* w = nullptr;           // unused (the weights sit in the triples)
   int32_t* perm = nullptr;     // plan position -> user index
   int32_t* item_off = nullptr; // per tile first work item, [nTiles + 1]
   int4* items = nullptr;       // (tile, begin, end, 0)

@@ -309,13 +309,13 @@ __global__ void item_fill_kernel(const int32_t* tile_start, const uint32_t* item
 
 template <typename R>
 __global__ void gather_sorted_kernel(const R* uv, const R* w, const uint32_t* perm, int64_t M,
-                                     R* uv_out, R* w_out, int32_t* perm_out) {
+                                     R* uvw_out, int32_t* perm_out) {
   const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (k >= M) return;
   const uint32_t j = perm[k];
-  uv_out[2 * k] = uv[2 * static_cast<int64_t>(j)];
-  uv_out[2 * k + 1] = uv[2 * static_cast<int64_t>(j) + 1];
-  w_out[k] = w ? w[j] : R(1);
+  uvw_out[3 * k] = uv[2 * static_cast<int64_t>(j)];
+  uvw_out[3 * k + 1] = uv[2 * static_cast<int64_t>(j) + 1];
+  uvw_out[3 * k + 2] = w ? w[j] : R(1);
   perm_out[k] = static_cast<int32_t>(j);
 }
 
@@ -431,8 +431,8 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   const size_t rs = p->prec == PR_F32 ? 4 : 8;
   const int64_t M = p->M;
   Carver a(persistent);
-  p->uv = a.take<char>(2 * M * rs);
-  p->w = a.take<char>(M * rs);
+  p->uv = a.take<char>(3 * M * rs);   // (u, v, w) per visibility, plan order
+  p->w = nullptr;
   p->perm = a.take<int32_t>(M);
   p->item_off = a.take<int32_t>(p->nTiles + 1);
   p->items = a.take<int4>(p->nItemsMax);
@@ -561,8 +561,7 @@ static int create_impl(pr_phi_plan_t* p, const R* uv, const R* w, hipStream_t s)
       std::swap(kin, kout);
       std::swap(vin, vout);
     }
-    gather_sorted_kernel<R><<<gb, 256, 0, s>>>(uv, w, vin, M, static_cast<R*>(p->uv), static_cast<R*>(p->w),
-                                               p->perm);
+    gather_sorted_kernel<R><<<gb, 256, 0, s>>>(uv, w, vin, M, static_cast<R*>(p->uv), p->perm);
     PR_TRY_LAUNCH();
     const int nt1 = p->nTiles + 1;
     tile_bounds_kernel<<<(nt1 + 255) / 256, 256, 0, s>>>(kin, M, p->nTiles, p->T * p->T, cs.tile_start);
