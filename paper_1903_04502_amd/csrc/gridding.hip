@@ -47,7 +47,6 @@ struct GwArgs {
   const cx_t<R>* grid;
   const R* table;
   const R* uv;               // (u, v, w) triples, plan order
-  const R* w;                // unused
   const int4* items;         // this launch's schedule: (tile, begin, end, item index); block b takes
   const int32_t* sched_off;  // entries [sched_off[b], sched_off[b + 1])
   int64_t nItems;
@@ -185,7 +184,6 @@ template <typename R>
 struct GwAdjArgs {
   const R* table;
   const R* uv;               // (u, v, w) triples, plan order
-  const R* w;                // unused
   const int4* items;         // this launch's schedule: (tile, begin, end, item index); block b takes
   const int32_t* sched_off;  // entries [sched_off[b], sched_off[b + 1])
   int64_t nItems;
@@ -1113,7 +1111,6 @@ GwArgs<R> gw_args(pr_phi_plan_t* p, double scale) {
   a.grid = static_cast<const cx_t<R>*>(p->grid);
   a.table = static_cast<const R*>(p->table);
   a.uv = static_cast<const R*>(p->uv);
-  a.w = static_cast<const R*>(p->w);
   a.items = p->sched_d;
   a.sched_off = p->sched_d_off;
   a.nItems = p->nItems;
@@ -1135,7 +1132,6 @@ GwAdjArgs<R> gwadj_args(pr_phi_plan_t* p, double scale) {
   GwAdjArgs<R> a{};
   a.table = static_cast<const R*>(p->table);
   a.uv = static_cast<const R*>(p->uv);
-  a.w = static_cast<const R*>(p->w);
   a.items = p->sched_g;
   a.sched_off = p->sched_g_off;
   a.nItems = p->nItems;

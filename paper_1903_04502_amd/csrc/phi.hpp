@@ -20,7 +20,6 @@ struct pr_phi_plan_t {
 
   // persistent workspace
   void* uv = nullptr;          // sorted (u, v, w) triples, Real[3M] (one load per visibility)
-  void* w = nullptr;           // unused (the weights sit in the triples)
   int32_t* perm = nullptr;     // plan position -> user index
   int32_t* item_off = nullptr; // per tile first work item, [nTiles + 1]
   int4* items = nullptr;       // (tile, begin, end, 0)

@@ -432,7 +432,6 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   const int64_t M = p->M;
   Carver a(persistent);
   p->uv = a.take<char>(3 * M * rs);   // (u, v, w) per visibility, plan order
-  p->w = nullptr;
   p->perm = a.take<int32_t>(M);
   p->item_off = a.take<int32_t>(p->nTiles + 1);
   p->items = a.take<int4>(p->nItemsMax);
