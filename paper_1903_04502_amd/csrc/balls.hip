@@ -8,11 +8,10 @@
 // iteration, after the degridding has written t = v + s - y:
 //   piece sums   sum |t|^2 over a piece (FP64, fixed tree)     section_sq_kernel
 //   section sums pieces of a section in order; kappa_j         section_kappa_kernel
-//   update       s' = s + varrho ((1 - kappa_j) t - s), q = (v - r) + s'
-//                (the same prologue as the fused gridding), q over t
-//                                                              local_update_kernel
-// and q is gridded with the plain gridding. Every reduction has a fixed
-// order, so the result is bitwise repeatable.
+// and the fused gridding of Algorithm 1 applies, per visibility, the
+// projection and multiplier update with its section's kappa_j (read through
+// the section id) before gridding. Every reduction has a fixed order, so the
+// result is bitwise repeatable.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -144,22 +143,8 @@ __global__ void section_kappa_kernel(const int32_t* pfirst, const double* piece_
   kappa[j] = nt <= eps[j] ? 1.0 : eps[j] / nt;
 }
 
-template <typename R>
-__global__ void local_update_kernel(cx_t<R>* t, cx_t<R>* s, const int32_t* section, const double* kappa, int64_t M,
-                                    R varrho) {
-  using C = cx_t<R>;
-  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < M;
-       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const R omk = R(1) - static_cast<R>(kappa[section[k]]);
-    const C tt = t[k], sk = s[k];
-    const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
-    const C sn = cmk<C>(sk.x + varrho * vr.x, sk.y + varrho * vr.y);
-    s[k] = sn;
-    t[k] = cmk<C>(vr.x + sn.x, vr.y + sn.y);
-  }
-}
-
-int balls_update(pr_balls_t* b, void* t, void* s, int prec, double varrho, hipStream_t st) {
+// ||t_j||^2 and kappa_j = min(1, eps_j / ||t_j||) of every section.
+int balls_kappa(pr_balls_t* b, const void* t, int prec, hipStream_t st) {
   if (b->npieces > 0) {
     const int G = static_cast<int>(std::min<int64_t>(b->npieces, 8192));
     if (prec == PR_F32)
@@ -173,16 +158,6 @@ int balls_update(pr_balls_t* b, void* t, void* s, int prec, double varrho, hipSt
   section_kappa_kernel<<<(b->nsec + 255) / 256, 256, 0, st>>>(b->pfirst, b->piece_sum, b->eps, b->nsec, b->kappa,
                                                               b->norm2);
   PR_TRY_LAUNCH();
-  if (b->M > 0) {
-    const int G = grid_for(b->M, 256, 8192);
-    if (prec == PR_F32)
-      local_update_kernel<float><<<G, 256, 0, st>>>(static_cast<float2*>(t), static_cast<float2*>(s), b->section,
-                                                    b->kappa, b->M, static_cast<float>(varrho));
-    else
-      local_update_kernel<double><<<G, 256, 0, st>>>(static_cast<double2*>(t), static_cast<double2*>(s), b->section,
-                                                     b->kappa, b->M, varrho);
-    PR_TRY_LAUNCH();
-  }
   return PR_OK;
 }
 
@@ -203,8 +178,10 @@ int local_step(AdmmJob* j, pr_balls_t* b, hipStream_t s) {
   const double* gamma_dev = j->device_gamma ? w.sums + kSumGamma : nullptr;
   PR_TRY(phi_fzs(phi, j->x, s));
   PR_TRY(phi_gw_admm(phi, av, 1.0, s));
-  PR_TRY(balls_update(b, w.t, w.s, phi->prec, prm.varrho, s));
-  PR_TRY(phi_gw_adjoint_dev(phi, w.t, w.sums + kSumScale, s));
+  PR_TRY(balls_kappa(b, w.t, phi->prec, s));
+  av.sec = b->section;
+  av.kappa_sec = b->kappa;
+  PR_TRY(phi_gw_adjoint_admm(phi, av, 1.0, s));
   PR_TRY(phi_fzs_adjoint_step(phi, j->x, prm.rho, w.xt, w.zbar, s));
   for (int k = 0; k < prm.inner_iters; ++k) {
     PR_TRY(psi_dual_update(psi, w.zbar, 0, w.d, prm.gamma, prm.eta, s, gamma_dev));

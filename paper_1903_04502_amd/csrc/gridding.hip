@@ -197,6 +197,8 @@ struct GwAdjArgs {
   const double* scalars;     // MODE 1: ball scale at kSlotKappa
   R varrho;
   R vr_coef;                 // MODE 1: gridded q = vr_coef (v - r) + s' (1 Algorithm 1, 0 primal-dual)
+  const int32_t* sec;        // MODE 1, local balls: section of each visibility (plan order), or null
+  const double* kappa_sec;   // MODE 1, local balls: kappa of each section
   cx_t<R>* patches;
 };
 
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
           // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
           // r = y + kappa t, s' = s + varrho (v - r), q = vr_coef (v - r) + s'
           const C t = ry[j], sk = rs[j];
-          const R omk = R(1) - kappa_ball;
+          const R omk = R(1) - (a.kappa_sec ? static_cast<R>(a.kappa_sec[a.sec[k]]) : kappa_ball);
           const C vr = cmk<C>(omk * t.x - sk.x, omk * t.y - sk.y);   // v - r
           const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
           a.s_io[k] = sn;
@@ -557,6 +559,7 @@ struct WalkPrefetch {
   C uv[WC];
   C val[WC];                      // MODE 0: y; MODE 1: t = v + s - y
   C s[MODE == 1 ? WC : 1];        // MODE 1: multiplier before the update
+  int sec[MODE == 1 ? WC : 1];    // MODE 1 with local balls: section of the position
   R w[WC];
   unsigned ok;                    // bit r: slot r holds a position of the item
 };
@@ -629,6 +632,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       } else {
         pf.val[r] = a.t_in[pc];
         pf.s[MODE == 1 ? r : 0] = a.s_io[pc];
+        if (a.sec) pf.sec[MODE == 1 ? r : 0] = a.sec[pc];
       }
     }
   };
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
         // r = y + kappa t, s' = s + varrho (v - r), q = vr_coef (v - r) + s'
         const C tt = pf.val[r], sk = pf.s[MODE == 1 ? r : 0];
-        const R omk = R(1) - kappa_ball;
+        const R omk = R(1) - (a.kappa_sec ? static_cast<R>(a.kappa_sec[pf.sec[MODE == 1 ? r : 0]]) : kappa_ball);
         const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
         sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
         val = cmk<C>(a.vr_coef * vr.x + sn.x, a.vr_coef * vr.y + sn.y);
@@ -1211,6 +1215,8 @@ int gwadj_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) 
   a.scalars = v.sums;
   a.varrho = static_cast<R>(v.varrho);
   a.vr_coef = static_cast<R>(v.vr_coef);
+  a.sec = v.sec;
+  a.kappa_sec = v.kappa_sec;
 #define CALL(JJ) (p->interp ? launch_grid<R, JJ, 1, true>(p, a, s) : launch_grid<R, JJ, 1, false>(p, a, s))
   PR_DISPATCH_J(p->J, CALL)
 #undef CALL

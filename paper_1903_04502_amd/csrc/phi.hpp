@@ -93,6 +93,8 @@ struct AdmmVis {
   const double* scale_dev = nullptr;   // device 1 / ||Phi||; overrides the host scale when set
   double vr_coef = 1.0;       // gridded value q = vr_coef (v - r) + s' (1: Algorithm 1; 0: primal-dual, q = s')
   double kappa_fixed = -1.0;  // >= 0: r = y + kappa_fixed t instead of the ball projection
+  const int32_t* sec = nullptr;        // local balls: section of each visibility (plan order)
+  const double* kappa_sec = nullptr;   // local balls: kappa of each section (overrides the ball's)
 };
 int phi_gw_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);
 int phi_gw_adjoint_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);
