@@ -3,12 +3,15 @@
 // its own ball ||Phi_j x - y_j|| <= eps_j, and the r step of Algorithm 1
 // projects every section independently.
 //
-// Set-up (pr_balls_create) sorts the plan positions by section (stable radix
-// sort) and cuts every section's range into pieces of kPiece positions. Per
+// With at most kSecAcc sections the degridding epilogue of Algorithm 1 also
+// keeps one FP64 ||t_j||^2 partial per section and block, and one small kernel
+// sums them in block order into kappa_j. With more sections, set-up
+// (pr_balls_create) sorts the plan positions by section (stable radix sort)
+// and cuts every section's range into pieces of kPiece positions; per
 // iteration, after the degridding has written t = v + s - y:
 //   piece sums   sum |t|^2 over a piece (FP64, fixed tree)     section_sq_kernel
 //   section sums pieces of a section in order; kappa_j         section_kappa_kernel
-// and the fused gridding of Algorithm 1 applies, per visibility, the
+// In both cases the fused gridding of Algorithm 1 applies, per visibility, the
 // projection and multiplier update with its section's kappa_j (read through
 // the section id) before gridding. Every reduction has a fixed order, so the
 // result is bitwise repeatable.
@@ -177,9 +180,13 @@ int local_step(AdmmJob* j, pr_balls_t* b, hipStream_t s) {
   av.scale_dev = w.sums + kSumScale;
   const double* gamma_dev = j->device_gamma ? w.sums + kSumGamma : nullptr;
   PR_TRY(phi_fzs(phi, j->x, s));
-  PR_TRY(phi_gw_admm(phi, av, 1.0, s));
-  PR_TRY(balls_kappa(b, w.t, phi->prec, s));
   av.sec = b->section;
+  av.sec_partials = b->nsec <= kSecAcc;
+  PR_TRY(phi_gw_admm(phi, av, 1.0, s));
+  if (av.sec_partials)
+    PR_TRY(phi_section_kappa(phi, b->nsec, b->eps, b->kappa, b->norm2, s));
+  else
+    PR_TRY(balls_kappa(b, w.t, phi->prec, s));
   av.kappa_sec = b->kappa;
   PR_TRY(phi_gw_adjoint_admm(phi, av, 1.0, s));
   PR_TRY(phi_fzs_adjoint_step(phi, j->x, prm.rho, w.xt, w.zbar, s));

@@ -57,6 +57,7 @@ struct GwArgs {
   cx_t<R>* y_out;          // MODE 0
   const cx_t<R>* y_obs;    // MODE 1
   const cx_t<R>* s_in;
+  const int32_t* sec;         // MODE 2: section of each visibility (plan order)
   cx_t<R>* t_out;
   double* partials;
 };
@@ -73,6 +74,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   C* patch = reinterpret_cast<C*>(smem_raw);
   const int P = a.P, T = a.T, K = a.K;
   double sum_t = 0.0, sum_r = 0.0;
+  double sacc[MODE == 2 ? kSecAcc : 1] = {};   // MODE 2: ||t||^2 per section
   // inputs of this thread's visibilities for the current and the next chunk
   R cu_[kDegridPer], cv_[kDegridPer], cw_[kDegridPer], nu_[kDegridPer], nv_[kDegridPer], nw_[kDegridPer];
   auto load = [&](int c0, int cend, R* u, R* v, R* w) {
@@ -153,8 +155,14 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
           const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
           a.t_out[k] = t;
           const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
-          sum_t += tr * tr + ti * ti;
+          const double t2 = tr * tr + ti * ti;
+          sum_t += t2;
           sum_r += dr * dr + di * di;
+          if (MODE == 2) {
+            const int sj = a.sec[k];
+#pragma unroll
+            for (int jj = 0; jj < (MODE == 2 ? kSecAcc : 1); ++jj) sacc[jj] += sj == jj ? t2 : 0.0;
+          }
         }
       }
 #pragma unroll
@@ -165,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       }
     }
   }
-  if (MODE == 1) {
+  if (MODE >= 1) {
     __syncthreads();
     double* sh = reinterpret_cast<double*>(smem_raw);
     const double bt = block_sum_f64(sum_t, sh);
@@ -173,6 +181,13 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
     if (tid == 0) {
       a.partials[kSlotT2 * kPartialsMax + blockIdx.x] = bt;
       a.partials[kSlotR2 * kPartialsMax + blockIdx.x] = br;
+    }
+    if (MODE == 2) {
+#pragma unroll
+      for (int jj = 0; jj < (MODE == 2 ? kSecAcc : 1); ++jj) {
+        const double bj = block_sum_f64(sacc[jj], sh);
+        if (tid == 0) a.partials[(kSlotSec0 + jj) * kPartialsMax + blockIdx.x] = bj;
+      }
     }
   }
 }
@@ -954,6 +969,18 @@ __global__ void ball_scale_kernel(const double* partials, int nblocks, double ep
   }
 }
 
+// Local balls: ||t_j||^2 from the degridding partials (block order) and kappa_j.
+__global__ void section_kappa_partials_kernel(const double* partials, int nblocks, int nsec, const double* eps,
+                                              double* kappa, double* norm2) {
+  const int j = threadIdx.x;
+  if (j >= nsec) return;
+  double s2 = 0;
+  for (int i = 0; i < nblocks; ++i) s2 += partials[(kSlotSec0 + j) * kPartialsMax + i];
+  norm2[j] = s2;
+  const double nt = sqrt(s2);
+  kappa[j] = nt <= eps[j] ? 1.0 : eps[j] / nt;
+}
+
 int degrid_blocks(const pr_phi_plan_t* p) {
   return static_cast<int>(p->nItems < kDegridBlocks ? p->nItems : kDegridBlocks);
 }
@@ -985,7 +1012,7 @@ int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
   const size_t patch = align16(static_cast<size_t>(p->P) * p->P * sizeof(C));
   const size_t tabb = static_cast<size_t>(a.tlen) * sizeof(R);
   size_t lds = patch;
-  if (MODE == 1 && lds < kThreads * sizeof(double)) lds = kThreads * sizeof(double);
+  if (MODE >= 1 && lds < kThreads * sizeof(double)) lds = kThreads * sizeof(double);
   const int G = degrid_blocks(p);
   if (lds + tabb <= kLdsSoft) {
     degrid_kernel<R, J, MODE, true, LIN><<<G, kThreads, lds + tabb, s>>>(a);
@@ -1091,9 +1118,13 @@ int setup_mode() {
 template <typename R, int J>
 int setup_kernels(bool lin) {
   if (lin) {
+    PR_TRY((allow_lds(degrid_kernel<R, J, 2, true, true>, kLdsHard)));
+    PR_TRY((allow_lds(degrid_kernel<R, J, 2, false, true>, kLdsHard)));
     PR_TRY((setup_mode<R, J, 0, true>()));
     return setup_mode<R, J, 1, true>();
   }
+  PR_TRY((allow_lds(degrid_kernel<R, J, 2, true, false>, kLdsHard)));
+  PR_TRY((allow_lds(degrid_kernel<R, J, 2, false, false>, kLdsHard)));
   PR_TRY((setup_mode<R, J, 0, false>()));
   return setup_mode<R, J, 1, false>();
 }
@@ -1179,8 +1210,11 @@ int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
   a.s_in = static_cast<const cx_t<R>*>(v.s);
   a.t_out = static_cast<cx_t<R>*>(v.t);
   a.partials = p->partials;
+  a.sec = v.sec;
   int rc;
-#define CALL(JJ) (p->interp ? launch_degrid<R, JJ, 1, true>(p, a, s) : launch_degrid<R, JJ, 1, false>(p, a, s))
+#define CALL(JJ)                                                                                      \
+  (v.sec_partials ? (p->interp ? launch_degrid<R, JJ, 2, true>(p, a, s) : launch_degrid<R, JJ, 2, false>(p, a, s)) \
+                  : (p->interp ? launch_degrid<R, JJ, 1, true>(p, a, s) : launch_degrid<R, JJ, 1, false>(p, a, s)))
   switch (p->J) {
     case 2: rc = CALL(2); break;
     case 4: rc = CALL(4); break;
@@ -1270,6 +1304,16 @@ int phi_gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s)
     return PR_EINVAL;
   }
   return p->prec == PR_F32 ? gw_admm<float>(p, v, scale, s) : gw_admm<double>(p, v, scale, s);
+}
+
+int phi_section_kappa(pr_phi_plan_t* p, int nsec, const double* eps, double* kappa, double* norm2, hipStream_t s) {
+  if (nsec < 1 || nsec > kSecAcc) {
+    set_error("internal: %d sections in the degridding partials", nsec);
+    return PR_EINVAL;
+  }
+  section_kappa_partials_kernel<<<1, 64, 0, s>>>(p->partials, degrid_blocks(p), nsec, eps, kappa, norm2);
+  PR_TRY_LAUNCH();
+  return PR_OK;
 }
 
 int phi_gw_adjoint_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {

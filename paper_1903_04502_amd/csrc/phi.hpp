@@ -50,7 +50,9 @@ namespace pr {
 constexpr int kPartialsMax = 4096;     // per-block partials, per quantity slot
 constexpr int kDegridBlocks = 2048;    // persistent degridding blocks (8 per CU); <= kPartialsMax
 constexpr int kGridBlocks = 512;       // persistent gridding blocks (2 per CU, bound by LDS)
-constexpr int kPartialSlots = 4;
+constexpr int kSecAcc = 8;           // local balls: sections summed in the degridding epilogue
+constexpr int kSlotSec0 = 4;         // their per-block partials: slots kSlotSec0 .. kSlotSec0 + kSecAcc - 1
+constexpr int kPartialSlots = kSlotSec0 + kSecAcc;
 constexpr int kScalars = 64;
 
 // Sizes of the two workspaces for a descriptor (validated beforehand).
@@ -95,9 +97,14 @@ struct AdmmVis {
   double kappa_fixed = -1.0;  // >= 0: r = y + kappa_fixed t instead of the ball projection
   const int32_t* sec = nullptr;        // local balls: section of each visibility (plan order)
   const double* kappa_sec = nullptr;   // local balls: kappa of each section (overrides the ball's)
+  bool sec_partials = false;           // degridding: also FP64 ||t_j||^2 partials per section (< kSecAcc)
 };
 int phi_gw_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);
 int phi_gw_adjoint_admm(pr_phi_plan_t* p, const AdmmVis& a, double scale, hipStream_t s);
+// After phi_gw_admm with sec_partials: norm2[j] = ||t_j||^2 and
+// kappa[j] = min(1, eps[j] / ||t_j||) for j < nsec <= kSecAcc (device arrays),
+// the partials summed in block order.
+int phi_section_kappa(pr_phi_plan_t* p, int nsec, const double* eps, double* kappa, double* norm2, hipStream_t s);
 // x_out = x_in - rho * Re(S Z^T F^H grid), and zbar = max(x_out, 0).
 int phi_fzs_adjoint_step(pr_phi_plan_t* p, const void* x_in, double rho, void* x_out,
                          void* zbar, hipStream_t s);
