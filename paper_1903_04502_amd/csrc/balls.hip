@@ -135,12 +135,19 @@ __global__ __launch_bounds__(kBallThreads) void section_sq_kernel(const cx_t<R>*
   }
 }
 
-__global__ void section_kappa_kernel(const int32_t* pfirst, const double* piece_sum, const double* eps,
-                                     int32_t nsec, double* kappa, double* norm2) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nsec) return;
+// One wave per section: lane l sums pieces l, l + 64, ... of its section, then
+// a fixed xor-butterfly over the wave.
+__global__ __launch_bounds__(kBallThreads) void section_kappa_kernel(const int32_t* pfirst, const double* piece_sum,
+                                                                     const double* eps, int32_t nsec, double* kappa,
+                                                                     double* norm2) {
+  const int j = blockIdx.x * (kBallThreads / 64) + static_cast<int>(threadIdx.x >> 6);
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  if (j >= nsec) return;   // whole waves leave together
   double s2 = 0;
-  for (int p = pfirst[j]; p < pfirst[j + 1]; ++p) s2 += piece_sum[p];
+  for (int p = pfirst[j] + lane; p < pfirst[j + 1]; p += 64) s2 += piece_sum[p];
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) s2 += __shfl_xor(s2, m, 64);
+  if (lane != 0) return;
   norm2[j] = s2;
   const double nt = sqrt(s2);
   kappa[j] = nt <= eps[j] ? 1.0 : eps[j] / nt;
@@ -158,8 +165,9 @@ int balls_kappa(pr_balls_t* b, const void* t, int prec, hipStream_t st) {
                                                             b->npieces, b->piece_sum);
     PR_TRY_LAUNCH();
   }
-  section_kappa_kernel<<<(b->nsec + 255) / 256, 256, 0, st>>>(b->pfirst, b->piece_sum, b->eps, b->nsec, b->kappa,
-                                                              b->norm2);
+  constexpr int kWaves = kBallThreads / 64;
+  section_kappa_kernel<<<(b->nsec + kWaves - 1) / kWaves, kBallThreads, 0, st>>>(b->pfirst, b->piece_sum, b->eps,
+                                                                                b->nsec, b->kappa, b->norm2);
   PR_TRY_LAUNCH();
   return PR_OK;
 }

@@ -114,6 +114,22 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
     __syncthreads();
     for (int c0 = it.y; c0 < it.z; c0 += CH) {
       if (c0 + CH < it.z) load(c0 + CH, it.z, nu_, nv_, nw_);
+      // MODE 2: the chunk's y, s and section ids, issued before any of its stores
+      // (for MODE 1 the same early issue measured slower: it loads them in place)
+      constexpr int NA = MODE == 2 ? kDegridPer : 1;
+      C yo_[NA], sk_[NA];
+      int sj_[NA];
+      if (MODE == 2) {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          const int k = c0 + tid + j * kThreads;
+          if (k < it.z) {
+            yo_[j] = a.y_obs[k];
+            sk_[j] = a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0));
+            sj_[j] = a.sec[k];
+          }
+        }
+      }
 #pragma unroll
       for (int j = 0; j < kDegridPer; ++j) {
         const int k = c0 + tid + j * kThreads;
@@ -151,7 +167,8 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
         if (MODE == 0) {
           a.y_out[k] = yk;
         } else {
-          const C yo = a.y_obs[k], sk = a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0));
+          const C yo = MODE == 2 ? yo_[MODE == 2 ? j : 0] : a.y_obs[k];
+          const C sk = MODE == 2 ? sk_[MODE == 2 ? j : 0] : (a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0)));
           const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
           a.t_out[k] = t;
           const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
@@ -159,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
           sum_t += t2;
           sum_r += dr * dr + di * di;
           if (MODE == 2) {
-            const int sj = a.sec[k];
+            const int sj = sj_[MODE == 2 ? j : 0];
 #pragma unroll
             for (int jj = 0; jj < (MODE == 2 ? kSecAcc : 1); ++jj) sacc[jj] += sj == jj ? t2 : 0.0;
           }
@@ -969,16 +986,20 @@ __global__ void ball_scale_kernel(const double* partials, int nblocks, double ep
   }
 }
 
-// Local balls: ||t_j||^2 from the degridding partials (block order) and kappa_j.
-__global__ void section_kappa_partials_kernel(const double* partials, int nblocks, int nsec, const double* eps,
+// Local balls: block j sums section j's degridding partials in a fixed order
+// (strided per thread, then a tree) and forms ||t_j||^2 and kappa_j.
+__global__ void section_kappa_partials_kernel(const double* partials, int nblocks, const double* eps,
                                               double* kappa, double* norm2) {
-  const int j = threadIdx.x;
-  if (j >= nsec) return;
+  __shared__ double sh[kThreads];
+  const int j = blockIdx.x;
   double s2 = 0;
-  for (int i = 0; i < nblocks; ++i) s2 += partials[(kSlotSec0 + j) * kPartialsMax + i];
-  norm2[j] = s2;
-  const double nt = sqrt(s2);
-  kappa[j] = nt <= eps[j] ? 1.0 : eps[j] / nt;
+  for (int i = threadIdx.x; i < nblocks; i += kThreads) s2 += partials[(kSlotSec0 + j) * kPartialsMax + i];
+  s2 = block_sum_f64(s2, sh);
+  if (threadIdx.x == 0) {
+    norm2[j] = s2;
+    const double nt = sqrt(s2);
+    kappa[j] = nt <= eps[j] ? 1.0 : eps[j] / nt;
+  }
 }
 
 int degrid_blocks(const pr_phi_plan_t* p) {
@@ -1311,7 +1332,7 @@ int phi_section_kappa(pr_phi_plan_t* p, int nsec, const double* eps, double* kap
     set_error("internal: %d sections in the degridding partials", nsec);
     return PR_EINVAL;
   }
-  section_kappa_partials_kernel<<<1, 64, 0, s>>>(p->partials, degrid_blocks(p), nsec, eps, kappa, norm2);
+  section_kappa_partials_kernel<<<nsec, kThreads, 0, s>>>(p->partials, degrid_blocks(p), eps, kappa, norm2);
   PR_TRY_LAUNCH();
   return PR_OK;
 }
