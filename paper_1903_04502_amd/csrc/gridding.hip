@@ -200,10 +200,22 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       a.partials[kSlotR2 * kPartialsMax + blockIdx.x] = br;
     }
     if (MODE == 2) {
+      // all section sums in one pass: a fixed xor butterfly per wave, then the
+      // waves in order (sh is free again after the trees above)
+      constexpr int NS = MODE == 2 ? kSecAcc : 1;
+      const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-      for (int jj = 0; jj < (MODE == 2 ? kSecAcc : 1); ++jj) {
-        const double bj = block_sum_f64(sacc[jj], sh);
-        if (tid == 0) a.partials[(kSlotSec0 + jj) * kPartialsMax + blockIdx.x] = bj;
+      for (int jj = 0; jj < NS; ++jj) {
+        double v = sacc[jj];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+        if (lane == 0) sh[wave * NS + jj] = v;
+      }
+      __syncthreads();
+      if (tid < NS) {
+        double bj = 0.0;
+        for (int q = 0; q < kThreads / 64; ++q) bj += sh[q * NS + tid];
+        a.partials[(kSlotSec0 + tid) * kPartialsMax + blockIdx.x] = bj;
       }
     }
   }

@@ -5,7 +5,8 @@ oracle, on the 64^2 image / 8192-visibility workload.
 Sections follow the paper's split: visibilities ordered by baseline length
 and cut into equal-count sections; radii eps_j = sigma sqrt(M_j + 2 sqrt(M_j))
 (the global rule applied per section). Also: random interleaved sections with
-an empty one, a single section against the global-ball solver, bad ids.
+an empty one, a single section against the global-ball solver, the two
+section-norm paths (8 sections, 9 with an empty one) against each other, bad ids.
 """
 import numpy as np
 import pytest
@@ -100,6 +101,23 @@ def test_interleaved_sections_with_an_empty_one(P):
                                   P.admm_params(0.0, gamma, iters=10, op_norm=nrm))
     assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-10
     assert balls.norms()[7] == 0.0
+
+
+def test_partials_path_matches_the_piece_path(P):
+    # up to 8 sections the norms come from the degridding partials, above 8 from
+    # the section-sorted pieces: 8 length sections, then the same ids with a 9th
+    # (empty, eps 0 -> kappa 1) section, must give the same iterate
+    say("local balls 8 sections (partials) vs 9 with an empty one (pieces)")
+    w, uv, uv64, spec, y, sigma, _ = c0_data()
+    sec = length_sections(uv64, 8)
+    prm = P.admm_params(0.0, 0.05, iters=10, op_norm=1.0)
+    e8 = radii(sec, 8, sigma)
+    x8, _, b8, *_ = gpu_local(P, w, uv, uv64, y, sec, 8, e8, "f64", prm)
+    x9, _, b9, *_ = gpu_local(P, w, uv, uv64, y, sec, 9, np.append(e8, 0.0), "f64", prm)
+    assert rel_l2(x9.cpu().numpy(), x8.cpu().numpy()) <= 1e-12
+    n8, n9 = b8.norms(), b9.norms()
+    assert n9[8] == 0.0
+    np.testing.assert_allclose(n9[:8], n8, rtol=1e-12)
 
 
 def test_one_section_matches_the_global_ball_solver(P):
