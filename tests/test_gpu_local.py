@@ -70,7 +70,11 @@ def gpu_local(P, w, uv, uv64, y, sec, nsec, eps_j, prec, prm, J=None):
     return x, rep, balls, plan, psi, y_plan
 
 
-@pytest.mark.parametrize("prec,tol,iters,nsec", [("f64", 1e-10, 50, 4), ("f32", 1e-4, 50, 4), ("f64", 1e-10, 10, 16)])
+# up to 8 sections the norms come from the degridding partials, above 8 from
+# the section-sorted pieces: both paths in both precisions, and the largest
+# section count of the first path
+@pytest.mark.parametrize("prec,tol,iters,nsec", [("f64", 1e-10, 50, 4), ("f32", 1e-4, 50, 4), ("f64", 1e-10, 10, 8),
+                                                 ("f64", 1e-10, 10, 16), ("f32", 1e-4, 20, 16)])
 def test_local_balls_parity_admm64(P, prec, tol, iters, nsec):
     say(f"local balls admm64 {prec} iters={iters} nsec={nsec}")
     w, uv, uv64, spec, y, sigma, _ = c0_data()
