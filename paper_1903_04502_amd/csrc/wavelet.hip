@@ -8,6 +8,7 @@
 // hi[m] likewise with g. Synthesis is the transpose: for output i only taps
 // q = i (mod 2) contribute, from coefficient m = ((i - q) mod L) / 2.
 // Coefficients are stored in the Mallat layout of each basis' n x n array.
+// Levels small enough for LDS run in one launch per transform (tail kernels).
 #include <cmath>
 
 #include "ops.hpp"
@@ -207,6 +208,152 @@ __global__ void combine_kernel(const R* __restrict__ dirac, const R* __restrict_
   }
 }
 
+// Tail levels in one launch: from the first level of size L <= kTailMaxL on,
+// one block per basis runs all the remaining levels with the approximation,
+// the row pass and the low-low band in LDS (2 L^2 values). Each output is the
+// same sum, in the same order, as in the per-level kernels. One block per
+// basis is slower than the per-level launches from L = 128 up (FP32 256^2:
+// ADMM iteration 0.18 -> 0.22 ms with levels 2..4 fused).
+constexpr int kTailThreads = 1024;
+constexpr int kTailMaxL = 64;
+constexpr size_t kTailLds = 2 * kTailMaxL * kTailMaxL * sizeof(double);
+
+template <typename R>
+bool tail_fits(int L) {
+  return L <= kTailMaxL;
+}
+
+// first level (1-based) handled by the tail kernels, levels + 1 if none
+template <typename R>
+int tail_level(int n, int levels) {
+  for (int lev = 1; lev <= levels; ++lev)
+    if (tail_fits<R>(n >> (lev - 1))) return lev;
+  return levels + 1;
+}
+
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Analysis levels lev0 .. levels (nlev of them; level lev0 has size L0 = 2^lg0)
+// of basis blockIdx.x; src is that level's input as in dwt_rows_kernel.
+template <typename R, int MODE>
+__global__ __launch_bounds__(kTailThreads) void dwt_tail_kernel(const R* __restrict__ src, int64_t src_basis_stride,
+                                                                int ld_src, int lg0, int nlev, int n, int64_t n2,
+                                                                R* __restrict__ coef, const Filt<R>* __restrict__ filt,
+                                                                R scale, R gamma_h, const double* __restrict__ gamma_dev,
+                                                                R eta, const R* __restrict__ wts) {
+  extern __shared__ char smem_raw[];
+  const int L0 = 1 << lg0;
+  R* A = reinterpret_cast<R*>(smem_raw);    // level input, L x L
+  R* B = A + static_cast<size_t>(L0) * L0;  // row pass, L x L
+  const R gamma = (MODE == 1 && gamma_dev) ? static_cast<R>(*gamma_dev) : gamma_h;
+  const int bi = blockIdx.x, tid = threadIdx.x;
+  const Filt<R>& f = filt[bi];
+  const R* in = src + bi * src_basis_stride;
+  R* cb = coef + bi * n2;
+  const R* wb = wts ? wts + bi * n2 : nullptr;
+  for (int i = tid; i < L0 * L0; i += kTailThreads) A[i] = in[static_cast<int64_t>(i >> lg0) * ld_src + (i & (L0 - 1))];
+  int lg = lg0;
+  for (int lv = 0; lv < nlev; ++lv, --lg) {
+    const int L = 1 << lg, half = L >> 1;
+    __syncthreads();   // A holds this level's input
+    for (int i = tid; i < L * half; i += kTailThreads) {
+      const int r = i >> (lg - 1), m = i & (half - 1);
+      const R* row = A + r * L;
+      R lo = 0, hi = 0;
+#pragma unroll
+      for (int q = 0; q < kTapsMax; ++q) {
+        if (q < f.taps) {
+          const R v = row[(2 * m + q) & (L - 1)];
+          lo += f.h[q] * v;
+          hi += f.g[q] * v;
+        }
+      }
+      B[r * L + m] = lo;
+      B[r * L + half + m] = hi;
+    }
+    __syncthreads();   // rows done; A is free for the next level's input
+    const bool last = lv == nlev - 1;
+    for (int i = tid; i < half * L; i += kTailThreads) {
+      const int m = i >> lg, c = i & (L - 1);
+      R lo = 0, hi = 0;
+#pragma unroll
+      for (int q = 0; q < kTapsMax; ++q) {
+        if (q < f.taps) {
+          const R v = B[((2 * m + q) & (L - 1)) * L + c];
+          lo += f.h[q] * v;
+          hi += f.g[q] * v;
+        }
+      }
+      if (c < half && !last) {
+        A[m * half + c] = lo;
+      } else {
+        const int64_t o = static_cast<int64_t>(m) * n + c;
+        if (MODE == 0) cb[o] = lo * scale;
+        else cb[o] = dual_clip(cb[o], lo * scale, wb ? gamma * wb[o] : gamma, eta);
+      }
+      const int64_t o = static_cast<int64_t>(half + m) * n + c;
+      if (MODE == 0) cb[o] = hi * scale;
+      else cb[o] = dual_clip(cb[o], hi * scale, wb ? gamma * wb[o] : gamma, eta);
+    }
+  }
+}
+
+// Synthesis levels levels .. lev0 (nlev of them, from the deepest, of size
+// 2^lgd) of basis blockIdx.x; level lev0's output goes to dst as in
+// idwt_rows_kernel, the others stay in LDS as the next level's low-low band.
+template <typename R>
+__global__ __launch_bounds__(kTailThreads) void idwt_tail_kernel(const R* __restrict__ coef, int64_t n2, int n, int lgd,
+                                                                 int nlev, R* __restrict__ dst, int64_t dst_basis_stride,
+                                                                 const Filt<R>* __restrict__ filt) {
+  extern __shared__ char smem_raw[];
+  const int L0 = 1 << (lgd + nlev - 1);
+  R* rw = reinterpret_cast<R*>(smem_raw);      // column pass, L x L
+  R* ll = rw + static_cast<size_t>(L0) * L0;   // low-low band of the next level, L x L (at most (L0/2)^2)
+  const int bi = blockIdx.x, tid = threadIdx.x;
+  const Filt<R>& f = filt[bi];
+  const R* cb = coef + bi * n2;
+  R* out = dst + bi * dst_basis_stride;
+  int lg = lgd;
+  for (int lv = 0; lv < nlev; ++lv, ++lg) {
+    const int L = 1 << lg, half = L >> 1;
+    const bool deepest = lv == 0, last = lv == nlev - 1;
+    __syncthreads();   // ll holds this level's low-low band; rw is free
+    for (int i = tid; i < L * L; i += kTailThreads) {
+      const int r = i >> lg, c = i & (L - 1);
+      R acc = 0;
+#pragma unroll
+      for (int q = 0; q < kTapsMax; ++q) {
+        if (q < f.taps && ((q ^ r) & 1) == 0) {
+          const int m = ((r - q) & (L - 1)) >> 1;
+          const R lo = (c < half && !deepest) ? ll[m * half + c] : cb[static_cast<int64_t>(m) * n + c];
+          const R hi = cb[static_cast<int64_t>(half + m) * n + c];
+          acc += f.h[q] * lo + f.g[q] * hi;
+        }
+      }
+      rw[i] = acc;
+    }
+    __syncthreads();   // columns done; ll is free
+    for (int i = tid; i < L * L; i += kTailThreads) {
+      const int r = i >> lg, c = i & (L - 1);
+      const R* row = rw + r * L;
+      R acc = 0;
+#pragma unroll
+      for (int q = 0; q < kTapsMax; ++q) {
+        if (q < f.taps && ((q ^ c) & 1) == 0) {
+          const int m = ((c - q) & (L - 1)) >> 1;
+          acc += f.h[q] * row[m] + f.g[q] * row[half + m];
+        }
+      }
+      if (last) out[i] = acc;
+      else ll[i] = acc;
+    }
+  }
+}
+
 __global__ void combine_finish_kernel(const double* partials, int nblocks, double* sums) {
   __shared__ double sh[kThreads];
   double dd = 0, xx = 0;
@@ -243,11 +390,25 @@ int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma,
   R* rows = static_cast<R*>(p->rows);
   R* lla = static_cast<R*>(p->ll_a);
   R* llb = static_cast<R*>(p->ll_b);
+  const int lev0 = tail_level<R>(n, p->levels);
   int L = n;
   for (int lev = 1; lev <= p->levels; ++lev, L >>= 1) {
     const R* src = lev == 1 ? x : ((lev - 1) & 1 ? lla : llb);
     const int64_t sstride = lev == 1 ? 0 : n2 / 4;
     const int ld = lev == 1 ? n : L;
+    if (lev == lev0) {
+      // this level and all deeper ones in one launch
+      const size_t lds = 2 * static_cast<size_t>(L) * L * sizeof(R);
+      const int nlev = p->levels - lev + 1;
+      if (mode == 0)
+        dwt_tail_kernel<R, 0><<<p->ndb, kTailThreads, lds, s>>>(src, sstride, ld, log2i(L), nlev, n, n2, wave, f, scale,
+                                                                R(gamma), gamma_dev, R(eta), nullptr);
+      else
+        dwt_tail_kernel<R, 1><<<p->ndb, kTailThreads, lds, s>>>(src, sstride, ld, log2i(L), nlev, n, n2, wave, f, scale,
+                                                                R(gamma), gamma_dev, R(eta), wwave);
+      PR_TRY_LAUNCH();
+      break;
+    }
     const int64_t work = static_cast<int64_t>(L) * (L / 2);
     const dim3 grid(grid_for(work, kThreads, 2048), p->ndb);
     dwt_rows_kernel<R><<<grid, kThreads, 0, s>>>(src, sstride, ld, L, rows, n2, f);
@@ -276,7 +437,18 @@ int synthesis_bases(pr_psi_plan_t* p, const R* coef, hipStream_t s) {
   R* lla = static_cast<R*>(p->ll_a);
   R* llb = static_cast<R*>(p->ll_b);
   R* recon = static_cast<R*>(p->recon);
-  for (int lev = p->levels; lev >= 1; --lev) {
+  const int lev0 = tail_level<R>(n, p->levels);
+  if (lev0 <= p->levels) {
+    // the deepest levels down to lev0 in one launch
+    const int L0 = n >> (lev0 - 1);
+    const size_t lds = (static_cast<size_t>(L0) * L0 + static_cast<size_t>(L0 / 2) * (L0 / 2)) * sizeof(R);
+    R* dst = lev0 == 1 ? recon : (lev0 & 1 ? lla : llb);
+    const int64_t dstride = lev0 == 1 ? n2 : n2 / 4;
+    idwt_tail_kernel<R><<<p->ndb, kTailThreads, lds, s>>>(wave, n2, n, log2i(n >> (p->levels - 1)),
+                                                          p->levels - lev0 + 1, dst, dstride, f);
+    PR_TRY_LAUNCH();
+  }
+  for (int lev = lev0 - 1; lev >= 1; --lev) {
     const int L = n >> (lev - 1);
     const R* llsrc = lev == p->levels ? wave : ((lev + 1) & 1 ? lla : llb);
     const int ldll = lev == p->levels ? n : L / 2;
@@ -377,6 +549,16 @@ static int upload_filters(pr_psi_plan_t* p, hipStream_t s) {
   return PR_OK;
 }
 
+// the tail kernels take up to kTailLds of dynamic LDS (on the current device)
+template <typename R>
+static int allow_tail_lds() {
+  const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+  PR_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(dwt_tail_kernel<R, 0>), attr, kTailLds));
+  PR_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(dwt_tail_kernel<R, 1>), attr, kTailLds));
+  PR_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(idwt_tail_kernel<R>), attr, kTailLds));
+  return PR_OK;
+}
+
 int psi_create(pr_psi_plan_t* p, hipStream_t s) {
   for (int k = 1; k <= 8; ++k) {
     if (!daubechies_filter(k, p->host_filters[k])) {
@@ -384,6 +566,7 @@ int psi_create(pr_psi_plan_t* p, hipStream_t s) {
       return PR_EINVAL;
     }
   }
+  PR_TRY(p->prec == PR_F32 ? allow_tail_lds<float>() : allow_tail_lds<double>());
   return p->prec == PR_F32 ? upload_filters<float>(p, s) : upload_filters<double>(p, s);
 }
 
