@@ -81,7 +81,10 @@ typedef struct {
   int32_t oversample; /* K = oversample * n; must be 2                      */
   int32_t J;          /* kernel support: 2, 4, 6 or 8                       */
   int32_t D;          /* table samples per grid cell, 1 <= D <= 1000000     */
-  int64_t M;          /* visibilities, 0 <= M < 2^31                        */
+  int64_t M;          /* visibilities, 0 <= M <= 2^31 - 2^20 (positions and
+                         the permutation are int32; every product with a
+                         position is formed in 64 bits). Largest count run
+                         on the GPU: see the tests of the 2048^2 share.     */
   int32_t prec;       /* PR_F32 or PR_F64                                    */
   int32_t tile;       /* tile side in grid cells: 0 = default, else 8/16/32  */
   int32_t interp;     /* kernel lookup (Section "Kernel Pre-Sampling"):
@@ -144,10 +147,14 @@ int pr_phi_grid_merge(pr_phi_plan plan, void* stream);
 
 /* Operator norm ||Phi|| by the power method on Re Phi^dagger Phi (Section
  * "Distributed Images"): x0 = constant image of unit norm, x <- A x / ||A x||
- * (norms in FP64), iters steps, result sqrt(||A x||) written to *norm (host).
- * vis_ws: device scratch of M complex values. Synchronises the stream. */
-int pr_phi_norm(pr_phi_plan plan, int32_t iters, void* vis_ws, double* norm,
-                void* stream);
+ * (norms in FP64), at most iters steps, result sqrt(||A x||) written to *norm
+ * (host). rtol > 0: stop after step k once |l_k - l_{k-1}| <= rtol l_k, with
+ * l_k = ||A x|| of step k (reads l_k back after every step); rtol = 0: exactly
+ * iters steps, fully on the device until the final read. vis_ws: device
+ * scratch of M complex values. Synchronises the stream. PR_EINVAL for
+ * iters < 1 or rtol < 0. */
+int pr_phi_norm(pr_phi_plan plan, int32_t iters, double rtol, void* vis_ws,
+                double* norm, void* stream);
 
 /* Tile-side autotuner: for each admissible tile side (8, 16, 32; desc->tile
  * is ignored) build the plan into the given workspaces and time `reps`
@@ -255,13 +262,47 @@ int pr_admm_workspace_size(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes);
 
 /* Run Algorithm 1. y: complex[M], plan order. x: real[n*n], in: x0, out:
  * the last iterate (in units of the normalised operator: the physical image
- * is x / ||Phi||), updated in place. 1 / ||Phi|| and gamma are kept in the
- * workspace on the device. rep: if not NULL, filled on return and the call
- * synchronises; if NULL and rel_tol == 0 the call is fully asynchronous.
- * The two plans must have the same n and precision. */
+ * is x / ||Phi||), updated in place. 1 / ||Phi||, gamma and the iteration
+ * count are kept in the workspace on the device (see pr_admm_resume). rep: if
+ * not NULL, filled on return and the call synchronises; if NULL and
+ * rel_tol == 0 the call is fully asynchronous. The two plans must have the
+ * same n and precision. */
 int pr_admm_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
                   const pr_admm_params* params, void* x, void* workspace,
                   pr_admm_report* rep, void* stream);
+
+/* Checkpoint and resume of Algorithm 1 (the state of its iteration: the
+ * iterate x, the Lagrange multiplier s, the DualFB dual variable d, the
+ * scalars 1 / ||Phi|| and gamma, and the outer iteration count).
+ *
+ * pr_admm_state_bytes: size of a checkpoint for these plans (a 256-byte
+ * header, then x, s, d and the FP64 scalar block, each 256-byte aligned).
+ *
+ * pr_admm_state_export: copy x and the state held in `workspace` (as left by
+ * pr_admm_solve or pr_admm_resume on the same plans) into `state`, host or
+ * device memory of pr_admm_state_bytes bytes owned by the caller.
+ * Synchronises the stream.
+ *
+ * pr_admm_state_import: restore a checkpoint into `workspace` (of
+ * pr_admm_workspace_size bytes for these plans) and x. PR_EINVAL if `state`
+ * holds no checkpoint or one made for plans of another n, M, precision or
+ * dictionary. Synchronises the stream.
+ *
+ * pr_admm_resume: params->iters more outer iterations of Algorithm 1 from the
+ * state in `workspace` and x, without clearing s and d; 1 / ||Phi|| comes from
+ * the workspace (params->op_norm, norm_iters and gamma_factor are ignored),
+ * and gamma too when params->gamma <= 0. The kernels and their order are
+ * those of pr_admm_solve, so solve(k) then resume(m) -- also through an
+ * export and an import into another workspace -- gives bitwise the x of
+ * solve(k + m). rep->iters_done counts every iteration since the solve. */
+int pr_admm_state_bytes(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes);
+int pr_admm_state_export(pr_phi_plan phi, pr_psi_plan psi, const void* workspace,
+                         const void* x, void* state, void* stream);
+int pr_admm_state_import(pr_phi_plan phi, pr_psi_plan psi, const void* state,
+                         void* workspace, void* x, void* stream);
+int pr_admm_resume(pr_phi_plan phi, pr_psi_plan psi, const void* y,
+                   const pr_admm_params* params, void* x, void* workspace,
+                   pr_admm_report* rep, void* stream);
 
 /* ------------------------------------------------------------------------
  * Reweighted analysis l1 (SARA reweighting; Section "Sparse Regularization"
@@ -306,7 +347,7 @@ int pr_admm_reweighted_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y,
  * ---------------------------------------------------------------------- */
 typedef struct pr_balls_t* pr_balls;
 
-/* M in [0, 2^31), nsec in [1, 2^24]. */
+/* M in [0, 2^31 - 2^20], nsec in [1, 2^24]. */
 int pr_balls_sizes(int64_t M, int32_t nsec, size_t* persistent_bytes, size_t* scratch_bytes);
 /* Sorts the plan positions by section (stable) and synchronises `stream`.
  * PR_EINVAL if a section id is out of range, PR_EWORKSPACE for a bad
@@ -322,9 +363,12 @@ int pr_balls_norms(pr_balls b, double* norms, void* stream);
 /* Algorithm 1 with the local balls: as pr_admm_solve (same workspace size,
  * pr_admm_workspace_size) with params->eps ignored and eps: HOST double[nsec],
  * the radii (copied to the device; the call synchronises once at the start).
- * Per iteration the degridding forms t, a fixed-order FP64 reduction gives
- * ||t_j|| per section, one pass applies the projections and the multiplier
- * update, and the plain gridding grids the result. */
+ * Per iteration the degridding forms t = v + s - y; with at most 8 sections
+ * its epilogue also keeps one FP64 ||t_j||^2 partial per section and block
+ * (summed in block order by one small kernel), with more sections a gather
+ * over the section-sorted positions forms them. The gridding's prologue then
+ * projects each visibility with its own section's kappa_j and updates the
+ * multiplier before gridding, as for the global ball. */
 int pr_admm_local_solve(pr_phi_plan phi, pr_psi_plan psi, pr_balls balls, const void* y,
                         const pr_admm_params* params, const double* eps, void* x,
                         void* workspace, pr_admm_report* rep, void* stream);
@@ -498,9 +542,10 @@ int pr_server_create(void* arena, size_t arena_bytes, int32_t max_active,
 int pr_server_destroy(pr_server s);
 /* Queue a request; fails with PR_EWORKSPACE if it can never fit the arena. */
 int pr_server_submit(pr_server s, const pr_job_desc* desc, int64_t* job_id);
-/* Retire finished jobs, admit queued ones, queue one outer iteration of each
- * running job (at most two in flight per job). Blocks only while an admitted
- * job's plan is built. Counts are optional. */
+/* Retire finished jobs, admit queued ones, and queue outer iterations of
+ * every running job until it has three in flight (each job's iterations are
+ * ordered on its own stream). Blocks only while an admitted job's plan is
+ * built. Counts are optional. */
 int pr_server_tick(pr_server s, int32_t* queued, int32_t* running,
                    int32_t* finished);
 /* state: 0 queued, 1 running, 2 finished, 3 failed. */

@@ -30,6 +30,8 @@ __global__ void zero_kernel(R* a, int64_t len) {
 
 __global__ void set_scalar_kernel(double* a, double v) { *a = v; }
 
+__global__ void add_scalar_kernel(double* a, double v) { *a += v; }
+
 __global__ void zero_f64_kernel(double* a, int len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) a[i] = 0.0;
@@ -191,22 +193,152 @@ int admm_device_setup(AdmmJob* j, hipStream_t s) {
   return PR_OK;
 }
 
-int admm_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x, void* ws,
-               pr_admm_report* rep, hipStream_t s) {
-  AdmmJob j;
-  PR_TRY(admm_job_init(&j, phi, psi, y, x, ws, prm, s));
-  PR_TRY(admm_device_setup(&j, s));
-  double host_sums[16] = {0};
+namespace {
+
+// The outer loop shared by a fresh solve and a resumed one: prm.iters steps
+// (or fewer once the relative change drops below rel_tol), then the device
+// iteration count advances by the steps taken.
+int admm_run(AdmmJob& j, const pr_admm_params& prm, pr_admm_report* rep, hipStream_t s) {
+  double host_sums[kSumSlots] = {0};
+  const int start = j.iters_done;
   for (int it = 0; it < prm.iters; ++it) {
     PR_TRY(admm_step(&j, s));
     if (prm.rel_tol > 0) {
-      PR_TRY_HIP(hipMemcpyAsync(host_sums, j.w.sums, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PR_TRY_HIP(hipMemcpyAsync(host_sums, j.w.sums, kSumSlots * sizeof(double), hipMemcpyDeviceToHost, s));
       PR_TRY_HIP(hipStreamSynchronize(s));
       const double rv = host_sums[kSumVar + 1] > 0 ? std::sqrt(host_sums[kSumVar] / host_sums[kSumVar + 1]) : INFINITY;
       if (rv < prm.rel_tol) break;
     }
   }
-  if (rep) PR_TRY(admm_report(&j, rep, s));
+  add_scalar_kernel<<<1, 1, 0, s>>>(j.w.sums + kSumIters, static_cast<double>(j.iters_done - start));
+  PR_TRY_LAUNCH();
+  if (rep) {
+    PR_TRY(admm_report(&j, rep, s));
+    double cnt = 0;
+    PR_TRY_HIP(hipMemcpyAsync(&cnt, j.w.sums + kSumIters, sizeof(double), hipMemcpyDeviceToHost, s));
+    PR_TRY_HIP(hipStreamSynchronize(s));
+    rep->iters_done = static_cast<int32_t>(cnt);
+  }
+  return PR_OK;
+}
+
+// Checkpoint header (the first 256 bytes of a state buffer).
+struct StateHeader {
+  uint32_t magic;      // 'P' 'R' 'S' 'T'
+  uint32_t version;
+  int32_t prec, n, nb, levels;
+  int64_t M;
+  uint32_t basis_mask;
+  int32_t slots;
+};
+constexpr uint32_t kStateMagic = 0x54535250u;
+constexpr size_t kStateHead = 256;
+
+struct StateParts {
+  size_t x, s, d, sums, total;
+};
+
+StateParts state_parts(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi) {
+  const size_t rs = phi->prec == PR_F32 ? 4 : 8;
+  const size_t n2 = static_cast<size_t>(phi->n) * phi->n;
+  auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+  StateParts p{};
+  p.x = kStateHead;
+  p.s = p.x + up(n2 * rs);
+  p.d = p.s + up(static_cast<size_t>(phi->M) * 2 * rs);
+  p.sums = p.d + up(static_cast<size_t>(psi->nb) * n2 * rs);
+  p.total = p.sums + up(kSumSlots * sizeof(double));
+  return p;
+}
+
+StateHeader state_header(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi) {
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.version = 1;
+  h.prec = phi->prec;
+  h.n = phi->n;
+  h.nb = psi->nb;
+  h.levels = psi->levels;
+  h.M = phi->M;
+  h.basis_mask = psi->mask;
+  h.slots = kSumSlots;
+  return h;
+}
+
+}  // namespace
+
+int admm_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x, void* ws,
+               pr_admm_report* rep, hipStream_t s) {
+  AdmmJob j;
+  PR_TRY(admm_job_init(&j, phi, psi, y, x, ws, prm, s));
+  PR_TRY(admm_device_setup(&j, s));
+  return admm_run(j, prm, rep, s);
+}
+
+int admm_resume(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x, void* ws,
+                pr_admm_report* rep, hipStream_t s) {
+  AdmmJob j;
+  j.phi = phi;
+  j.psi = psi;
+  j.y = y;
+  j.x = x;
+  j.prm = prm;
+  j.iters_done = 0;
+  admm_layout(phi, psi, ws, &j.w);
+  // 1 / ||Phi|| always, and gamma unless the caller fixes it, come from the
+  // device slots the first solve filled
+  j.device_scale = true;
+  j.device_gamma = !(prm.gamma > 0);
+  return admm_run(j, prm, rep, s);
+}
+
+size_t admm_state_bytes(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi) { return state_parts(phi, psi).total; }
+
+int admm_state_export(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* ws, const void* x, void* state,
+                      hipStream_t s) {
+  AdmmWs w{};
+  admm_layout(phi, psi, const_cast<void*>(ws), &w);
+  const StateParts p = state_parts(phi, psi);
+  const size_t rs = phi->prec == PR_F32 ? 4 : 8;
+  const size_t n2 = static_cast<size_t>(phi->n) * phi->n;
+  char* dst = static_cast<char*>(state);
+  const StateHeader h = state_header(phi, psi);
+  PR_TRY_HIP(hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipMemcpyAsync(dst + p.x, x, n2 * rs, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipMemcpyAsync(dst + p.s, w.s, static_cast<size_t>(phi->M) * 2 * rs, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipMemcpyAsync(dst + p.d, w.d, static_cast<size_t>(psi->nb) * n2 * rs, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipMemcpyAsync(dst + p.sums, w.sums, kSumSlots * sizeof(double), hipMemcpyDefault, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));   // the header lives on this call's stack
+  return PR_OK;
+}
+
+int admm_state_import(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* state, void* ws, void* x,
+                      hipStream_t s) {
+  const char* src = static_cast<const char*>(state);
+  StateHeader h{};
+  PR_TRY_HIP(hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));
+  const StateHeader want = state_header(phi, psi);
+  if (h.magic != kStateMagic || h.version != want.version) {
+    set_error("state buffer does not hold an ADMM checkpoint");
+    return PR_EINVAL;
+  }
+  if (h.prec != want.prec || h.n != want.n || h.nb != want.nb || h.levels != want.levels || h.M != want.M ||
+      h.basis_mask != want.basis_mask || h.slots != want.slots) {
+    set_error("checkpoint was made for other plans (n %d, M %lld, bases %d, levels %d, prec %d)", h.n,
+              static_cast<long long>(h.M), h.nb, h.levels, h.prec);
+    return PR_EINVAL;
+  }
+  AdmmWs w{};
+  admm_layout(phi, psi, ws, &w);
+  const StateParts p = state_parts(phi, psi);
+  const size_t rs = phi->prec == PR_F32 ? 4 : 8;
+  const size_t n2 = static_cast<size_t>(phi->n) * phi->n;
+  PR_TRY_HIP(hipMemcpyAsync(x, src + p.x, n2 * rs, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipMemcpyAsync(w.s, src + p.s, static_cast<size_t>(phi->M) * 2 * rs, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipMemcpyAsync(w.d, src + p.d, static_cast<size_t>(psi->nb) * n2 * rs, hipMemcpyDefault, s));
+  PR_TRY_HIP(hipMemcpyAsync(w.sums, src + p.sums, kSumSlots * sizeof(double), hipMemcpyDefault, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));
   return PR_OK;
 }
 

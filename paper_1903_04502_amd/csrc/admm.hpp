@@ -13,6 +13,7 @@ constexpr int kSumL1 = 12;       // ||Psi^dagger x||_1
 constexpr int kSumScale = 16;    // 1 / ||Phi|| when kept on the device
 constexpr int kSumGamma = 17;    // gamma when kept on the device
 constexpr int kSumGammaStep = 18; // gamma * step, the FISTA prox threshold, on the device
+constexpr int kSumIters = 19;    // outer iterations since the first pr_admm_solve (pr_admm_resume continues it)
 constexpr int kSumSlots = 32;
 
 struct AdmmWs {
@@ -57,6 +58,15 @@ int admm_step(AdmmJob* j, hipStream_t s);
 int admm_report(AdmmJob* j, pr_admm_report* rep, hipStream_t s);
 int admm_solve(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x,
                void* ws, pr_admm_report* rep, hipStream_t s);
+// Continue from the state in ws and x (s, d, 1 / ||Phi||, gamma, the count).
+int admm_resume(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* y, const pr_admm_params& prm, void* x,
+                void* ws, pr_admm_report* rep, hipStream_t s);
+// Checkpoint layout: a header, then x, s, d and the FP64 scalar block.
+size_t admm_state_bytes(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi);
+int admm_state_export(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* ws, const void* x, void* state,
+                      hipStream_t s);
+int admm_state_import(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* state, void* ws, void* x,
+                      hipStream_t s);
 
 // Device-resident set-up after admm_job_init: 1 / ||Phi|| into sums[kSumScale]
 // (from prm.op_norm, or the power method with prm.norm_iters steps), and,

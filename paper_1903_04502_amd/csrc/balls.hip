@@ -219,7 +219,7 @@ int pr_balls_sizes(int64_t M, int32_t nsec, size_t* persistent_bytes, size_t* sc
   clear_error();
   PR_NONNULL(persistent_bytes);
   PR_NONNULL(scratch_bytes);
-  if (M < 0 || M > INT32_MAX) { set_error("M must be in [0, 2^31)"); return PR_EINVAL; }
+  if (M < 0 || M > kMaxVisibilities) { set_error("M must be in [0, 2^31 - 2^20]"); return PR_EINVAL; }
   if (nsec < 1 || nsec > (1 << 24)) { set_error("nsec must be in [1, 2^24]"); return PR_EINVAL; }
   *persistent_bytes = balls_layout(M, nsec, nullptr, nullptr);
   *scratch_bytes = balls_scratch_layout(M, nsec, nullptr, nullptr);

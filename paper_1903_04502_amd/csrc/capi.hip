@@ -167,14 +167,15 @@ int pr_phi_adjoint(pr_phi_plan plan, const void* y, void* x, void* stream) {
   return phi_fzs_adjoint(plan, x, as_stream(stream));
 }
 
-int pr_phi_norm(pr_phi_plan plan, int32_t iters, void* vis_ws, double* norm, void* stream) {
+int pr_phi_norm(pr_phi_plan plan, int32_t iters, double rtol, void* vis_ws, double* norm, void* stream) {
   clear_error();
   PR_NONNULL(plan);
   PR_NONNULL(norm);
   if (plan->M > 0) PR_NONNULL(vis_ws);
   if (iters < 1) { set_error("iters = %d must be >= 1", iters); return PR_EINVAL; }
+  if (!(rtol >= 0)) { set_error("rtol must be >= 0"); return PR_EINVAL; }
   PR_TRY(check_sticky());
-  return phi_norm(plan, iters, vis_ws, norm, as_stream(stream));
+  return phi_norm(plan, iters, rtol, vis_ws, norm, as_stream(stream));
 }
 
 // --------------------------------------------------------------------------
@@ -309,6 +310,57 @@ int pr_admm_solve(pr_phi_plan phi, pr_psi_plan psi, const void* y, const pr_admm
   PR_TRY(admm_check_params(params));
   PR_TRY(check_sticky());
   return admm_solve(phi, psi, y, *params, x, workspace, rep, as_stream(stream));
+}
+
+int pr_admm_resume(pr_phi_plan phi, pr_psi_plan psi, const void* y, const pr_admm_params* params, void* x,
+                   void* workspace, pr_admm_report* rep, void* stream) {
+  clear_error();
+  PR_NONNULL(phi);
+  PR_NONNULL(psi);
+  PR_NONNULL(y);
+  PR_NONNULL(params);
+  PR_NONNULL(x);
+  if (!workspace || !aligned256(workspace)) { set_error("workspace must be non-NULL and 256-byte aligned"); return PR_EWORKSPACE; }
+  PR_TRY(admm_check_plans(phi, psi));
+  PR_TRY(admm_check_params(params));
+  PR_TRY(check_sticky());
+  return admm_resume(phi, psi, y, *params, x, workspace, rep, as_stream(stream));
+}
+
+int pr_admm_state_bytes(pr_phi_plan phi, pr_psi_plan psi, size_t* bytes) {
+  clear_error();
+  PR_NONNULL(phi);
+  PR_NONNULL(psi);
+  PR_NONNULL(bytes);
+  PR_TRY(admm_check_plans(phi, psi));
+  *bytes = admm_state_bytes(phi, psi);
+  return PR_OK;
+}
+
+int pr_admm_state_export(pr_phi_plan phi, pr_psi_plan psi, const void* workspace, const void* x, void* state,
+                         void* stream) {
+  clear_error();
+  PR_NONNULL(phi);
+  PR_NONNULL(psi);
+  PR_NONNULL(x);
+  PR_NONNULL(state);
+  if (!workspace || !aligned256(workspace)) { set_error("workspace must be non-NULL and 256-byte aligned"); return PR_EWORKSPACE; }
+  PR_TRY(admm_check_plans(phi, psi));
+  PR_TRY(check_sticky());
+  return admm_state_export(phi, psi, workspace, x, state, as_stream(stream));
+}
+
+int pr_admm_state_import(pr_phi_plan phi, pr_psi_plan psi, const void* state, void* workspace, void* x,
+                         void* stream) {
+  clear_error();
+  PR_NONNULL(phi);
+  PR_NONNULL(psi);
+  PR_NONNULL(state);
+  PR_NONNULL(x);
+  if (!workspace || !aligned256(workspace)) { set_error("workspace must be non-NULL and 256-byte aligned"); return PR_EWORKSPACE; }
+  PR_TRY(admm_check_plans(phi, psi));
+  PR_TRY(check_sticky());
+  return admm_state_import(phi, psi, state, workspace, x, as_stream(stream));
 }
 
 }  // extern "C"

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   double sacc[MODE == 2 ? kSecAcc : 1] = {};   // MODE 2: ||t||^2 per section
   // inputs of this thread's visibilities for the current and the next chunk
   R cu_[kDegridPer], cv_[kDegridPer], cw_[kDegridPer], nu_[kDegridPer], nv_[kDegridPer], nw_[kDegridPer];
-  auto load = [&](int c0, int cend, R* u, R* v, R* w) {
+  auto load = [&](int64_t c0, int64_t cend, R* u, R* v, R* w) {
 #pragma unroll
     for (int j = 0; j < kDegridPer; ++j) {
       const int64_t k = c0 + tid + j * kThreads;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       patch[i] = a.grid[static_cast<int64_t>(gv) * K + gu];
     }
     __syncthreads();
-    for (int c0 = it.y; c0 < it.z; c0 += CH) {
+    for (int64_t c0 = it.y; c0 < it.z; c0 += CH) {
       if (c0 + CH < it.z) load(c0 + CH, it.z, nu_, nv_, nw_);
       // MODE 2: the chunk's y, s and section ids, issued before any of its stores
       // (for MODE 1 the same early issue measured slower: it loads them in place)
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       if (MODE == 2) {
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-          const int k = c0 + tid + j * kThreads;
+          const int64_t k = c0 + tid + j * kThreads;
           if (k < it.z) {
             yo_[j] = a.y_obs[k];
             sk_[j] = a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0));
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       }
 #pragma unroll
       for (int j = 0; j < kDegridPer; ++j) {
-        const int k = c0 + tid + j * kThreads;
+        const int64_t k = c0 + tid + j * kThreads;
         if (k >= it.z) continue;
         const AxisTaps xu = axis_taps(static_cast<double>(cu_[j]), a.kappa, J, a.D);
         const AxisTaps xv = axis_taps(static_cast<double>(cv_[j]), a.kappa, J, a.D);
@@ -665,10 +665,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 #pragma unroll
     for (int r = 0; r < WC; ++r) {
       const int q = q0 + lane_q;
-      const int pos = it.y + (lane_t + r * kSegStride) * L + q;
+      const int64_t pos = static_cast<int64_t>(it.y) + (lane_t + r * kSegStride) * L + q;
       const bool ok = q < L && pos < it.z;
       pf.ok |= static_cast<unsigned>(ok) << r;
-      const int pc = ok ? pos : it.y;
+      const int64_t pc = ok ? pos : static_cast<int64_t>(it.y);
       pf.uv[r] = cmk<C>(a.uv[3 * pc], a.uv[3 * pc + 1]);
       pf.w[r] = a.uv[3 * pc + 2];
       if (MODE == 0) {
@@ -705,7 +705,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       const C uvr = pf.uv[r];
       const C wv = cmk<C>(val.x * ws, val.y * ws);
       if (ok) {
-        if (MODE == 1) a.s_io[it.y + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
+        if (MODE == 1) a.s_io[static_cast<int64_t>(it.y) + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
         const int slot = lane_q * kStagePitch + lane_t + r * kSegStride;
         st[slot] = Staged{uvr, wv};
       }

@@ -325,10 +325,11 @@ int phi_norm_device(pr_phi_plan_t* p, int iters, void* vis, double* inv_norm, hi
   return PR_OK;
 }
 
-int phi_norm(pr_phi_plan_t* p, int iters, void* vis, double* norm, hipStream_t s) {
+int phi_norm(pr_phi_plan_t* p, int iters, double rtol, void* vis, double* norm, hipStream_t s) {
   const int64_t N = static_cast<int64_t>(p->n) * p->n;
   double* s2 = p->scalars + 8;
   PR_TRY(fill_real(p->img_a, N, p->prec, 1.0 / p->n, s));
+  double h = 0, lam_prev = -1.0;
   for (int it = 0; it < iters; ++it) {
     PR_TRY(phi_fzs(p, p->img_a, s));
     PR_TRY(phi_gw(p, vis, 1.0, s));
@@ -336,8 +337,15 @@ int phi_norm(pr_phi_plan_t* p, int iters, void* vis, double* norm, hipStream_t s
     PR_TRY(phi_fzs_adjoint(p, p->img_b, s));
     PR_TRY(reduce_sumsq(p->img_b, nullptr, N, p->prec, p->partials, s2, s, nullptr));
     PR_TRY(normalise(p->img_a, p->img_b, N, p->prec, s2, s));
+    if (rtol > 0) {
+      // l_k = ||A x_k||: stop once it has settled to rtol
+      PR_TRY_HIP(hipMemcpyAsync(&h, s2, sizeof(double), hipMemcpyDeviceToHost, s));
+      PR_TRY_HIP(hipStreamSynchronize(s));
+      const double lam = std::sqrt(h);
+      if (lam_prev >= 0 && std::fabs(lam - lam_prev) <= rtol * lam) break;
+      lam_prev = lam;
+    }
   }
-  double h = 0;
   PR_TRY_HIP(hipMemcpyAsync(&h, s2, sizeof(double), hipMemcpyDeviceToHost, s));
   PR_TRY_HIP(hipStreamSynchronize(s));
   *norm = iters > 0 ? std::sqrt(std::sqrt(h)) : 0.0;

@@ -47,6 +47,10 @@ struct pr_phi_plan_t {
 
 namespace pr {
 
+// Largest visibility count a plan accepts: positions, item bounds and the
+// permutation are 32-bit, and every kernel forms (position + a per-item
+// offset below 2^20) without overflow; products with positions are 64-bit.
+constexpr int64_t kMaxVisibilities = (int64_t(1) << 31) - (int64_t(1) << 20);
 constexpr int kPartialsMax = 4096;     // per-block partials, per quantity slot
 constexpr int kDegridBlocks = 2048;    // persistent degridding blocks (8 per CU); <= kPartialsMax
 constexpr int kGridBlocks = 512;       // persistent gridding blocks (2 per CU, bound by LDS)
@@ -83,7 +87,9 @@ int phi_gw_adjoint(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s)
 int phi_gw_adjoint_parts(pr_phi_plan_t* p, const void* y, double scale, int parts, hipStream_t s);
 // Gridding with the scale read from device memory (1 / ||Phi|| of a solve).
 int phi_gw_adjoint_dev(pr_phi_plan_t* p, const void* y, const double* scale_dev, hipStream_t s);
-int phi_norm(pr_phi_plan_t* p, int iters, void* vis, double* norm, hipStream_t s);
+// Power method (host result): at most iters steps; rtol > 0 stops once
+// ||A x|| changes by at most rtol of itself between steps.
+int phi_norm(pr_phi_plan_t* p, int iters, double rtol, void* vis, double* norm, hipStream_t s);
 
 // Fused ADMM stages (defined with the operator kernels).
 struct AdmmVis {

@@ -357,7 +357,10 @@ int phi_validate(const pr_phi_desc* d) {
   if (d->oversample != 2) { set_error("oversample = %d: only 2 is supported", d->oversample); return PR_EUNSUPPORTED; }
   if (d->J != 2 && d->J != 4 && d->J != 6 && d->J != 8) { set_error("J = %d: must be 2, 4, 6 or 8", d->J); return PR_EINVAL; }
   if (d->D < 1 || d->D > 1000000) { set_error("D = %d: must be in [1, 1e6]", d->D); return PR_EINVAL; }
-  if (d->M < 0 || d->M >= (int64_t(1) << 31)) { set_error("M = %lld out of range", static_cast<long long>(d->M)); return PR_EINVAL; }
+  if (d->M < 0 || d->M > kMaxVisibilities) {
+    set_error("M = %lld out of range [0, %lld]", static_cast<long long>(d->M), static_cast<long long>(kMaxVisibilities));
+    return PR_EINVAL;
+  }
   if (d->prec != PR_F32 && d->prec != PR_F64) { set_error("prec = %d", d->prec); return PR_EINVAL; }
   if (d->interp != 0 && d->interp != 1) { set_error("interp = %d: must be 0 (nearest) or 1 (linear)", d->interp); return PR_EINVAL; }
   if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32) {

@@ -90,7 +90,7 @@ _SIGS = {
     "pr_phi_fzs_adjoint": (C.c_int, [_VP, _VP, _VP]),
     "pr_phi_grid_patches": (C.c_int, [_VP, _VP, _VP]),
     "pr_phi_grid_merge": (C.c_int, [_VP, _VP]),
-    "pr_phi_norm": (C.c_int, [_VP, _I32, _VP, C.POINTER(_D), _VP]),
+    "pr_phi_norm": (C.c_int, [_VP, _I32, _D, _VP, C.POINTER(_D), _VP]),
     "pr_psi_plan_sizes": (C.c_int, [_I32, _I32, _U32, _I32, C.POINTER(_SZ), C.POINTER(_SZ)]),
     "pr_psi_plan_create": (C.c_int, [_I32, _I32, _U32, _I32, _VP, _VP, _VP, C.POINTER(_VP)]),
     "pr_psi_plan_destroy": (C.c_int, [_VP]),
@@ -104,6 +104,11 @@ _SIGS = {
     "pr_admm_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
     "pr_admm_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_admm_params), _VP, _VP,
                                 C.POINTER(pr_admm_report), _VP]),
+    "pr_admm_resume": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_admm_params), _VP, _VP,
+                                 C.POINTER(pr_admm_report), _VP]),
+    "pr_admm_state_bytes": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
+    "pr_admm_state_export": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "pr_admm_state_import": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pr_fista_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
     "pr_fista_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_fista_params), _VP, _VP,
                                  C.POINTER(pr_admm_report), _VP]),
@@ -262,9 +267,10 @@ def pr_phi_grid_merge(plan, stream=None):
     _check(lib().pr_phi_grid_merge(plan, stream if stream is not None else _stream()))
 
 
-def pr_phi_norm(plan, iters, vis_ws, stream=None) -> float:
+def pr_phi_norm(plan, iters, rtol, vis_ws, stream=None) -> float:
     v = _D()
-    _check(lib().pr_phi_norm(plan, iters, _ptr(vis_ws), C.byref(v), stream if stream is not None else _stream()))
+    _check(lib().pr_phi_norm(plan, iters, float(rtol), _ptr(vis_ws), C.byref(v),
+                             stream if stream is not None else _stream()))
     return v.value
 
 
@@ -334,6 +340,29 @@ def pr_admm_solve(phi, psi, y, params: pr_admm_params, x, workspace, want_report
     _check(lib().pr_admm_solve(phi, psi, _ptr(y), C.byref(params), _ptr(x), _ptr(workspace),
                                C.byref(rep) if want_report else None, stream if stream is not None else _stream()))
     return rep if want_report else None
+
+
+def pr_admm_resume(phi, psi, y, params: pr_admm_params, x, workspace, want_report=True, stream=None):
+    rep = pr_admm_report()
+    _check(lib().pr_admm_resume(phi, psi, _ptr(y), C.byref(params), _ptr(x), _ptr(workspace),
+                                C.byref(rep) if want_report else None, stream if stream is not None else _stream()))
+    return rep if want_report else None
+
+
+def pr_admm_state_bytes(phi, psi) -> int:
+    v = _SZ()
+    _check(lib().pr_admm_state_bytes(phi, psi, C.byref(v)))
+    return v.value
+
+
+def pr_admm_state_export(phi, psi, workspace, x, state, stream=None):
+    _check(lib().pr_admm_state_export(phi, psi, _ptr(workspace), _ptr(x), _ptr(state),
+                                      stream if stream is not None else _stream()))
+
+
+def pr_admm_state_import(phi, psi, state, workspace, x, stream=None):
+    _check(lib().pr_admm_state_import(phi, psi, _ptr(state), _ptr(workspace), _ptr(x),
+                                      stream if stream is not None else _stream()))
 
 
 def pr_phi_tune(desc: pr_phi_desc, uv, w, persistent, scratch, vis_ws, reps=3, stream=None):
@@ -513,9 +542,9 @@ class PhiPlan:
         pr_phi_adjoint(self.handle, y, x)
         return x
 
-    def norm(self, iters=100):
+    def norm(self, iters=100, rtol=0.0):
         vis = torch.empty(max(self.M, 1), dtype=self.cdtype, device=self.device)
-        return pr_phi_norm(self.handle, iters, vis)
+        return pr_phi_norm(self.handle, iters, rtol, vis)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -32,6 +32,14 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm((a - b).ravel()) / (den if den > 0 else 1.0))
 
 
+def max_rel(a, b) -> float:
+    """Largest element-wise error over the largest reference magnitude."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    den = float(np.max(np.abs(b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0)) if b.size else 0.0
+
+
 def to_dev(a, dtype):
     return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
 

@@ -45,7 +45,8 @@ def test_version_and_error_text(P):
 
 @pytest.mark.parametrize("field,value,code", [
     ("n", 4, 1), ("n", 8192, 1), ("oversample", 3, 4), ("J", 5, 1), ("J", 10, 1),
-    ("D", 0, 1), ("M", -1, 1), ("M", 1 << 31, 1), ("prec", 2, 1), ("tile", 12, 1),
+    ("D", 0, 1), ("M", -1, 1), ("M", 1 << 31, 1), ("M", (1 << 31) - (1 << 20) + 1, 1), ("prec", 2, 1),
+    ("tile", 12, 1),
 ])
 def test_phi_descriptor_validation(P, field, value, code):
     d = P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0)
@@ -85,7 +86,7 @@ def test_workspace_and_null_checks(P):
     assert L.pr_phi_plan_create(C.byref(d), None, None, 256, 512, None, C.byref(h)) == P.PR_EINVAL
     assert L.pr_phi_apply(None, 256, 256, None) == P.PR_EINVAL
     assert L.pr_phi_adjoint(None, 256, 256, None) == P.PR_EINVAL
-    assert L.pr_phi_norm(None, 10, 256, None, None) == P.PR_EINVAL
+    assert L.pr_phi_norm(None, 10, 0.0, 256, None, None) == P.PR_EINVAL
 
 
 def test_prox_argument_checks(P):
@@ -138,6 +139,7 @@ def test_balls_argument_checks(P):
     assert L.pr_balls_sizes(1000, 0, C.byref(pb), C.byref(sb)) == P.PR_EINVAL
     assert L.pr_balls_sizes(-1, 4, C.byref(pb), C.byref(sb)) == P.PR_EINVAL
     assert L.pr_balls_sizes(1 << 31, 4, C.byref(pb), C.byref(sb)) == P.PR_EINVAL
+    assert L.pr_balls_sizes((1 << 31) - (1 << 20) + 1, 4, C.byref(pb), C.byref(sb)) == P.PR_EINVAL
     assert L.pr_balls_sizes(1000, 4, C.byref(pb), C.byref(sb)) == P.PR_OK
     assert pb.value >= 8 * 1000 and sb.value >= 16 * 1000
     h = C.c_void_p()
@@ -146,3 +148,86 @@ def test_balls_argument_checks(P):
     assert L.pr_balls_create(1000, 4, None, 256, pb.value, 256, sb.value, None, C.byref(h)) == P.PR_EINVAL
     rep = P.pr_admm_report()
     assert L.pr_admm_local_solve(None, None, None, None, None, None, None, None, C.byref(rep), None) == P.PR_EINVAL
+
+
+def test_largest_visibility_count_is_accepted(P):
+    """The bound is 2^31 - 2^20 visibilities: positions plus any per-item
+    offset stay below 2^31, and products with positions are 64-bit."""
+    big = (1 << 31) - (1 << 20)
+    pb, sb = P.pr_phi_plan_sizes(P.pr_phi_desc(2048, 2, 4, 2000, big, 0, 0))
+    assert pb >= 16 * big
+    L = P.lib()
+    p2, s2 = C.c_size_t(), C.c_size_t()
+    assert L.pr_balls_sizes(big, 4, C.byref(p2), C.byref(s2)) == P.PR_OK
+
+
+def test_checkpoint_argument_checks(P):
+    L = P.lib()
+    prm = P.admm_params(1.0, 0.1)
+    rep = P.pr_admm_report()
+    sz = C.c_size_t()
+    assert L.pr_admm_state_bytes(None, None, C.byref(sz)) == P.PR_EINVAL
+    assert L.pr_admm_state_export(None, None, 256, 256, 256, None) == P.PR_EINVAL
+    assert L.pr_admm_state_import(None, None, 256, 256, 256, None) == P.PR_EINVAL
+    assert L.pr_admm_resume(None, None, None, C.byref(prm), None, None, C.byref(rep), None) == P.PR_EINVAL
+    assert L.pr_phi_norm(None, 10, -1.0, 256, None, None) == P.PR_EINVAL
+
+
+_LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "purimi.h"
+#define F(T, f) printf(#T " " #f " %zu %zu\n", offsetof(T, f), sizeof(((T*)0)->f));
+#define S(T) printf(#T " __size__ %zu 0\n", sizeof(T));
+int main(void) {
+  S(pr_phi_desc) F(pr_phi_desc, n) F(pr_phi_desc, oversample) F(pr_phi_desc, J) F(pr_phi_desc, D)
+  F(pr_phi_desc, M) F(pr_phi_desc, prec) F(pr_phi_desc, tile) F(pr_phi_desc, interp)
+  S(pr_admm_params) F(pr_admm_params, iters) F(pr_admm_params, inner_iters) F(pr_admm_params, eps)
+  F(pr_admm_params, gamma) F(pr_admm_params, rho) F(pr_admm_params, varrho) F(pr_admm_params, eta)
+  F(pr_admm_params, rel_tol) F(pr_admm_params, op_norm) F(pr_admm_params, gamma_factor)
+  F(pr_admm_params, norm_iters)
+  S(pr_admm_report) F(pr_admm_report, iters_done) F(pr_admm_report, rel_var) F(pr_admm_report, resid_norm)
+  F(pr_admm_report, l1_norm) F(pr_admm_report, op_norm) F(pr_admm_report, nonfinite)
+  S(pr_reweight_params) F(pr_reweight_params, rounds) F(pr_reweight_params, delta0) F(pr_reweight_params, beta)
+  S(pr_fista_params) F(pr_fista_params, iters) F(pr_fista_params, inner_iters) F(pr_fista_params, gamma)
+  F(pr_fista_params, lambda) F(pr_fista_params, eta) F(pr_fista_params, op_norm)
+  F(pr_fista_params, gamma_factor) F(pr_fista_params, norm_iters)
+  S(pr_pd_params) F(pr_pd_params, iters) F(pr_pd_params, inner_iters) F(pr_pd_params, misfit)
+  F(pr_pd_params, eps) F(pr_pd_params, gamma) F(pr_pd_params, tau) F(pr_pd_params, sigma)
+  F(pr_pd_params, theta) F(pr_pd_params, eta) F(pr_pd_params, op_norm) F(pr_pd_params, gamma_factor)
+  F(pr_pd_params, norm_iters)
+  S(pr_job_desc) F(pr_job_desc, n) F(pr_job_desc, J) F(pr_job_desc, D) F(pr_job_desc, tile)
+  F(pr_job_desc, levels) F(pr_job_desc, basis_mask) F(pr_job_desc, prec) F(pr_job_desc, M) F(pr_job_desc, uv)
+  F(pr_job_desc, w) F(pr_job_desc, y) F(pr_job_desc, params) F(pr_job_desc, interp)
+  return 0;
+}
+"""
+
+
+def test_ctypes_structs_match_the_c_header(P, tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets, as laid out by the host C compiler."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(_LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    rename = {"lambda": "lambda_"}
+    checked = 0
+    for line in out:
+        if not line.strip():
+            continue
+        tname, field, off, size = line.split()
+        T = getattr(P, tname)
+        if field == "__size__":
+            assert C.sizeof(T) == int(off), tname
+        else:
+            f = getattr(T, rename.get(field, field))
+            assert (f.offset, f.size) == (int(off), int(size)), (tname, field)
+        checked += 1
+    assert checked >= 60

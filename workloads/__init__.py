@@ -168,6 +168,9 @@ CONFIGS = {
     # single-operator throughput, J in {4, 6}
     "op256": Workload("op-256sq-M1e6-J4", 1, 256, 2, 1_000_000, 4, 2000, 4, 1),
     "op256j6": Workload("op-256sq-M1e6-J6", 1, 256, 2, 1_000_000, 6, 2000, 4, 1),
+    # mid-size solver parity: several wavelet levels run per level (not in the
+    # small-image tail), work items span many staged chunks
+    "mid128": Workload("mid-128sq-M4e4-J4", 5, 128, 2, 40_000, 4, 2000, 3, 20),
     # one GPU's share of the large distributed run
     "share2048": Workload("share-2048sq-M5e8-J4-ringcore", 2, 2048, 2, 500_000_000, 4, 2000, 4, 20,
                    uv_law="ringcore"),
