@@ -244,17 +244,24 @@ def phi_adjoint(y, uv, w, spec: PhiSpec):
     return phi_adjoint_complex(y, uv, w, spec).real
 
 
-def power_method(uv, w, spec: PhiSpec, iters: int = 100):
+def power_method(uv, w, spec: PhiSpec, iters: int = 100, rtol: float = 0.0):
     """Largest eigenvalue of Re Phi^H Phi by power iteration; returns ||Phi||.
 
     Starts from the constant image of unit norm; each step x <- A x / ||A x||;
     the estimate after the last step is ||A x|| and ||Phi|| = sqrt of it.
+    With rtol > 0 the iteration also stops after the first step whose estimate
+    changed by at most rtol times itself from the step before (Section
+    "Distributed Images" normalises Phi by this power-method estimate).
     """
     n = spec.n
     x = np.full((n, n), 1.0 / n)
     lam = 0.0
+    lam_prev = -1.0
     for _ in range(iters):
         ax = phi_adjoint(phi(x, uv, w, spec), uv, w, spec)
         lam = float(np.sqrt(np.sum(ax * ax)))
         x = ax / lam
+        if rtol > 0 and lam_prev >= 0 and abs(lam - lam_prev) <= rtol * lam:
+            break
+        lam_prev = lam
     return math.sqrt(lam)

@@ -163,6 +163,18 @@ def test_power_method_matches_dense_two_norm():
     ref = np.linalg.norm(real_map, 2)
     got = ms.power_method(uv, w, spec, iters=2000)
     assert got == pytest.approx(ref, rel=1e-8)
+    # the stopping rule: a tight rtol reaches the same norm well before 2000
+    # steps; every estimate ||A x|| of a unit x is a lower bound of ||A||
+    assert ms.power_method(uv, w, spec, iters=2000, rtol=1e-15) == pytest.approx(ref, rel=1e-7)
+    for rtol in (1e-2, 1e-3, 1e-6):
+        est = ms.power_method(uv, w, spec, iters=2000, rtol=rtol)
+        assert est <= ref * (1 + 1e-12)
+    # a loose rtol stops after the first step that changes by <= rtol: the same
+    # value as a fixed count equal to that step
+    loose = ms.power_method(uv, w, spec, iters=2000, rtol=1e-2)
+    steps = next(k for k in range(1, 2000)
+                 if ms.power_method(uv, w, spec, iters=k) == loose)
+    assert steps < 2000
 
 
 def test_visibility_order_is_irrelevant():
