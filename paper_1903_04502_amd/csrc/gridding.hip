@@ -19,6 +19,7 @@
 // patches of each grid cell, items in order.
 #include <mutex>
 #include <set>
+#include <type_traits>
 #include <utility>
 
 #include "phi.hpp"
@@ -38,6 +39,47 @@ constexpr size_t kLdsSoft = 81920;    // two blocks per CU
 constexpr size_t kLdsHard = 163840;   // per-workgroup limit on gfx950
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+// Visibility storage and kernel lookup of a launch (template argument LK):
+// 0 nearest sample and 1 first-order lookup, both from stored (u, v, w)
+// triples (taps formed in FP64 per visibility and launch); 2 nearest sample
+// from stored (tap word, w) pairs (FP32 plans; the taps were formed by the
+// plan with the same arithmetic).
+constexpr int kLkNearest = 0, kLkLinear = 1, kLkWords = 2;
+
+// Taps of one visibility and its base cell (lu, lv) relative to tile
+// (tu, tv). TW: x holds the tap word's bits, y is unused; else x, y = u, v.
+template <bool TW, typename R>
+__device__ __forceinline__ void vis_taps(R x, R y, double kappa, int J, int D, int K, int T, int tu, int tv,
+                                         AxisTaps& xu, AxisTaps& xv, int& lu, int& lv) {
+  if constexpr (TW) {
+    const uint32_t w = __float_as_uint(static_cast<float>(x));
+    xu = word_axis((w >> 8) & 0xFFFu);
+    xv = word_axis(w >> 20);
+    lu = static_cast<int>(w & 15u);
+    lv = static_cast<int>((w >> 4) & 15u);
+  } else {
+    xu = axis_taps(static_cast<double>(x), kappa, J, D);
+    xv = axis_taps(static_cast<double>(y), kappa, J, D);
+    lu = mod_pow2(xu.j0, K) - tu * T;
+    lv = mod_pow2(xv.j0, K) - tv * T;
+  }
+}
+
+// Stored inputs of plan position k: (x, y, w) as vis_taps takes them.
+template <bool TW, typename R>
+__device__ __forceinline__ void vis_load(const R* uv, int64_t k, R& x, R& y, R& w) {
+  if constexpr (TW) {
+    const uint2 q = reinterpret_cast<const uint2*>(uv)[k];
+    x = __uint_as_float(q.x);
+    y = R(0);
+    w = __uint_as_float(q.y);
+  } else {
+    x = uv[3 * k];
+    y = uv[3 * k + 1];
+    w = uv[3 * k + 2];
+  }
+}
 
 // ---------------------------------------------------------------------------
 // degridding
@@ -64,9 +106,10 @@ struct GwArgs {
 
 constexpr int kDegridPer = 4;   // visibilities per thread per chunk
 
-template <typename R, int J, int MODE, bool TAB_LDS, bool LIN>
+template <typename R, int J, int MODE, bool TAB_LDS, int LK>
 __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   using C = cx_t<R>;
+  constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
   const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int CH = kThreads * kDegridPer;
   extern __shared__ char smem_raw[];
@@ -81,11 +124,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
 #pragma unroll
     for (int j = 0; j < kDegridPer; ++j) {
       const int64_t k = c0 + tid + j * kThreads;
-      if (k < cend) {
-        u[j] = a.uv[3 * k];
-        v[j] = a.uv[3 * k + 1];
-        w[j] = a.uv[3 * k + 2];
-      }
+      if (k < cend) vis_load<TW>(a.uv, k, u[j], v[j], w[j]);
     }
   };
   const int kbeg = a.sched_off[blockIdx.x], kend = a.sched_off[blockIdx.x + 1];
@@ -134,10 +173,9 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
       for (int j = 0; j < kDegridPer; ++j) {
         const int64_t k = c0 + tid + j * kThreads;
         if (k >= it.z) continue;
-        const AxisTaps xu = axis_taps(static_cast<double>(cu_[j]), a.kappa, J, a.D);
-        const AxisTaps xv = axis_taps(static_cast<double>(cv_[j]), a.kappa, J, a.D);
-        const int lu = mod_pow2(xu.j0, K) - tu * T;
-        const int lv = mod_pow2(xv.j0, K) - tv * T;
+        AxisTaps xu, xv;
+        int lu, lv;
+        vis_taps<TW>(cu_[j], cv_[j], a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
         if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
           // cannot happen for a plan's own sorted baselines; flag instead of reading out of the patch
           const R nan = R(NAN);
@@ -292,9 +330,10 @@ constexpr int kGridPer = 4;   // staged visibilities per thread: B <= kThreads *
 // moment is therefore a sum in a fixed order: deterministic, no atomics. The
 // next batch's inputs are loaded into registers while the current one is
 // accumulated.
-template <typename R, int J, int JA, int MODE, bool TAB_LDS, bool LIN>
+template <typename R, int J, int JA, int MODE, bool TAB_LDS, int LK>
 __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
+  constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
   const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int TPC = (J + JA - 1) / JA;
@@ -351,9 +390,7 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
       const int i = tid + j * kThreads;
       if (i < n0) {
         const int64_t k = b0 + i;
-        ru[j] = a.uv[3 * k];
-        rv[j] = a.uv[3 * k + 1];
-        rw[j] = a.uv[3 * k + 2];
+        vis_load<TW>(a.uv, k, ru[j], rv[j], rw[j]);
         if (MODE == 0) {
           ry[j] = a.y_in[k];
         } else {
@@ -392,10 +429,9 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
         const int i = tid + j * kThreads;
         if (i >= nb) continue;
         const int64_t k = bs + i;
-        const AxisTaps xu = axis_taps(static_cast<double>(ru[j]), a.kappa, J, a.D);
-        const AxisTaps xv = axis_taps(static_cast<double>(rv[j]), a.kappa, J, a.D);
-        int lu = mod_pow2(xu.j0, K) - tu * T;
-        int lv = mod_pow2(xv.j0, K) - tv * T;
+        AxisTaps xu, xv;
+        int lu, lv;
+        vis_taps<TW>(ru[j], rv[j], a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
         const bool inside = static_cast<unsigned>(lu) < static_cast<unsigned>(T) &&
                             static_cast<unsigned>(lv) < static_cast<unsigned>(T);
         C val;
@@ -600,11 +636,14 @@ template <typename R, int MODE>
 struct WalkPrefetch {
   using C = cx_t<R>;
   static constexpr int WC = WalkChunk<R>::value;
-  C uv[WC];
+  // one (u, v, w) triple per slot, loaded as one piece and consumed in place
+  // (a separate w register makes the compiler copy it out of the load's
+  // destination, which waits for the load while the next ones are issued)
+  struct Uvw { R u, v, w; };
+  Uvw uvw[WC];
   C val[WC];                      // MODE 0: y; MODE 1: t = v + s - y
   C s[MODE == 1 ? WC : 1];        // MODE 1: multiplier before the update
   int sec[MODE == 1 ? WC : 1];    // MODE 1 with local balls: section of the position
-  R w[WC];
   unsigned ok;                    // bit r: slot r holds a position of the item
 };
 
@@ -626,9 +665,10 @@ struct WalkPrefetch {
 // whole sum in its side slot after the walk; the owner then adds, in segment
 // order, the side slots of the middle segments and the final part already in
 // the moments, and stores the total.
-template <typename R, int J, int MODE, bool TAB_LDS, bool LIN>
+template <typename R, int J, int MODE, bool TAB_LDS, int LK>
 __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
+  constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
   const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int WC = WalkChunk<R>::value;
@@ -669,8 +709,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       const bool ok = q < L && pos < it.z;
       pf.ok |= static_cast<unsigned>(ok) << r;
       const int64_t pc = ok ? pos : static_cast<int64_t>(it.y);
-      pf.uv[r] = cmk<C>(a.uv[3 * pc], a.uv[3 * pc + 1]);
-      pf.w[r] = a.uv[3 * pc + 2];
+      vis_load<TW>(a.uv, pc, pf.uvw[r].u, pf.uvw[r].v, pf.uvw[r].w);
       if (MODE == 0) {
         pf.val[r] = a.y_in[pc];
       } else {
@@ -701,8 +740,8 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
         val = cmk<C>(a.vr_coef * vr.x + sn.x, a.vr_coef * vr.y + sn.y);
       }
-      const R ws = pf.w[r] * scale;
-      const C uvr = pf.uv[r];
+      const R ws = pf.uvw[r].w * scale;
+      const C uvr = cmk<C>(pf.uvw[r].u, pf.uvw[r].v);
       const C wv = cmk<C>(val.x * ws, val.y * ws);
       if (ok) {
         if (MODE == 1) a.s_io[static_cast<int64_t>(it.y) + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
@@ -748,28 +787,31 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       for (int i = tid; i < lay.borrow; i += kThreads) t[i] = a.table[i];
     }
 
+    // the item's first chunk was prefetched during the previous item's last
+    // chunk (or before the loop)
+    commit(it, L, 0);
+
     R ar[JJ], ai[JJ];
     int first = -1, cur = -1, nruns = 0;
 #pragma unroll
     for (int e = 0; e < JJ; ++e) ar[e] = ai[e] = R(0);
     for (int q0 = 0; q0 < L; q0 += WC) {
-      if (q0 > 0) __syncthreads();   // the previous chunk has been walked
-      commit(it, L, q0);
-      {
-        // one call site for both prefetch targets (next chunk, or next item's first)
-        const bool more = q0 + WC < L;
-        if (more || has_next) issue(more ? it : itn, more ? L : Ln, more ? q0 + WC : 0);
-      }
-      __syncthreads();
+      const bool more = q0 + WC < L;
+      // Prefetch the next chunk, else the next item's first chunk, into
+      // registers; they are stored after this chunk's walk, in the same
+      // iteration, so no prefetched register is carried around the loop (a
+      // carried one makes the compiler copy it, waiting for its load). With
+      // nothing left the slots reload this item's first positions, unused.
+      issue(more || !has_next ? it : itn, more || !has_next ? L : Ln, more ? q0 + WC : 0);
+      __syncthreads();   // the chunk is staged
       const int qn = min(WC, segn - q0);
       for (int i = 0; i < qn; ++i) {
         const Staged sp = st[i * kStagePitch + tid];
         const C uv = sp.uv;
         C val = sp.val;
-        const AxisTaps xu = axis_taps(static_cast<double>(uv.x), a.kappa, J, a.D);
-        const AxisTaps xv = axis_taps(static_cast<double>(uv.y), a.kappa, J, a.D);
-        int lu = mod_pow2(xu.j0, K) - tu * T;
-        int lv = mod_pow2(xv.j0, K) - tv * T;
+        AxisTaps xu, xv;
+        int lu, lv;
+        vis_taps<TW>(uv.x, uv.y, a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
         if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
           // cannot happen for a plan's own sorted baselines: keep LDS indices in range, poison the value
           lu = lv = 0;
@@ -804,6 +846,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
             ai[qq * J + b] += wv[b] * yi;
           }
         }
+      }
+      if (more) {
+        __syncthreads();   // the chunk has been walked
+        commit(it, L, q0 + WC);
       }
     }
     if (TAB_LDS && lay.borrow) __syncthreads();   // every walk done with the table head
@@ -1039,7 +1085,7 @@ int allow_lds(K kernel, size_t bytes) {
   return PR_OK;
 }
 
-template <typename R, int J, int MODE, bool LIN>
+template <typename R, int J, int MODE, int LK>
 int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
   using C = cx_t<R>;
   const size_t patch = align16(static_cast<size_t>(p->P) * p->P * sizeof(C));
@@ -1048,10 +1094,10 @@ int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
   if (MODE >= 1 && lds < kThreads * sizeof(double)) lds = kThreads * sizeof(double);
   const int G = degrid_blocks(p);
   if (lds + tabb <= kLdsSoft) {
-    degrid_kernel<R, J, MODE, true, LIN><<<G, kThreads, lds + tabb, s>>>(a);
+    degrid_kernel<R, J, MODE, true, LK><<<G, kThreads, lds + tabb, s>>>(a);
   } else if (lds <= kLdsHard) {
-    PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false, LIN>, lds));
-    degrid_kernel<R, J, MODE, false, LIN><<<G, kThreads, lds, s>>>(a);
+    PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false, LK>, lds));
+    degrid_kernel<R, J, MODE, false, LK><<<G, kThreads, lds, s>>>(a);
   } else {
     set_error("degridding patch of tile %d does not fit in LDS", p->T);
     return PR_EUNSUPPORTED;
@@ -1084,7 +1130,7 @@ bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
   return false;
 }
 
-template <typename R, int J, int MODE, bool LIN>
+template <typename R, int J, int MODE, int LK>
 int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) {
   using C = cx_t<R>;
   constexpr int JA = GridSplit<R, J>::JA;
@@ -1099,11 +1145,11 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
     const size_t bytes = tl ? with.total : without.total;
     if (bytes <= kLdsHard) {
       if (tl) {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LIN>, bytes));
-        grid_walk_kernel<R, J, MODE, true, LIN><<<G, kThreads, bytes, s>>>(a);
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LK>, bytes));
+        grid_walk_kernel<R, J, MODE, true, LK><<<G, kThreads, bytes, s>>>(a);
       } else {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LIN>, bytes));
-        grid_walk_kernel<R, J, MODE, false, LIN><<<G, kThreads, bytes, s>>>(a);
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LK>, bytes));
+        grid_walk_kernel<R, J, MODE, false, LK><<<G, kThreads, bytes, s>>>(a);
       }
       walked = true;
     }
@@ -1118,11 +1164,11 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
     }
     a.B = B;
     if (tab_lds) {
-      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true, LIN>, bytes));
-      grid_kernel<R, J, JA, MODE, true, LIN><<<G, kThreads, bytes, s>>>(a);
+      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true, LK>, bytes));
+      grid_kernel<R, J, JA, MODE, true, LK><<<G, kThreads, bytes, s>>>(a);
     } else {
-      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false, LIN>, bytes));
-      grid_kernel<R, J, JA, MODE, false, LIN><<<G, kThreads, bytes, s>>>(a);
+      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false, LK>, bytes));
+      grid_kernel<R, J, JA, MODE, false, LK><<<G, kThreads, bytes, s>>>(a);
     }
   }
   PR_TRY_LAUNCH();
@@ -1134,43 +1180,55 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
   return PR_OK;
 }
 
-template <typename R, int J, int MODE, bool LIN>
+template <typename R, int J, int MODE, int LK>
 int setup_mode() {
   constexpr int JA = GridSplit<R, J>::JA;
-  PR_TRY((allow_lds(degrid_kernel<R, J, MODE, true, LIN>, kLdsHard)));
-  PR_TRY((allow_lds(degrid_kernel<R, J, MODE, false, LIN>, kLdsHard)));
+  PR_TRY((allow_lds(degrid_kernel<R, J, MODE, true, LK>, kLdsHard)));
+  PR_TRY((allow_lds(degrid_kernel<R, J, MODE, false, LK>, kLdsHard)));
   if constexpr (J <= 4) {
-    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LIN>, kLdsHard)));
-    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LIN>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LK>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LK>, kLdsHard)));
   }
-  PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, true, LIN>, kLdsHard)));
-  PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, false, LIN>, kLdsHard)));
+  PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, true, LK>, kLdsHard)));
+  PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, false, LK>, kLdsHard)));
   return PR_OK;
 }
 
-template <typename R, int J>
-int setup_kernels(bool lin) {
-  if (lin) {
-    PR_TRY((allow_lds(degrid_kernel<R, J, 2, true, true>, kLdsHard)));
-    PR_TRY((allow_lds(degrid_kernel<R, J, 2, false, true>, kLdsHard)));
-    PR_TRY((setup_mode<R, J, 0, true>()));
-    return setup_mode<R, J, 1, true>();
+template <typename R, int J, int LK>
+int setup_kernels() {
+  PR_TRY((allow_lds(degrid_kernel<R, J, 2, true, LK>, kLdsHard)));
+  PR_TRY((allow_lds(degrid_kernel<R, J, 2, false, LK>, kLdsHard)));
+  PR_TRY((setup_mode<R, J, 0, LK>()));
+  return setup_mode<R, J, 1, LK>();
+}
+
+// Compile-time dispatch on the kernel width and on the plan's lookup kind
+// (tap words exist for FP32 plans only).
+template <typename F>
+int with_j(int J, F&& f) {
+  switch (J) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: set_error("J = %d unsupported", J); return PR_EUNSUPPORTED;
   }
-  PR_TRY((allow_lds(degrid_kernel<R, J, 2, true, false>, kLdsHard)));
-  PR_TRY((allow_lds(degrid_kernel<R, J, 2, false, false>, kLdsHard)));
-  PR_TRY((setup_mode<R, J, 0, false>()));
-  return setup_mode<R, J, 1, false>();
+}
+
+template <typename R, typename F>
+int with_lk(const pr_phi_plan_t* p, F&& f) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (p->tapwords) return f(std::integral_constant<int, kLkWords>{});
+  }
+  if (p->interp) return f(std::integral_constant<int, kLkLinear>{});
+  return f(std::integral_constant<int, kLkNearest>{});
 }
 
 template <typename R>
-int setup_prec(int J, bool lin) {
-  switch (J) {
-    case 2: return setup_kernels<R, 2>(lin);
-    case 4: return setup_kernels<R, 4>(lin);
-    case 6: return setup_kernels<R, 6>(lin);
-    case 8: return setup_kernels<R, 8>(lin);
-    default: set_error("J = %d unsupported", J); return PR_EUNSUPPORTED;
-  }
+int setup_prec(const pr_phi_plan_t* p) {
+  return with_j(p->J, [&](auto jj) {
+    return with_lk<R>(p, [&](auto lk) { return setup_kernels<R, decltype(jj)::value, decltype(lk)::value>(); });
+  });
 }
 
 template <typename R>
@@ -1217,22 +1275,13 @@ GwAdjArgs<R> gwadj_args(pr_phi_plan_t* p, double scale) {
   return a;
 }
 
-#define PR_DISPATCH_J(J, CALL) \
-  switch (J) {                 \
-    case 2: return CALL(2);    \
-    case 4: return CALL(4);    \
-    case 6: return CALL(6);    \
-    case 8: return CALL(8);    \
-    default: set_error("J = %d unsupported", J); return PR_EUNSUPPORTED; \
-  }
-
 template <typename R>
 int gw_plain(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {
   GwArgs<R> a = gw_args<R>(p, scale);
   a.y_out = static_cast<cx_t<R>*>(y);
-#define CALL(JJ) (p->interp ? launch_degrid<R, JJ, 0, true>(p, a, s) : launch_degrid<R, JJ, 0, false>(p, a, s))
-  PR_DISPATCH_J(p->J, CALL)
-#undef CALL
+  return with_j(p->J, [&](auto jj) {
+    return with_lk<R>(p, [&](auto lk) { return launch_degrid<R, decltype(jj)::value, 0, decltype(lk)::value>(p, a, s); });
+  });
 }
 
 template <typename R>
@@ -1244,18 +1293,12 @@ int gw_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {
   a.t_out = static_cast<cx_t<R>*>(v.t);
   a.partials = p->partials;
   a.sec = v.sec;
-  int rc;
-#define CALL(JJ)                                                                                      \
-  (v.sec_partials ? (p->interp ? launch_degrid<R, JJ, 2, true>(p, a, s) : launch_degrid<R, JJ, 2, false>(p, a, s)) \
-                  : (p->interp ? launch_degrid<R, JJ, 1, true>(p, a, s) : launch_degrid<R, JJ, 1, false>(p, a, s)))
-  switch (p->J) {
-    case 2: rc = CALL(2); break;
-    case 4: rc = CALL(4); break;
-    case 6: rc = CALL(6); break;
-    case 8: rc = CALL(8); break;
-    default: set_error("J = %d unsupported", p->J); return PR_EUNSUPPORTED;
-  }
-#undef CALL
+  const int rc = with_j(p->J, [&](auto jj) {
+    return with_lk<R>(p, [&](auto lk) {
+      constexpr int JJ = decltype(jj)::value, LK = decltype(lk)::value;
+      return v.sec_partials ? launch_degrid<R, JJ, 2, LK>(p, a, s) : launch_degrid<R, JJ, 1, LK>(p, a, s);
+    });
+  });
   if (rc != PR_OK) return rc;
   ball_scale_kernel<<<1, kThreads, 0, s>>>(p->partials, degrid_blocks(p), v.eps, v.kappa_fixed, v.sums);
   PR_TRY_LAUNCH();
@@ -1268,9 +1311,11 @@ int gwadj_plain(pr_phi_plan_t* p, const void* y, double scale, hipStream_t s, in
   GwAdjArgs<R> a = gwadj_args<R>(p, scale);
   a.y_in = static_cast<const cx_t<R>*>(y);
   a.scale_dev = scale_dev;
-#define CALL(JJ) (p->interp ? launch_grid<R, JJ, 0, true>(p, a, s, parts) : launch_grid<R, JJ, 0, false>(p, a, s, parts))
-  PR_DISPATCH_J(p->J, CALL)
-#undef CALL
+  return with_j(p->J, [&](auto jj) {
+    return with_lk<R>(p, [&](auto lk) {
+      return launch_grid<R, decltype(jj)::value, 0, decltype(lk)::value>(p, a, s, parts);
+    });
+  });
 }
 
 template <typename R>
@@ -1284,9 +1329,9 @@ int gwadj_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) 
   a.vr_coef = static_cast<R>(v.vr_coef);
   a.sec = v.sec;
   a.kappa_sec = v.kappa_sec;
-#define CALL(JJ) (p->interp ? launch_grid<R, JJ, 1, true>(p, a, s) : launch_grid<R, JJ, 1, false>(p, a, s))
-  PR_DISPATCH_J(p->J, CALL)
-#undef CALL
+  return with_j(p->J, [&](auto jj) {
+    return with_lk<R>(p, [&](auto lk) { return launch_grid<R, decltype(jj)::value, 1, decltype(lk)::value>(p, a, s); });
+  });
 }
 
 template <typename R>
@@ -1299,7 +1344,7 @@ __global__ void zero_cx_kernel(cx_t<R>* a, int64_t n) {
 }  // namespace
 
 int phi_gridding_setup(pr_phi_plan_t* p) {
-  return p->prec == PR_F32 ? setup_prec<float>(p->J, p->interp != 0) : setup_prec<double>(p->J, p->interp != 0);
+  return p->prec == PR_F32 ? setup_prec<float>(p) : setup_prec<double>(p);
 }
 
 int phi_gw(pr_phi_plan_t* p, void* y, double scale, hipStream_t s) {

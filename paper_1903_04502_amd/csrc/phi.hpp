@@ -12,6 +12,10 @@ struct pr_phi_plan_t {
   int nTiles = 0;
   int prec = PR_F32;
   int interp = 0;   // 0 nearest sample, 1 first-order (linear) lookup
+  // Storage of the sorted visibilities: false, (u, v, w) triples (Real[3M]);
+  // true, for FP32 nearest-sample plans with tiles <= 16 and D <= 2047, one
+  // (tap word, w) pair per visibility (uint32 + float, 8 bytes; taps.hpp)
+  bool tapwords = false;
   int64_t M = 0;
   int64_t nItems = 0, nItemsMax = 0;
   int chunk = 0;    // max visibilities per gridding work item
@@ -19,7 +23,7 @@ struct pr_phi_plan_t {
   double beta = 0;  // Kaiser-Bessel shape
 
   // persistent workspace
-  void* uv = nullptr;          // sorted (u, v, w) triples, Real[3M] (one load per visibility)
+  void* uv = nullptr;          // sorted visibilities: (u, v, w) triples or (tap word, w) pairs
   int32_t* perm = nullptr;     // plan position -> user index
   int32_t* item_off = nullptr; // per tile first work item, [nTiles + 1]
   int4* items = nullptr;       // (tile, begin, end, 0)

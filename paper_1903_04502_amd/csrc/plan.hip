@@ -319,6 +319,20 @@ __global__ void gather_sorted_kernel(const R* uv, const R* w, const uint32_t* pe
   perm_out[k] = static_cast<int32_t>(j);
 }
 
+// FP32 nearest-sample plans: the taps of each visibility evaluated once, with
+// the same axis_taps as the cell keys, stored as (tap word, w) in plan order.
+__global__ void gather_tapwords_kernel(const float* uv, const float* w, const uint32_t* perm, int64_t M,
+                                       double kappa, int K, int J, int D, int T, uint2* out, int32_t* perm_out) {
+  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (k >= M) return;
+  const uint32_t j = perm[k];
+  const AxisTaps tu = axis_taps(static_cast<double>(uv[2 * static_cast<int64_t>(j)]), kappa, J, D);
+  const AxisTaps tv = axis_taps(static_cast<double>(uv[2 * static_cast<int64_t>(j) + 1]), kappa, J, D);
+  const int lu = mod_pow2(tu.j0, K) & (T - 1), lv = mod_pow2(tv.j0, K) & (T - 1);
+  out[k] = make_uint2(tap_word(tu, tv, lu, lv), __float_as_uint(w ? w[j] : 1.0f));
+  perm_out[k] = static_cast<int32_t>(j);
+}
+
 // ---------------------------------------------------------------------------
 // layout, validation, creation
 // ---------------------------------------------------------------------------
@@ -362,7 +376,10 @@ int phi_validate(const pr_phi_desc* d) {
     return PR_EINVAL;
   }
   if (d->prec != PR_F32 && d->prec != PR_F64) { set_error("prec = %d", d->prec); return PR_EINVAL; }
-  if (d->interp != 0 && d->interp != 1) { set_error("interp = %d: must be 0 (nearest) or 1 (linear)", d->interp); return PR_EINVAL; }
+  if (d->interp < 0 || d->interp > 2) {
+    set_error("interp = %d: must be 0 (nearest), 1 (linear) or 2 (nearest, taps recomputed per launch)", d->interp);
+    return PR_EINVAL;
+  }
   if (d->tile != 0 && d->tile != 8 && d->tile != 16 && d->tile != 32) {
     set_error("tile = %d: must be 0, 8, 16 or 32", d->tile);
     return PR_EINVAL;
@@ -385,9 +402,10 @@ int phi_prepare(pr_phi_plan_t* p, const pr_phi_desc* d) {
   p->D = d->D;
   p->M = d->M;
   p->prec = d->prec;
-  p->interp = d->interp;
+  p->interp = d->interp == 1 ? 1 : 0;
   p->T = d->tile ? d->tile : default_tile(d->J, d->prec, d->M, p->K);
   p->P = p->T + p->J - 1;
+  p->tapwords = d->interp == 0 && d->prec == PR_F32 && p->T <= kTapWordMaxTile && d->D <= kTapWordMaxD;
   p->nT = p->K / p->T;
   p->nTiles = p->nT * p->nT;
   // Work-item size: about M / 2048 visibilities (a power of two in [2048, 8192])
@@ -434,7 +452,8 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   const size_t rs = p->prec == PR_F32 ? 4 : 8;
   const int64_t M = p->M;
   Carver a(persistent);
-  p->uv = a.take<char>(3 * M * rs);   // (u, v, w) per visibility, plan order
+  // (u, v, w) or (tap word, w) per visibility, plan order
+  p->uv = a.take<char>(p->tapwords ? 8 * M : 3 * M * rs);
   p->perm = a.take<int32_t>(M);
   p->item_off = a.take<int32_t>(p->nTiles + 1);
   p->items = a.take<int4>(p->nItemsMax);
@@ -563,7 +582,16 @@ static int create_impl(pr_phi_plan_t* p, const R* uv, const R* w, hipStream_t s)
       std::swap(kin, kout);
       std::swap(vin, vout);
     }
-    gather_sorted_kernel<R><<<gb, 256, 0, s>>>(uv, w, vin, M, static_cast<R*>(p->uv), p->perm);
+    if constexpr (std::is_same<R, float>::value) {
+      if (p->tapwords) {
+        gather_tapwords_kernel<<<gb, 256, 0, s>>>(uv, w, vin, M, p->kappa, p->K, p->J, p->D, p->T,
+                                                  static_cast<uint2*>(p->uv), p->perm);
+      } else {
+        gather_sorted_kernel<R><<<gb, 256, 0, s>>>(uv, w, vin, M, static_cast<R*>(p->uv), p->perm);
+      }
+    } else {
+      gather_sorted_kernel<R><<<gb, 256, 0, s>>>(uv, w, vin, M, static_cast<R*>(p->uv), p->perm);
+    }
     PR_TRY_LAUNCH();
     const int nt1 = p->nTiles + 1;
     tile_bounds_kernel<<<(nt1 + 255) / 256, 256, 0, s>>>(kin, M, p->nTiles, p->T * p->T, cs.tile_start);

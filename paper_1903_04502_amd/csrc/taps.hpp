@@ -48,6 +48,33 @@ __device__ __forceinline__ AxisTaps axis_taps(double u, double kappa, int J, int
   return t;
 }
 
+// Compact pre-sampled taps of one visibility (nearest-sample lookup): the
+// plan evaluates axis_taps once and stores, in 32 bits, the base cell within
+// its tile (4 bits per axis, tiles of at most 16 cells) and, per axis,
+// 2 * up + (up != dn) in 12 bits (D <= 2047). The launches then read the
+// sample indices instead of recomputing them from (u, v): the same integers,
+// so the same weights.
+constexpr int kTapWordMaxTile = 16;
+constexpr int kTapWordMaxD = 2047;
+
+__device__ __forceinline__ uint32_t tap_word(const AxisTaps& tu, const AxisTaps& tv, int lu, int lv) {
+  const uint32_t au = 2u * static_cast<uint32_t>(tu.up) + (tu.up != tu.dn ? 1u : 0u);
+  const uint32_t av = 2u * static_cast<uint32_t>(tv.up) + (tv.up != tv.dn ? 1u : 0u);
+  return static_cast<uint32_t>(lu) | (static_cast<uint32_t>(lv) << 4) | (au << 8) | (av << 20);
+}
+
+// The sample indices of one axis from its 12 bits (j0, ff and r are not used
+// by the nearest-sample lookup and stay zero).
+__device__ __forceinline__ AxisTaps word_axis(uint32_t a12) {
+  AxisTaps t;
+  t.j0 = 0;
+  t.up = static_cast<int>(a12 >> 1);
+  t.dn = t.up - static_cast<int>(a12 & 1u);
+  t.ff = 0;
+  t.r = 0.0;
+  return t;
+}
+
 // Table index of tap a.
 __device__ __forceinline__ int tap_index(const AxisTaps& t, int a, int J, int D) {
   const int m = J / 2 - 1 - a;

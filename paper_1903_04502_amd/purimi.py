@@ -506,7 +506,10 @@ def tune_tile(n, uv, w=None, J=4, D=2000, oversample=2, prec=None, reps=3, inter
 class PhiPlan:
     """Measurement operator plan for one set of baselines (see pr_phi_plan_create).
     tile: 0 = the library default, "auto" = measured by the autotuner.
-    interp: 0 = nearest table sample, 1 = first-order (linear) lookup."""
+    interp: 0 = nearest table sample (FP32 plans with tiles <= 16 and D <= 2047
+    store each visibility's taps, evaluated once), 1 = first-order (linear)
+    lookup, 2 = nearest table sample with the taps recomputed from the stored
+    (u, v) at every launch (the same samples as 0)."""
 
     def __init__(self, n, uv, w=None, J=4, D=2000, oversample=2, tile=0, prec=None, interp=0):
         dev = uv.device

@@ -73,8 +73,10 @@ def test_phi_sizes_scale_with_the_problem(P):
     f64 = P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 8192, 1, 0))
     assert all(v > 0 and v % 256 == 0 for v in small + big + f64)
     assert big[0] > small[0] and f64[0] > small[0]
-    # persistent part holds at least uv, w and the permutation (16 B per visibility in FP32)
-    assert big[0] >= 16 * 81920
+    # persistent part holds at least the stored taps (or uv), w and the
+    # permutation: 12 B per visibility in FP32 with stored taps, else 16 B
+    assert big[0] >= 12 * 81920
+    assert P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 81920, 0, 0, 2))[0] >= 16 * 81920
 
 
 def test_workspace_and_null_checks(P):
@@ -118,9 +120,28 @@ def test_psi_and_admm_checks(P):
 
 def test_interp_mode_is_validated(P):
     assert P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0, 1))[0] > 0
-    with pytest.raises(P.PrError) as e:
-        P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0, 2))
-    assert e.value.code == P.PR_EINVAL
+    assert P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0, 2))[0] > 0
+    for bad in (-1, 3):
+        with pytest.raises(P.PrError) as e:
+            P.pr_phi_plan_sizes(P.pr_phi_desc(64, 2, 4, 2000, 1000, 0, 0, bad))
+        assert e.value.code == P.PR_EINVAL
+
+
+def test_visibility_storage_follows_the_lookup(P):
+    """Nearest-sample FP32 plans with tiles <= 16 and D <= 2047 keep 8 bytes
+    per visibility (tap word, w) instead of the 12-byte (u, v, w) triple; every
+    other plan keeps the triples (interp 2 asks for them explicitly)."""
+    M = 100000
+    size = lambda prec=0, tile=0, interp=0, D=2000: P.pr_phi_plan_sizes(
+        P.pr_phi_desc(256, 2, 4, D, M, prec, tile, interp))[0]
+    words, triples = size(), size(interp=2)
+    assert triples - words == pytest.approx(4 * M, abs=4096)
+    assert size(tile=8) < size(tile=8, interp=2)
+    assert size(tile=32) - size(tile=32, interp=2) == 0           # tile 32: triples
+    assert size(interp=1) == size(interp=2)                       # first order: triples
+    assert size(D=2048) - size(D=2048, interp=2) == 0             # 12-bit sample field
+    assert size(D=2047) < size(D=2047, interp=2)
+    assert size(prec=1) == size(prec=1, interp=2)                 # FP64: triples
 
 
 def test_fista_argument_checks(P):
@@ -155,7 +176,7 @@ def test_largest_visibility_count_is_accepted(P):
     offset stay below 2^31, and products with positions are 64-bit."""
     big = (1 << 31) - (1 << 20)
     pb, sb = P.pr_phi_plan_sizes(P.pr_phi_desc(2048, 2, 4, 2000, big, 0, 0))
-    assert pb >= 16 * big
+    assert pb >= 12 * big   # stored taps (4 B), w (4 B), permutation (4 B) per visibility
     L = P.lib()
     p2, s2 = C.c_size_t(), C.c_size_t()
     assert L.pr_balls_sizes(big, 4, C.byref(p2), C.byref(s2)) == P.PR_OK

@@ -158,3 +158,39 @@ def test_phi_parity_at_the_single_operator_size(P, J):
     x_gpu = plan.adjoint(to_dev(y_ref, torch.complex64)).cpu().numpy()
     x_ref = ms.phi_adjoint(y_ref[np.argsort(perm)], uv64, None, spec)
     assert rel_l2(x_gpu, x_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("n,M,J,tile,weights", [
+    (64, 12345, 4, 16, True),
+    (64, 12345, 4, 8, False),
+    (32, 3001, 6, 8, True),       # J > 4: the J-lane gridding kernel
+    (32, 999, 2, 16, False),
+    (32, 2048, 8, 8, True),
+    (128, 200000, 4, 16, True),   # multi-chunk walk items
+])
+def test_stored_taps_equal_recomputed_taps(P, n, M, J, tile, weights):
+    """FP32 plans store each visibility's nearest-sample taps (interp 0); the
+    same plan with interp 2 recomputes them from (u, v) at every launch. Both
+    pick the same samples, so Phi, Phi^dagger and the fused ADMM stages agree
+    bit for bit."""
+    say(f"stored vs recomputed taps n={n} M={M} J={J} tile={tile} w={weights}")
+    x, uv, w, spec = problem(n, M, J, 2000, seed=7 * n + M + J, prec="f32", weights=weights)
+    uv_d = torch.as_tensor(uv).to(DEV)
+    w_d = None if w is None else torch.as_tensor(w).to(DEV)
+    a = P.PhiPlan(n, uv_d, w_d, J=J, D=2000, tile=tile, interp=0)
+    b = P.PhiPlan(n, uv_d, w_d, J=J, D=2000, tile=tile, interp=2)
+    assert a.persistent.numel() < b.persistent.numel()     # (tap word, w) pairs vs (u, v, w)
+    assert torch.equal(a.perm(), b.perm())
+    xd = to_dev(x, torch.float32)
+    ya, yb = a.apply(xd), b.apply(xd)
+    assert torch.equal(ya, yb)
+    rng = np.random.default_rng(M + 1)
+    yy = to_dev(rng.standard_normal(M) + 1j * rng.standard_normal(M), torch.complex64)
+    assert torch.equal(a.adjoint(yy), b.adjoint(yy))
+    # the fused ADMM degridding epilogue and gridding prologue
+    psi = P.PsiPlan(n, 3, 0x1FF, P.PR_F32, DEV)
+    prm = P.admm_params(0.5 * float(torch.linalg.vector_norm(ya).item()), 1e-3, iters=3, op_norm=1.0)
+    xa, ra = P.admm_solve(a, psi, ya, prm)
+    xb, rb = P.admm_solve(b, psi, ya, prm)
+    assert torch.equal(xa, xb)
+    assert ra.resid_norm == rb.resid_norm and ra.l1_norm == rb.l1_norm
