@@ -47,6 +47,22 @@ __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size
 // plan with the same arithmetic).
 constexpr int kLkNearest = 0, kLkLinear = 1, kLkWords = 2;
 
+// Complex zero written as one 64-bit pattern for FP32 (a single 64-bit move
+// per accumulator instead of two 32-bit ones).
+template <typename C>
+__device__ __forceinline__ C zero_cx() {
+  if constexpr (sizeof(C) == 8) return __builtin_bit_cast(C, 0.0);
+  else return cmk<C>(0.0, 0.0);
+}
+
+// Element at a 32-bit byte offset from a (typically block-uniform) base: the
+// address is formed as base + zero-extended offset, one VALU add at most.
+template <typename T>
+__device__ __forceinline__ T* byte_at(T* base, uint32_t boff) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + boff);
+}
+
 // Taps of one visibility and its base cell (lu, lv) relative to tile
 // (tu, tv). TW: x holds the tap word's bits, y is unused; else x, y = u, v.
 template <bool TW, typename R>
@@ -665,7 +681,9 @@ struct WalkPrefetch {
 // whole sum in its side slot after the walk; the owner then adds, in segment
 // order, the side slots of the middle segments and the final part already in
 // the moments, and stores the total.
-template <typename R, int J, int MODE, bool TAB_LDS, int LK>
+// TS: the tile side when fixed at compile time (16 for the stored-tap plans:
+// moment and patch offsets become immediates), else 0 (read from the args).
+template <typename R, int J, int MODE, bool TAB_LDS, int LK, int TS>
 __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
   constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
@@ -674,7 +692,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   constexpr int WC = WalkChunk<R>::value;
   constexpr int kSegStride = kThreads / WC;
   extern __shared__ char smem_raw[];
-  const WalkLds<R, J> lay(a.T, a.tlen, TAB_LDS);
+  const WalkLds<R, J> lay(TS ? TS : a.T, a.tlen, TAB_LDS);
   C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
   // staged position: (u, v) and the weighted value side by side (one 16-byte
   // LDS access in FP32)
@@ -683,12 +701,11 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   C* side = reinterpret_cast<C*>(smem_raw + lay.stage);          // after the walk
   int* fcell = reinterpret_cast<int*>(smem_raw + lay.fcell);
   int* lcell = reinterpret_cast<int*>(smem_raw + lay.lcell);
-  int* helper = fcell;            // after the middles are known: helper assignments
   unsigned long long* nonmid = reinterpret_cast<unsigned long long*>(smem_raw + lay.masks);   // per wave
   unsigned long long* helpmask = nonmid + kThreads / 64;                                       // per wave
   const int tid = threadIdx.x;
   const R* tab = a.table;
-  const int T = a.T, P = a.P, K = a.K;
+  const int T = TS ? TS : a.T, P = TS ? TS + J - 1 : a.P, K = a.K;
   const int TT = T * T;
   R kappa_ball = 1;
   if (MODE == 1) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
@@ -700,22 +717,32 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   // Every slot loads (a slot past its segment reads the item's first
   // position, unused): no branches around the loads, so the loaded registers
   // are not moved and nothing waits for them before the commit.
+  // Positions are addressed from the item's first visibility (a block-uniform
+  // base) with 32-bit item-relative offsets (items hold fewer than 2^20).
   auto issue = [&](const int4& it, int L, int q0) {
     pf.ok = 0u;
+    const int n = it.z - it.y;
+    const int64_t b0 = it.y;
+    const C* vi = (MODE == 0 ? a.y_in : a.t_in) + b0;
 #pragma unroll
     for (int r = 0; r < WC; ++r) {
       const int q = q0 + lane_q;
-      const int64_t pos = static_cast<int64_t>(it.y) + (lane_t + r * kSegStride) * L + q;
-      const bool ok = q < L && pos < it.z;
+      const int o = (lane_t + r * kSegStride) * L + q;
+      const bool ok = q < L && o < n;
       pf.ok |= static_cast<unsigned>(ok) << r;
-      const int64_t pc = ok ? pos : static_cast<int64_t>(it.y);
-      vis_load<TW>(a.uv, pc, pf.uvw[r].u, pf.uvw[r].v, pf.uvw[r].w);
-      if (MODE == 0) {
-        pf.val[r] = a.y_in[pc];
+      const uint32_t oc = ok ? static_cast<uint32_t>(o) : 0u;
+      if constexpr (TW) {
+        const uint2 w2 = *byte_at(reinterpret_cast<const uint2*>(a.uv) + b0, oc * 8u);
+        pf.uvw[r].u = __uint_as_float(w2.x);
+        pf.uvw[r].v = R(0);
+        pf.uvw[r].w = __uint_as_float(w2.y);
       } else {
-        pf.val[r] = a.t_in[pc];
-        pf.s[MODE == 1 ? r : 0] = a.s_io[pc];
-        if (a.sec) pf.sec[MODE == 1 ? r : 0] = a.sec[pc];
+        vis_load<TW>(a.uv, b0 + oc, pf.uvw[r].u, pf.uvw[r].v, pf.uvw[r].w);
+      }
+      pf.val[r] = *byte_at(vi, oc * static_cast<uint32_t>(sizeof(C)));
+      if (MODE == 1) {
+        pf.s[MODE == 1 ? r : 0] = *byte_at(a.s_io + b0, oc * static_cast<uint32_t>(sizeof(C)));
+        if (a.sec) pf.sec[MODE == 1 ? r : 0] = a.sec[b0 + oc];
       }
     }
   };
@@ -744,7 +771,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       const C uvr = cmk<C>(pf.uvw[r].u, pf.uvw[r].v);
       const C wv = cmk<C>(val.x * ws, val.y * ws);
       if (ok) {
-        if (MODE == 1) a.s_io[static_cast<int64_t>(it.y) + (lane_t + r * kSegStride) * L + q0 + lane_q] = sn;
+        if (MODE == 1) {
+          const uint32_t o = static_cast<uint32_t>((lane_t + r * kSegStride) * L + q0 + lane_q);
+          *byte_at(a.s_io + static_cast<int64_t>(it.y), o * static_cast<uint32_t>(sizeof(C))) = sn;
+        }
         const int slot = lane_q * kStagePitch + lane_t + r * kSegStride;
         st[slot] = Staged{uvr, wv};
       }
@@ -791,10 +821,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     // chunk (or before the loop)
     commit(it, L, 0);
 
-    R ar[JJ], ai[JJ];
+    C acc[JJ];
     int first = -1, cur = -1, nruns = 0;
 #pragma unroll
-    for (int e = 0; e < JJ; ++e) ar[e] = ai[e] = R(0);
+    for (int e = 0; e < JJ; ++e) acc[e] = zero_cx<C>();
     for (int q0 = 0; q0 < L; q0 += WC) {
       const bool more = q0 + WC < L;
       // Prefetch the next chunk, else the next item's first chunk, into
@@ -805,45 +835,63 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       issue(more || !has_next ? it : itn, more || !has_next ? L : Ln, more ? q0 + WC : 0);
       __syncthreads();   // the chunk is staged
       const int qn = min(WC, segn - q0);
-      for (int i = 0; i < qn; ++i) {
-        const Staged sp = st[i * kStagePitch + tid];
-        const C uv = sp.uv;
-        C val = sp.val;
+      // One staged position: its weighted value, base cell and tap weights.
+      // Two register sets alternate (software pipeline): the LDS reads of the
+      // next position (staged inputs, then table samples) are in flight while
+      // the current one is accumulated. The index is clamped to the last valid
+      // position, so every read is of a staged entry.
+      struct Pos { C val; int c; R wu[J], wv[J]; };
+      auto fetch = [&](int i, Pos& q) {
+        const Staged sp = st[min(i, qn - 1) * kStagePitch + tid];
+        q.val = sp.val;
         AxisTaps xu, xv;
         int lu, lv;
-        vis_taps<TW>(uv.x, uv.y, a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
+        vis_taps<TW>(sp.uv.x, sp.uv.y, a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
         if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
           // cannot happen for a plan's own sorted baselines: keep LDS indices in range, poison the value
           lu = lv = 0;
-          val = cmk<C>(R(NAN), R(NAN));
+          q.val = cmk<C>(R(NAN), R(NAN));
         }
-        const int c = lv * T + lu;
-        if (c != cur) {
+        q.c = lv * T + lu;
+        axis_weights<LIN, J>(tab, xv, a.D, a.tlen, q.wv);
+        axis_weights<LIN, J>(tab, xu, a.D, a.tlen, q.wu);
+      };
+      auto accumulate = [&](const Pos& q) {
+        if (q.c != cur) {
           if (nruns > 0) {
             // the run on cur ended inside this segment: its sum is final
             // unless it is the segment's first run and continues the previous
             // segment, in which case the owner adds it later
 #pragma unroll
-            for (int e = 0; e < JJ; ++e) mom[e * TT + cur] = cmk<C>(ar[e], ai[e]);
+            for (int e = 0; e < JJ; ++e) mom[e * TT + cur] = acc[e];
           } else {
-            first = c;
+            first = q.c;
           }
-          cur = c;
+          cur = q.c;
           ++nruns;
 #pragma unroll
-          for (int e = 0; e < JJ; ++e) ar[e] = ai[e] = R(0);
+          for (int e = 0; e < JJ; ++e) acc[e] = zero_cx<C>();
         }
-        R wv[J], wu[J];
-        axis_weights<LIN, J>(tab, xv, a.D, a.tlen, wv);
-        axis_weights<LIN, J>(tab, xu, a.D, a.tlen, wu);
 #pragma unroll
         for (int qq = 0; qq < J; ++qq) {
-          const R g = wu[qq];
-          const R yr = val.x * g, yi = val.y * g;
+          const R g = q.wu[qq];
+          const R yr = q.val.x * g, yi = q.val.y * g;
 #pragma unroll
           for (int b = 0; b < J; ++b) {
-            ar[qq * J + b] += wv[b] * yr;
-            ai[qq * J + b] += wv[b] * yi;
+            acc[qq * J + b].x += q.wv[b] * yr;
+            acc[qq * J + b].y += q.wv[b] * yi;
+          }
+        }
+      };
+      if (qn > 0) {
+        Pos pa, pb;
+        fetch(0, pa);
+        for (int i = 0; i < qn; i += 2) {
+          fetch(i + 1, pb);
+          accumulate(pa);
+          if (i + 1 < qn) {
+            fetch(i + 2, pa);
+            accumulate(pb);
           }
         }
       }
@@ -861,69 +909,91 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     const bool middle = nruns == 1 && tid > 0 && lcell[tid - 1] == first;
     if (middle) {
 #pragma unroll
-      for (int e = 0; e < JJ; ++e) side[e * kThreads + tid] = cmk<C>(ar[e], ai[e]);
+      for (int e = 0; e < JJ; ++e) side[e * kThreads + tid] = acc[e];
     }
-    helper[tid] = -1;               // the cell lists are not read again
     {
       const unsigned long long bal = __ballot(!middle);
       if ((tid & 63) == 0) nonmid[tid >> 6] = bal;
     }
     __syncthreads();   // side slots and the non-middle masks written
-    // owner of the last run: its middle segments are [tid + 1, jend), jend the
-    // next segment that is not a middle one; a final segment, if any, has
-    // already stored its part in the moments of cur
+    // A run over several segments: its owner (a non-middle segment whose last
+    // run it is) and the middle segments [owner + 1, jend), jend the next
+    // segment that is not a middle one; a final segment, if any, has already
+    // stored its part in the moments of cur. Owner and middles find both ends
+    // from the per-wave masks in constant time.
     const bool owner = nruns > 0 && !middle;
-    int jend = tid + 1;
-    if (owner) {
-      const int w = tid >> 6, lane = tid & 63;
-      unsigned long long m = lane == 63 ? 0ull : (nonmid[w] & (~0ull << (lane + 1)));
-      int ww = w;
+    const int wv_ = tid >> 6, lane = tid & 63;
+    int base = tid, jend = tid + 1;
+    if (owner || middle) {
+      unsigned long long m = lane == 63 ? 0ull : (nonmid[wv_] & (~0ull << (lane + 1)));
+      int ww = wv_;
       while (m == 0ull && ww + 1 < kThreads / 64) m = nonmid[++ww];
       jend = m ? ww * 64 + __builtin_ctzll(m) : kThreads;
     }
-    // long runs: JJ middle threads each sum one moment over the run's middle
-    // segments (in segment order) for the owner
-    const bool helped = owner && jend - tid - 1 >= JJ;
-    if (helped) {
-      for (int e = 0; e < JJ; ++e) helper[tid + 1 + e] = (tid << 9) | jend;
+    if (middle) {
+      // thread 0 is never a middle, so a non-middle segment below exists
+      unsigned long long m = nonmid[wv_] & ((1ull << lane) - 1ull);
+      int ww = wv_;
+      while (m == 0ull && ww > 0) m = nonmid[--ww];
+      base = ww * 64 + 63 - __builtin_clzll(m);
     }
+    // Long runs (at least JJ middles): the middles themselves sum the parked
+    // moments in two fixed-order levels. The nm middles split into
+    // G = nm / JJ contiguous groups; middle k takes moment k mod JJ of group
+    // k / JJ and leaves the group's sum in the group's first slot; then middle
+    // e (< JJ) adds the G group sums of moment e in order into the first
+    // middle's slot, which the owner reads.
+    const int nm = jend - base - 1;
+    const bool helped = owner && nm >= JJ;
+    const bool helping = middle && nm >= JJ;
     {
       const unsigned long long bal = __ballot(helped);
       if ((tid & 63) == 0) helpmask[tid >> 6] = bal;
     }
-    __syncthreads();   // helper assignments and the per-wave flags written
+    __syncthreads();   // the per-wave flags written
     unsigned long long anyhelp = 0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) anyhelp |= helpmask[w];
     if (anyhelp) {
-      const int hv = helper[tid];
-      if (hv >= 0) {
-        const int o = hv >> 9, je = hv & 511, e = tid - o - 1;
+      const int k = tid - base - 1, G = nm / JJ;
+      if (helping && k / JJ < G) {
+        const int e = k % JJ, g = k / JJ;
+        const int lo = base + 1 + (g * nm) / G, hi = base + 1 + ((g + 1) * nm) / G;
         R sr = 0, si = 0;
-        for (int j = o + 1; j < je; ++j) {
+        for (int j = lo; j < hi; ++j) {
           const C d = side[e * kThreads + j];
           sr += d.x;
           si += d.y;
         }
-        side[e * kThreads + o + 1] = cmk<C>(sr, si);
+        side[e * kThreads + lo] = cmk<C>(sr, si);
       }
-      __syncthreads();   // the helpers' totals are in the first middle slot of each run
+      __syncthreads();   // every group sum written
+      if (helping && k < JJ) {
+        R sr = 0, si = 0;
+        for (int g = 0; g < G; ++g) {
+          const C d = side[k * kThreads + base + 1 + (g * nm) / G];
+          sr += d.x;
+          si += d.y;
+        }
+        side[k * kThreads + base + 1] = cmk<C>(sr, si);
+      }
+      __syncthreads();   // the run totals are in the first middle slot of each run
     }
     if (owner) {
       if (helped) {
 #pragma unroll
         for (int e = 0; e < JJ; ++e) {
           const C d = side[e * kThreads + tid + 1];
-          ar[e] += d.x;
-          ai[e] += d.y;
+          acc[e].x += d.x;
+          acc[e].y += d.y;
         }
       } else {
         for (int j = tid + 1; j < jend; ++j) {
 #pragma unroll
           for (int e = 0; e < JJ; ++e) {
             const C d = side[e * kThreads + j];
-            ar[e] += d.x;
-            ai[e] += d.y;
+            acc[e].x += d.x;
+            acc[e].y += d.y;
           }
         }
       }
@@ -931,7 +1001,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       for (int e = 0; e < JJ; ++e) {
         C* m = &mom[e * TT + cur];
         const C fin = *m;                // final segment's part, or zero
-        *m = cmk<C>(ar[e] + fin.x, ai[e] + fin.y);
+        *m = cmk<C>(acc[e].x + fin.x, acc[e].y + fin.y);
       }
     }
     __syncthreads();
@@ -1144,12 +1214,20 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
     const bool tl = with.total <= kLdsSoft || (without.total > kLdsSoft && with.total <= kLdsHard);
     const size_t bytes = tl ? with.total : without.total;
     if (bytes <= kLdsHard) {
-      if (tl) {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LK>, bytes));
-        grid_walk_kernel<R, J, MODE, true, LK><<<G, kThreads, bytes, s>>>(a);
+      if (LK == kLkWords && a.T == 16) {
+        if (tl) {
+          PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 16>, bytes));
+          grid_walk_kernel<R, J, MODE, true, LK, 16><<<G, kThreads, bytes, s>>>(a);
+        } else {
+          PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 16>, bytes));
+          grid_walk_kernel<R, J, MODE, false, LK, 16><<<G, kThreads, bytes, s>>>(a);
+        }
+      } else if (tl) {
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 0>, bytes));
+        grid_walk_kernel<R, J, MODE, true, LK, 0><<<G, kThreads, bytes, s>>>(a);
       } else {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LK>, bytes));
-        grid_walk_kernel<R, J, MODE, false, LK><<<G, kThreads, bytes, s>>>(a);
+        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 0>, bytes));
+        grid_walk_kernel<R, J, MODE, false, LK, 0><<<G, kThreads, bytes, s>>>(a);
       }
       walked = true;
     }
@@ -1186,8 +1264,12 @@ int setup_mode() {
   PR_TRY((allow_lds(degrid_kernel<R, J, MODE, true, LK>, kLdsHard)));
   PR_TRY((allow_lds(degrid_kernel<R, J, MODE, false, LK>, kLdsHard)));
   if constexpr (J <= 4) {
-    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LK>, kLdsHard)));
-    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LK>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 0>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 0>, kLdsHard)));
+    if constexpr (LK == kLkWords) {
+      PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 16>, kLdsHard)));
+      PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 16>, kLdsHard)));
+    }
   }
   PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, true, LK>, kLdsHard)));
   PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, false, LK>, kLdsHard)));
