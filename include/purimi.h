@@ -220,6 +220,19 @@ int pr_proj_l2ball(const void* in, const void* center, void* out, int64_t len,
                    int32_t prec, double eps, void* scratch, double* dist,
                    void* stream);
 
+/* pr_proj_l2ball without the scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). The FP64 partial sums live in a static
+ * device array of the library (16 KB per GPU, held until the process ends;
+ * its address is looked up once per device on the first call there). It
+ * allocates nothing; every length the library accepts fits (the scratch does
+ * not grow with len). Calls that overlap on one GPU (other streams or host
+ * threads) share the array and race: serialise them. Same arguments, result
+ * bits and errors as pr_proj_l2ball; PR_EUNSUPPORTED for device ids >= 64. */
+int pr_proj_l2ball_noalloc(const void* in, const void* center, void* out,
+                           int64_t len, int32_t prec, double eps, double* dist,
+                           void* stream);
+
 /* ------------------------------------------------------------------------
  * Dual Forward-Backward ADMM (Algorithm 1) for
  *   min ||Psi^dagger x||_1 + iota_{R+}(x) + iota_{||Phi x - y|| <= eps}

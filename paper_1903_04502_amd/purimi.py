@@ -101,6 +101,7 @@ _SIGS = {
     "pr_prox_l1": (C.c_int, [_VP, _VP, _I64, _I32, _I32, _D, _VP]),
     "pr_proj_l2ball_scratch_bytes": (_SZ, [_I64]),
     "pr_proj_l2ball": (C.c_int, [_VP, _VP, _VP, _I64, _I32, _D, _VP, C.POINTER(_D), _VP]),
+    "pr_proj_l2ball_noalloc": (C.c_int, [_VP, _VP, _VP, _I64, _I32, _D, C.POINTER(_D), _VP]),
     "pr_admm_workspace_size": (C.c_int, [_VP, _VP, C.POINTER(_SZ)]),
     "pr_admm_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pr_admm_params), _VP, _VP,
                                 C.POINTER(pr_admm_report), _VP]),
@@ -326,6 +327,15 @@ def pr_proj_l2ball(inp, center, out, eps, scratch, want_dist=False, stream=None)
     _check(lib().pr_proj_l2ball(_ptr(inp), _ptr(center), _ptr(out), inp.numel(), _prec_of(inp.dtype), float(eps),
                                 _ptr(scratch), C.byref(d) if want_dist else None,
                                 stream if stream is not None else _stream()))
+    return d.value if want_dist else None
+
+
+def pr_proj_l2ball_noalloc(inp, center, out, eps, want_dist=False, stream=None):
+    """pr_proj_l2ball with the library's static scratch (allocates nothing)."""
+    d = _D()
+    _check(lib().pr_proj_l2ball_noalloc(_ptr(inp), _ptr(center), _ptr(out), inp.numel(), _prec_of(inp.dtype),
+                                        float(eps), C.byref(d) if want_dist else None,
+                                        stream if stream is not None else _stream()))
     return d.value if want_dist else None
 
 
