@@ -610,6 +610,16 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(GwAdjArgs<R> a) {
 // Positions per thread and staged chunk: FP32 8, FP64 4 (the prefetch
 // registers hold one chunk).
 template <typename R> struct WalkChunk { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
+// Positions per segment fetched by one prefetch: two staged chunks, so that
+// the 16-lane groups that load one segment read whole 128-byte lines of each
+// visibility array (8-byte values in FP32: 16 positions; FP64: 8 positions of
+// 16-byte values). Loading one chunk (half a line) at a time let the L2 evict
+// a line between its two halves: the walk fetched 2.3 times its bytes.
+// Only where the registers allow it (two waves per SIMD): FP32 stored-tap
+// walks without section ids; the others prefetch one chunk at a time.
+template <typename R, int MODE, int LK> struct WalkPrefetchLen {
+  static constexpr int value = (sizeof(R) == 4 && LK == kLkWords && MODE != 3 ? 2 : 1) * WalkChunk<R>::value;
+};
 // Row pitch of the staged chunk, in entries: one more than the thread count,
 // so the WC lanes that store the WC positions of one segment hit different
 // banks (a pitch of exactly kThreads puts them on one bank).
@@ -644,22 +654,23 @@ struct WalkLds {
   }
 };
 
-// Registers holding one chunk's inputs between the loads and the LDS stores,
-// so that the loads of the next chunk (or of the next item's first chunk) are
-// in flight while the current chunk is walked. Slot r of thread tid is
-// position (tid mod WC) of segment tid / WC + r * kThreads / WC.
-template <typename R, int MODE>
+// Registers holding two chunks' inputs between the loads and the LDS stores,
+// so that the loads of the next pair of chunks (or of the next item's first
+// pair) are in flight while a chunk is walked. Slot r of thread tid is
+// position (tid mod PF) of segment tid / PF + r * kThreads / PF; the lanes
+// with (tid mod PF) < WC stage the pair's first chunk, the others its second.
+template <typename R, int MODE, int LK>
 struct WalkPrefetch {
   using C = cx_t<R>;
-  static constexpr int WC = WalkChunk<R>::value;
+  static constexpr int WC = WalkPrefetchLen<R, MODE, LK>::value;
   // one (u, v, w) triple per slot, loaded as one piece and consumed in place
   // (a separate w register makes the compiler copy it out of the load's
   // destination, which waits for the load while the next ones are issued)
   struct Uvw { R u, v, w; };
   Uvw uvw[WC];
-  C val[WC];                      // MODE 0: y; MODE 1: t = v + s - y
-  C s[MODE == 1 ? WC : 1];        // MODE 1: multiplier before the update
-  int sec[MODE == 1 ? WC : 1];    // MODE 1 with local balls: section of the position
+  C val[WC];                      // MODE 0: y; MODE 1, 3: t = v + s - y
+  C s[MODE != 0 ? WC : 1];        // MODE 1, 3: multiplier before the update
+  int sec[MODE == 3 ? WC : 1];    // MODE 3 (local balls): section of the position
   unsigned ok;                    // bit r: slot r holds a position of the item
 };
 
@@ -687,10 +698,14 @@ template <typename R, int J, int MODE, bool TAB_LDS, int LK, int TS>
 __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
   constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
+  // MODE 0: plain gridding; 1: fused ADMM prologue (global ball); 3: the same
+  // with each visibility's section ball (local balls; section ids prefetched)
+  constexpr bool ADMM = MODE != 0, SEC = MODE == 3;
   const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   constexpr int JJ = J * J;
   constexpr int WC = WalkChunk<R>::value;
-  constexpr int kSegStride = kThreads / WC;
+  constexpr int PF = WalkPrefetchLen<R, MODE, LK>::value;
+  constexpr int kSegStride = kThreads / PF;
   extern __shared__ char smem_raw[];
   const WalkLds<R, J> lay(TS ? TS : a.T, a.tlen, TAB_LDS);
   C* mom = reinterpret_cast<C*>(smem_raw + lay.mom);
@@ -708,12 +723,13 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   const int T = TS ? TS : a.T, P = TS ? TS + J - 1 : a.P, K = a.K;
   const int TT = T * T;
   R kappa_ball = 1;
-  if (MODE == 1) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
-  const int lane_q = tid & (WC - 1);      // position within the chunk this thread loads
-  const int lane_t = tid / WC;            // first segment this thread loads for
+  if (ADMM) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
+  const int lane_q = tid & (PF - 1);      // position within the pair this thread loads
+  const int lane_t = tid / PF;            // first segment this thread loads for
+  const int lane_h = lane_q / WC;         // the chunk of the pair this thread stages
 
-  WalkPrefetch<R, MODE> pf;
-  // issue the loads of positions q0 .. q0 + WC - 1 of every segment of item it
+  WalkPrefetch<R, MODE, LK> pf;
+  // issue the loads of positions q0 .. q0 + PF - 1 of every segment of item it
   // Every slot loads (a slot past its segment reads the item's first
   // position, unused): no branches around the loads, so the loaded registers
   // are not moved and nothing waits for them before the commit.
@@ -725,7 +741,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     const int64_t b0 = it.y;
     const C* vi = (MODE == 0 ? a.y_in : a.t_in) + b0;
 #pragma unroll
-    for (int r = 0; r < WC; ++r) {
+    for (int r = 0; r < PF; ++r) {
       const int q = q0 + lane_q;
       const int o = (lane_t + r * kSegStride) * L + q;
       const bool ok = q < L && o < n;
@@ -740,20 +756,18 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         vis_load<TW>(a.uv, b0 + oc, pf.uvw[r].u, pf.uvw[r].v, pf.uvw[r].w);
       }
       pf.val[r] = *byte_at(vi, oc * static_cast<uint32_t>(sizeof(C)));
-      if (MODE == 1) {
-        pf.s[MODE == 1 ? r : 0] = *byte_at(a.s_io + b0, oc * static_cast<uint32_t>(sizeof(C)));
-        if (a.sec) pf.sec[MODE == 1 ? r : 0] = a.sec[b0 + oc];
-      }
+      if (ADMM) pf.s[ADMM ? r : 0] = *byte_at(a.s_io + b0, oc * static_cast<uint32_t>(sizeof(C)));
+      if (SEC) pf.sec[SEC ? r : 0] = a.sec[b0 + oc];
     }
   };
-  // store the prefetched chunk lane-transposed (ADMM prologue applied here).
-  // The values are formed for every slot and only the stores are predicated,
-  // so every prefetched register is consumed on every path (no conservative
-  // waits on them later).
-  auto commit = [&](const int4& it, int L, int q0) {
+  // store chunk h of the prefetched pair (positions q0 + h WC ..) lane-
+  // transposed (ADMM prologue applied here). The values are formed for every
+  // slot and only the stores are predicated, so every prefetched register is
+  // consumed on every path (no conservative waits on them later).
+  auto commit = [&](const int4& it, int L, int q0, int h) {
 #pragma unroll
-    for (int r = 0; r < WC; ++r) {
-      const bool ok = (pf.ok >> r) & 1u;
+    for (int r = 0; r < PF; ++r) {
+      const bool ok = ((pf.ok >> r) & 1u) && lane_h == h;
       C val;
       C sn = cmk<C>(R(0), R(0));
       if (MODE == 0) {
@@ -761,8 +775,8 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       } else {
         // ball projection and multiplier update of Algorithm 1 from t = v + s - y:
         // r = y + kappa t, s' = s + varrho (v - r), q = vr_coef (v - r) + s'
-        const C tt = pf.val[r], sk = pf.s[MODE == 1 ? r : 0];
-        const R omk = R(1) - (a.kappa_sec ? static_cast<R>(a.kappa_sec[pf.sec[MODE == 1 ? r : 0]]) : kappa_ball);
+        const C tt = pf.val[r], sk = pf.s[ADMM ? r : 0];
+        const R omk = R(1) - (SEC ? static_cast<R>(a.kappa_sec[pf.sec[SEC ? r : 0]]) : kappa_ball);
         const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);   // v - r
         sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
         val = cmk<C>(a.vr_coef * vr.x + sn.x, a.vr_coef * vr.y + sn.y);
@@ -771,11 +785,11 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       const C uvr = cmk<C>(pf.uvw[r].u, pf.uvw[r].v);
       const C wv = cmk<C>(val.x * ws, val.y * ws);
       if (ok) {
-        if (MODE == 1) {
+        if (ADMM) {
           const uint32_t o = static_cast<uint32_t>((lane_t + r * kSegStride) * L + q0 + lane_q);
           *byte_at(a.s_io + static_cast<int64_t>(it.y), o * static_cast<uint32_t>(sizeof(C))) = sn;
         }
-        const int slot = lane_q * kStagePitch + lane_t + r * kSegStride;
+        const int slot = (lane_q - h * WC) * kStagePitch + lane_t + r * kSegStride;
         st[slot] = Staged{uvr, wv};
       }
     }
@@ -817,47 +831,30 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       for (int i = tid; i < lay.borrow; i += kThreads) t[i] = a.table[i];
     }
 
-    // the item's first chunk was prefetched during the previous item's last
-    // chunk (or before the loop)
-    commit(it, L, 0);
+    // the item's first pair was prefetched during the previous item's last
+    // pair (or before the loop)
+    commit(it, L, 0, 0);
 
     C acc[JJ];
     int first = -1, cur = -1, nruns = 0;
 #pragma unroll
     for (int e = 0; e < JJ; ++e) acc[e] = zero_cx<C>();
-    for (int q0 = 0; q0 < L; q0 += WC) {
-      const bool more = q0 + WC < L;
-      // Prefetch the next chunk, else the next item's first chunk, into
-      // registers; they are stored after this chunk's walk, in the same
-      // iteration, so no prefetched register is carried around the loop (a
-      // carried one makes the compiler copy it, waiting for its load). With
-      // nothing left the slots reload this item's first positions, unused.
-      issue(more || !has_next ? it : itn, more || !has_next ? L : Ln, more ? q0 + WC : 0);
-      __syncthreads();   // the chunk is staged
+    // walk the staged chunk at positions q0 .. q0 + WC - 1 of this thread's segment
+    auto walk = [&](int q0) {
       const int qn = min(WC, segn - q0);
-      // One staged position: its weighted value, base cell and tap weights.
-      // Two register sets alternate (software pipeline): the LDS reads of the
-      // next position (staged inputs, then table samples) are in flight while
-      // the current one is accumulated. The index is clamped to the last valid
-      // position, so every read is of a staged entry.
-      struct Pos { C val; int c; R wu[J], wv[J]; };
-      auto fetch = [&](int i, Pos& q) {
-        const Staged sp = st[min(i, qn - 1) * kStagePitch + tid];
-        q.val = sp.val;
+      for (int i = 0; i < qn; ++i) {
+        const Staged sp = st[i * kStagePitch + tid];
+        C val = sp.val;
         AxisTaps xu, xv;
         int lu, lv;
         vis_taps<TW>(sp.uv.x, sp.uv.y, a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
         if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
           // cannot happen for a plan's own sorted baselines: keep LDS indices in range, poison the value
           lu = lv = 0;
-          q.val = cmk<C>(R(NAN), R(NAN));
+          val = cmk<C>(R(NAN), R(NAN));
         }
-        q.c = lv * T + lu;
-        axis_weights<LIN, J>(tab, xv, a.D, a.tlen, q.wv);
-        axis_weights<LIN, J>(tab, xu, a.D, a.tlen, q.wu);
-      };
-      auto accumulate = [&](const Pos& q) {
-        if (q.c != cur) {
+        const int c = lv * T + lu;
+        if (c != cur) {
           if (nruns > 0) {
             // the run on cur ended inside this segment: its sum is final
             // unless it is the segment's first run and continues the previous
@@ -865,39 +862,51 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 #pragma unroll
             for (int e = 0; e < JJ; ++e) mom[e * TT + cur] = acc[e];
           } else {
-            first = q.c;
+            first = c;
           }
-          cur = q.c;
+          cur = c;
           ++nruns;
 #pragma unroll
           for (int e = 0; e < JJ; ++e) acc[e] = zero_cx<C>();
         }
+        R wv[J], wu[J];
+        axis_weights<LIN, J>(tab, xv, a.D, a.tlen, wv);
+        axis_weights<LIN, J>(tab, xu, a.D, a.tlen, wu);
 #pragma unroll
         for (int qq = 0; qq < J; ++qq) {
-          const R g = q.wu[qq];
-          const R yr = q.val.x * g, yi = q.val.y * g;
+          const R g = wu[qq];
+          const R yr = val.x * g, yi = val.y * g;
 #pragma unroll
           for (int b = 0; b < J; ++b) {
-            acc[qq * J + b].x += q.wv[b] * yr;
-            acc[qq * J + b].y += q.wv[b] * yi;
-          }
-        }
-      };
-      if (qn > 0) {
-        Pos pa, pb;
-        fetch(0, pa);
-        for (int i = 0; i < qn; i += 2) {
-          fetch(i + 1, pb);
-          accumulate(pa);
-          if (i + 1 < qn) {
-            fetch(i + 2, pa);
-            accumulate(pb);
+            acc[qq * J + b].x += wv[b] * yr;
+            acc[qq * J + b].y += wv[b] * yi;
           }
         }
       }
-      if (more) {
-        __syncthreads();   // the chunk has been walked
-        commit(it, L, q0 + WC);
+    };
+    // Pairs of chunks: the pair's first chunk is staged; walk it, stage its
+    // second chunk from the registers, then prefetch the next pair (of this
+    // item, else the next item's first pair; with nothing left the slots
+    // reload this item's first positions, unused) while the second chunk is
+    // walked, and stage the next pair's first chunk. One prefetch call site,
+    // reached once per pair.
+    for (int p0 = 0; p0 < L; p0 += PF) {
+      const bool second = PF > WC && p0 + WC < L;   // the pair has a second chunk
+      const bool next = p0 + PF < L;           // this item has another pair
+      __syncthreads();   // the first chunk is staged
+      walk(p0);
+      if (second) {
+        __syncthreads();   // the first chunk has been walked
+        commit(it, L, p0, 1);
+      }
+      issue(next || !has_next ? it : itn, next || !has_next ? L : Ln, next ? p0 + PF : 0);
+      if (second) {
+        __syncthreads();   // the second chunk is staged
+        walk(p0 + WC);
+      }
+      if (next) {
+        __syncthreads();   // the second chunk has been walked
+        commit(it, L, p0 + PF, 0);
       }
     }
     if (TAB_LDS && lay.borrow) __syncthreads();   // every walk done with the table head
@@ -1200,6 +1209,35 @@ bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
   return false;
 }
 
+// Segment walk (J <= 4): table in LDS if that keeps two blocks per CU, or if
+// one block per CU is all that fits either way. Returns false if it does not
+// fit in LDS at all (the caller then uses the J-lane kernel).
+template <typename R, int J, int WMODE, int LK>
+int launch_walk(pr_phi_plan_t* p, GwAdjArgs<R>& a, hipStream_t s, int G, bool* walked) {
+  const WalkLds<R, J> with(a.T, a.tlen, true), without(a.T, a.tlen, false);
+  const bool tl = with.total <= kLdsSoft || (without.total > kLdsSoft && with.total <= kLdsHard);
+  const size_t bytes = tl ? with.total : without.total;
+  *walked = false;
+  if (bytes > kLdsHard) return PR_OK;
+  if (LK == kLkWords && a.T == 16) {
+    if (tl) {
+      PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, true, LK, 16>, bytes));
+      grid_walk_kernel<R, J, WMODE, true, LK, 16><<<G, kThreads, bytes, s>>>(a);
+    } else {
+      PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, false, LK, 16>, bytes));
+      grid_walk_kernel<R, J, WMODE, false, LK, 16><<<G, kThreads, bytes, s>>>(a);
+    }
+  } else if (tl) {
+    PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, true, LK, 0>, bytes));
+    grid_walk_kernel<R, J, WMODE, true, LK, 0><<<G, kThreads, bytes, s>>>(a);
+  } else {
+    PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, false, LK, 0>, bytes));
+    grid_walk_kernel<R, J, WMODE, false, LK, 0><<<G, kThreads, bytes, s>>>(a);
+  }
+  *walked = true;
+  return PR_OK;
+}
+
 template <typename R, int J, int MODE, int LK>
 int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) {
   using C = cx_t<R>;
@@ -1207,29 +1245,14 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
   const int G = grid_blocks(p);
   bool walked = false;
   if (!(parts & 1)) walked = true;   // patches not asked for
-  if constexpr (J <= 4) if (parts & 1) {
-    // segment walk: table in LDS if that keeps two blocks per CU, or if one
-    // block per CU is all that fits either way
-    const WalkLds<R, J> with(a.T, a.tlen, true), without(a.T, a.tlen, false);
-    const bool tl = with.total <= kLdsSoft || (without.total > kLdsSoft && with.total <= kLdsHard);
-    const size_t bytes = tl ? with.total : without.total;
-    if (bytes <= kLdsHard) {
-      if (LK == kLkWords && a.T == 16) {
-        if (tl) {
-          PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 16>, bytes));
-          grid_walk_kernel<R, J, MODE, true, LK, 16><<<G, kThreads, bytes, s>>>(a);
-        } else {
-          PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 16>, bytes));
-          grid_walk_kernel<R, J, MODE, false, LK, 16><<<G, kThreads, bytes, s>>>(a);
-        }
-      } else if (tl) {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 0>, bytes));
-        grid_walk_kernel<R, J, MODE, true, LK, 0><<<G, kThreads, bytes, s>>>(a);
+  if constexpr (J <= 4) {
+    if (parts & 1) {
+      // the ADMM prologue with section balls is its own walk instance (MODE 3)
+      if (MODE == 1 && a.sec) {
+        PR_TRY((launch_walk<R, J, MODE == 1 ? 3 : MODE, LK>(p, a, s, G, &walked)));
       } else {
-        PR_TRY(allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 0>, bytes));
-        grid_walk_kernel<R, J, MODE, false, LK, 0><<<G, kThreads, bytes, s>>>(a);
+        PR_TRY((launch_walk<R, J, MODE, LK>(p, a, s, G, &walked)));
       }
-      walked = true;
     }
   }
   if (!walked) {
@@ -1264,11 +1287,16 @@ int setup_mode() {
   PR_TRY((allow_lds(degrid_kernel<R, J, MODE, true, LK>, kLdsHard)));
   PR_TRY((allow_lds(degrid_kernel<R, J, MODE, false, LK>, kLdsHard)));
   if constexpr (J <= 4) {
-    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 0>, kLdsHard)));
-    PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 0>, kLdsHard)));
+    constexpr int WM[2] = {MODE, MODE == 1 ? 3 : MODE};
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], true, LK, 0>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], false, LK, 0>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], true, LK, 0>, kLdsHard)));
+    PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], false, LK, 0>, kLdsHard)));
     if constexpr (LK == kLkWords) {
-      PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, true, LK, 16>, kLdsHard)));
-      PR_TRY((allow_lds(grid_walk_kernel<R, J, MODE, false, LK, 16>, kLdsHard)));
+      PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], true, LK, 16>, kLdsHard)));
+      PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], false, LK, 16>, kLdsHard)));
+      PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], true, LK, 16>, kLdsHard)));
+      PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], false, LK, 16>, kLdsHard)));
     }
   }
   PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, true, LK>, kLdsHard)));
