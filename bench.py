@@ -133,6 +133,101 @@ def run_linear(P, dev, n, J, D, uv32, x_true, K_steps, W_steps, with_oracle):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_gw(task):
+    """Worker: the oracle's degridding of one chunk of visibilities."""
+    from oracle import measurement as ms
+    X, uv, spec = task
+    return ms.gw(X, uv, None, spec)
+
+
+def _cpu_gw_adjoint(task):
+    """Worker: the oracle's gridding of one chunk of visibilities (a partial grid)."""
+    from oracle import measurement as ms
+    y, uv, spec = task
+    return ms.gw_adjoint(y, uv, None, spec)
+
+
+def cpu_pair_parallel(x, uv64, spec, workers):
+    """The oracle's Phi and Phi^dagger with the visibility work split into
+    `workers` chunks on as many spawned processes (none of them touches the
+    GPU): S Z and F and their adjoints once in this process, the degridding and
+    gridding of each chunk in a worker, partial grids added in chunk order."""
+    import multiprocessing as mp
+    from oracle import measurement as ms
+    M = uv64.shape[0]
+    bounds = np.linspace(0, M, workers + 1).astype(np.int64)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_cpu_gw, [(np.zeros((spec.K, spec.K), complex), uv64[:8], spec)] * workers)   # start-up
+        t0 = time.perf_counter()
+        X = ms.szf(x, spec)
+        y = np.concatenate(pool.map(_cpu_gw, [(X, uv64[a:b], spec) for a, b in zip(bounds[:-1], bounds[1:])]))
+        t1 = time.perf_counter()
+        grids = pool.map(_cpu_gw_adjoint, [(y[a:b], uv64[a:b], spec) for a, b in zip(bounds[:-1], bounds[1:])])
+        g = grids[0]
+        for q in grids[1:]:
+            g = g + q
+        ms.szf_adjoint(g, spec).real
+        t2 = time.perf_counter()
+    return {"workers": workers, "phi_s": t1 - t0, "adj_s": t2 - t1, "pair_s": t2 - t0}
+
+
+def run_j6(P, dev, n, D, L, uv32, x_true, K_steps, W_steps, with_oracle):
+    """The same workload with the J = 6 kernel (the wider support the
+    benchmark configuration names), FP32: (Phi, Phi^dagger) pairs and one
+    ADMM iteration."""
+    import torch
+    plan = P.PhiPlan(n, torch.as_tensor(uv32).to(dev), None, J=6, D=D)
+    psi = P.PsiPlan(n, L, 0x1FF, P.PR_F32, dev)
+    x = torch.as_tensor(x_true, dtype=torch.float32, device=dev)
+    y = torch.empty(plan.M, dtype=torch.complex64, device=dev)
+    xg = torch.empty_like(x)
+    for _ in range(W_steps):
+        P.pr_phi_apply(plan.handle, x, y)
+        P.pr_phi_adjoint(plan.handle, y, xg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K_steps):
+        P.pr_phi_apply(plan.handle, x, y)
+        P.pr_phi_adjoint(plan.handle, y, xg)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / K_steps
+    op_norm = plan.norm(100)
+    gamma = 1e-3 * float(psi.adjoint(plan.adjoint(y) / op_norm).abs().max().item())
+    eps = 0.05 * float(torch.linalg.vector_norm(y).item()) / op_norm
+    ws = torch.empty(P.pr_admm_workspace_size(plan.handle, psi.handle), dtype=torch.uint8, device=dev)
+    xa = torch.zeros_like(x)
+    P.pr_admm_solve(plan.handle, psi.handle, y, P.admm_params(eps, gamma, iters=W_steps, op_norm=op_norm), xa, ws,
+                    want_report=False)
+    xa.zero_()
+    torch.cuda.synchronize()
+    e0.record()
+    P.pr_admm_solve(plan.handle, psi.handle, y, P.admm_params(eps, gamma, iters=K_steps, op_norm=op_norm), xa, ws,
+                    want_report=False)
+    e1.record()
+    torch.cuda.synchronize()
+    out = {"workload": "op-256sq-M1e6-J6", "J": 6, "phi_pair_ms": t, "vis_per_s": plan.M / (t * 1e-3),
+           "admm_iter_ms_fp32": e0.elapsed_time(e1) / K_steps, "tile": plan.desc.tile}
+    if with_oracle:
+        from oracle import measurement as ms
+        P.pr_phi_apply(plan.handle, x, y)
+        y_ref = ms.phi(x_true, uv32.astype(np.float64), None, ms.PhiSpec(n, 2 * n, 6, D))
+        perm = plan.perm().cpu().numpy()
+        out["phi_rel_err_vs_oracle"] = float(np.linalg.norm(y.cpu().numpy() - y_ref[perm]) / np.linalg.norm(y_ref))
+    return out
+
+
 def run_batch(P, dev, args):
     """64 channels of uneven n and M stepped together (tiles from the autotuner)."""
     import torch
@@ -180,18 +275,28 @@ def run_batch(P, dev, args):
     xo = [torch.empty_like(m["x_d"]) for m in members]
     stream = torch.cuda.current_stream(dev)
     K, Wm = args.steps, args.warmup
-    for _ in range(Wm):
-        P.pr_batch_phi_apply(b.handle, xs, ys)
-        P.pr_batch_phi_adjoint(b.handle, ys, xo)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(K):
-        P.pr_batch_phi_apply(b.handle, xs, ys)
-        P.pr_batch_phi_adjoint(b.handle, ys, xo)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_pair = e0.elapsed_time(e1) / K
+
+    def time_pairs():
+        for _ in range(Wm):
+            P.pr_batch_phi_apply(b.handle, xs, ys)
+            P.pr_batch_phi_adjoint(b.handle, ys, xo)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(K):
+            P.pr_batch_phi_apply(b.handle, xs, ys)
+            P.pr_batch_phi_adjoint(b.handle, ys, xo)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    t_pair_members = time_pairs()          # one launch sequence per member, over the streams
+    y_members = [v.clone() for v in ys]
+    x_members = [v.clone() for v in xo]
+    b.fuse(dev)                            # one launch per stage for all members
+    t_pair = time_pairs()
+    fused_bitwise = all(torch.equal(a_, c_) for a_, c_ in zip(ys, y_members)) and \
+        all(torch.equal(a_, c_) for a_, c_ in zip(xo, x_members))
     out = {}
     for use_graph in (True, False):
         b.step(Wm, use_graph=use_graph)
@@ -203,9 +308,19 @@ def run_batch(P, dev, args):
         out["graph" if use_graph else "streams"] = e0.elapsed_time(e1) / K
     rep = [b.report(m["slot"]) for m in members[:4]]
     sum_m = int(sum(m["M"] for m in members))
+    # algorithmic bytes of one batched (Phi, Phi^dagger): 40 B per visibility
+    # (u, v, w and y read or written by the degridding and by the gridding) plus
+    # the pruned transforms of each channel, 4n^2 + 16nK + 8K^2 each way
+    fft_b = sum(2 * (4 * m["n"] ** 2 + 16 * m["n"] * 2 * m["n"] + 8 * (2 * m["n"]) ** 2) for m in members)
+    pair_bytes = 40.0 * sum_m + fft_b
+    ach = pair_bytes / (t_pair * 1e-3) / 1e9
     return {"workload": "channels-64ch-n128..1024-M1e4..5e6-J4-sara3", "channels": len(members), "visibilities": sum_m,
             "tiles_from_autotuner": {str(k): v for k, v in sorted(tiles.items())},
             "phi_pair_ms": t_pair, "vis_per_s": sum_m / (t_pair * 1e-3),
+            "phi_pair_ms_per_member_launches": t_pair_members, "fused_bitwise_equal_to_per_member": fused_bitwise,
+            "roofline": {"bound": "hbm", "kernel": "fused batched (Phi, Phi^dagger), all launches", "achieved": ach,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_pair": pair_bytes},
             "admm_step_ms_graph": out["graph"], "admm_step_ms_streams": out["streams"],
             "admm_vis_per_s": sum_m / (out["graph"] * 1e-3),
             "max_rel_err_fp32_vs_fp64": max(errs64), "median_rel_err_fp32_vs_fp64": float(np.median(errs64)),
@@ -230,7 +345,7 @@ def serve_pool(n_small=24):
     return pool
 
 
-def run_serve(P, dev, args, prec):
+def run_serve(P, dev, args, prec, rate=None, nreq=None):
     """Poisson arrivals of imaging solves through the continuous-batching server."""
     import torch
     import workloads as W
@@ -249,9 +364,11 @@ def run_serve(P, dev, args, prec):
         y, _, eps = W.add_noise_torch(y_user, W.unit_complex_noise_torch(d["M"], gen, dev, y_user.dtype))
         data.append(dict(n=d["n"], M=d["M"], uv=uv_d, y=y, x=x_d, eps=eps))
     torch.cuda.synchronize()
+    rate = args.serve_rate if rate is None else rate
+    nreq = args.serve_requests if nreq is None else nreq
     rng = np.random.default_rng(1004)   # same arrivals and job mix for both precisions
-    total = args.serve_warmup + args.serve_requests
-    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, total))
+    total = args.serve_warmup + nreq
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, total))
     big = rng.uniform(size=total) < 0.05
     pick = np.where(big, len(data) - 2 + rng.integers(0, 2, total), rng.integers(0, len(data) - 2, total))
     arena = (48 << 30) if prec == P.PR_F32 else (96 << 30)
@@ -290,7 +407,7 @@ def run_serve(P, dev, args, prec):
     last = max(v[2] for v in timed) if timed else 0.0
     e = np.array([errs[j] for j in lat if lat[j][0] >= args.serve_warmup])
     nbig = int(big[args.serve_warmup:].sum())
-    return {"workload": "serving-poisson-channel-law+5pct-2048sq-M5e7-30iters", "rate_req_s": args.serve_rate,
+    return {"workload": "serving-poisson-channel-law+5pct-2048sq-M5e7-30iters", "rate_req_s": rate,
             "requests": len(timed), "warmup_requests": args.serve_warmup, "big_jobs": nbig,
             "solves_per_s": len(timed) / (last - first) if timed else 0.0,
             "p50_ms": float(np.percentile(l_ms, 50)) if timed else None,
@@ -300,16 +417,21 @@ def run_serve(P, dev, args, prec):
             "completed_all": done == total}
 
 
-def pmc_probe(P, dev):
-    """The kernels the counter passes read: 256^2 / 1e6 gridding and degridding, and a
+def pmc_probe(P, dev, workload="op256"):
+    """The kernels the counter passes read: the workload's gridding and
+    degridding (256^2 / 1e6 by default, or the 2048^2 / 5e8 share), and a
     plain 512 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate bytes."""
     import torch
     import workloads as W
-    wl = W.CONFIGS["op256"]
+    wl = W.CONFIGS[workload]
     rng = W.rng_for(wl.index)
     x = W.make_sky(wl, rng)
-    uv = W.make_uv(wl, rng)
-    plan = P.PhiPlan(wl.n, torch.as_tensor(uv).to(dev), None, J=wl.J, D=wl.D)
+    if workload == "share2048":
+        uv_d = W.uv_ring_core_torch(wl.M, W.torch_generator(wl.index, dev), dev)
+    else:
+        uv_d = torch.as_tensor(W.make_uv(wl, rng)).to(dev)
+    plan = P.PhiPlan(wl.n, uv_d, None, J=wl.J, D=wl.D)
+    del uv_d
     xd = torch.as_tensor(x, dtype=torch.float32, device=dev)
     y = plan.apply(xd)
     for _ in range(5):
@@ -335,8 +457,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200, help="timed requests per precision")
-    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=1000, help="timed requests (FP32)")
+    ap.add_argument("--serve-requests-fp64", type=int, default=200,
+                    help="timed requests in FP64 (it saturates below 20 req/s, so the queue only grows)")
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates (req/s): FP32 load sweep")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2048^2 / 5e8-visibility sub-run reported under `large_workload`")
@@ -356,7 +481,7 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     if args.pmc_probe:
-        pmc_probe(P, dev)
+        pmc_probe(P, dev, args.workload if args.workload != "op256j6" else "op256")
         return
     wl = W.CONFIGS[args.workload]
     n, M, J, D, L = wl.n, wl.M, wl.J, wl.D, wl.levels
@@ -455,6 +580,10 @@ def main():
         t_admm = a0.elapsed_time(a1) / K_steps
         rep = P.pr_admm_solve(h, psi.handle, y, P.admm_params(eps, gamma, iters=K_steps, op_norm=op_norm),
                               torch.zeros((n, n), dtype=rdt, device=dev), ws, want_report=True)
+        # one iteration from x = 0 (compared with the oracle's first iteration)
+        x_it1 = torch.zeros((n, n), dtype=rdt, device=dev)
+        P.pr_admm_solve(h, psi.handle, y, P.admm_params(eps, gamma, iters=1, op_norm=op_norm), x_it1, ws,
+                        want_report=False)
         del ws
         # ---- FISTA iterations (MAP problem, the same gamma, unit step)
         fws = torch.empty(P.pr_fista_workspace_size(h, psi.handle), dtype=torch.uint8, device=dev)
@@ -515,7 +644,7 @@ def main():
                     t_phi=t_phi, t_adj=t_adj, t_pair=t_pair,
                     t_admm=t_admm, t_fista=t_fista, t_pd=t_pd, t_local=t_local, items=plan.items, tile=plan.desc.tile, op_norm=op_norm, gamma=gamma,
                     eps=eps, resid=rep.resid_norm, nonfinite=rep.nonfinite, y_plan=yv, perm=perm,
-                    plan=plan, x=x)
+                    plan=plan, x=x, y_data=y, x_adj=xg, x_it1=x_it1)
 
     log("FP32 runs")
     r32 = run_prec(P.PR_F32)
@@ -597,8 +726,8 @@ def main():
         y_or = y_s[perm[pos].cpu().numpy()]
         res["phi_rel_err_fp32_vs_oracle_sample"] = float(np.linalg.norm(y_gpu - y_or) / np.linalg.norm(y_or))
     elif not args.no_cpu_baseline:
-        log("CPU baseline: oracle Phi and Phi^dagger on the full input")
-        from oracle import measurement as ms
+        log("CPU baseline: oracle Phi and Phi^dagger on the full input (one thread, then all host cores)")
+        from oracle import admm as oadmm, measurement as ms, wavelets as owv
         spec = ms.PhiSpec(n, 2 * n, J, D)
         uv64 = uv32.astype(np.float64)
         t0 = time.perf_counter()
@@ -606,24 +735,51 @@ def main():
         t1 = time.perf_counter()
         ms.phi_adjoint(y_ref, uv64, None, spec)
         t2 = time.perf_counter()
-        res["cpu_baseline"] = {"value": M / (t2 - t0), "unit": "visibilities/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one Phi ({t1 - t0:.1f} s) and one Phi^dagger ({t2 - t1:.1f} s) of the "
-                                         f"FP64 NumPy oracle on the full {M}-visibility input (single thread)",
-                               "host_cpus": os.cpu_count()}
+        workers = min(16, os.cpu_count() or 1)
+        tp = cpu_pair_parallel(x_true, uv64, spec, workers)
+        res["cpu_baseline"] = {"value": M / tp["pair_s"], "unit": "visibilities/s", "cores": tp["workers"],
+                               "kind": "oracle",
+                               "sample": f"one Phi ({tp['phi_s']:.2f} s) and one Phi^dagger ({tp['adj_s']:.2f} s) of "
+                                         f"the FP64 NumPy oracle on the full {M}-visibility input, the visibilities "
+                                         f"split over {tp['workers']} worker processes (the oracle's own degridding "
+                                         f"and gridding per chunk, partial grids added in chunk order)",
+                               "single_thread": {"value": M / (t2 - t0), "phi_s": t1 - t0, "adj_s": t2 - t1},
+                               "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+        # the oracle's first ADMM iteration with the GPU's operator norm and gamma (one thread)
         perm = r32["perm"].cpu().numpy()
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(perm.size)
+        y_user = r32["y_data"].cpu().numpy().astype(np.complex128)[inv]
+        nrm = r32["op_norm"]
+        S = owv.Sara(n, L)
+        t0 = time.perf_counter()
+        x1_ref, _, _, _ = oadmm.admm(y_user, lambda v: ms.phi(v, uv64, None, spec) / nrm,
+                                     lambda v: ms.phi_adjoint(v, uv64, None, spec) / nrm, S.forward, S.adjoint,
+                                     r32["eps"], oadmm.AdmmParams(gamma=r32["gamma"], iters=1), np.zeros((n, n)))
+        res["cpu_baseline"]["admm_iter_s_single_thread"] = time.perf_counter() - t0
+        rel = lambda g, r: float(np.linalg.norm(g - r) / np.linalg.norm(r))
         y32 = r32["y_plan"].cpu().numpy().astype(np.complex128)
         # the last Phi of the timed loop was applied to the sky: compare in plan order
-        err = float(np.linalg.norm(y32 - y_ref[perm]) / np.linalg.norm(y_ref))
-        res["phi_rel_err_fp32_vs_oracle"] = err
+        res["phi_rel_err_fp32_vs_oracle"] = rel(y32, y_ref[perm])
+        xadj_ref = ms.phi_adjoint(y_user, uv64, None, spec)
+        res["phi_adjoint_rel_err_fp32_vs_oracle"] = rel(r32["x_adj"].cpu().numpy(), xadj_ref)
+        res["admm_iter_rel_err_fp32_vs_oracle"] = rel(r32["x_it1"].cpu().numpy(), x1_ref)
         if r64 is not None:
             y64 = r64["y_plan"].cpu().numpy()
             perm64 = r64["perm"].cpu().numpy()
-            res["fp64"]["phi_rel_err_vs_oracle"] = float(np.linalg.norm(y64 - y_ref[perm64]) / np.linalg.norm(y_ref))
+            res["fp64"]["phi_rel_err_vs_oracle"] = rel(y64, y_ref[perm64])
+            inv64 = np.empty_like(perm64)
+            inv64[perm64] = np.arange(perm64.size)
+            yu64 = r64["y_data"].cpu().numpy()[inv64]
+            res["fp64"]["phi_adjoint_rel_err_vs_oracle"] = rel(r64["x_adj"].cpu().numpy(),
+                                                             ms.phi_adjoint(yu64, uv64, None, spec))
     del r32, r64
     torch.cuda.empty_cache()
     if not big:
         log("first-order kernel lookup")
         res["linear_lookup"] = run_linear(P, dev, n, J, D, uv32, x_true, K_steps, W_steps, not args.no_cpu_baseline)
+        log("J = 6")
+        res["j6"] = run_j6(P, dev, n, D, L, uv32, x_true, K_steps, W_steps, not args.no_cpu_baseline)
     if not args.no_batch:
         log("batched channels")
         res["batch"] = run_batch(P, dev, args)
@@ -631,10 +787,17 @@ def main():
         for prec in (P.PR_F32, P.PR_F64):
             tag = "fp32" if prec == P.PR_F32 else "fp64"
             log(f"serving {tag}")
-            res.setdefault("serving", {})[tag] = run_serve(P, dev, args, prec)
+            nreq = args.serve_requests if prec == P.PR_F32 else args.serve_requests_fp64
+            res.setdefault("serving", {})[tag] = run_serve(P, dev, args, prec, nreq=nreq)
             torch.cuda.empty_cache()
         s32, s64 = res["serving"]["fp32"], res["serving"]["fp64"]
         s32["img_err_gap_vs_fp64"] = abs(s32["img_err_median"] - s64["img_err_median"])
+        for rate in [float(r) for r in args.serve_sweep.split(",") if r.strip()]:
+            log(f"serving sweep fp32 at {rate} req/s")
+            r = run_serve(P, dev, args, P.PR_F32, rate=rate, nreq=max(100, int(10 * rate)))
+            res.setdefault("serving_sweep_fp32", []).append(
+                {k: r[k] for k in ("rate_req_s", "requests", "solves_per_s", "p50_ms", "p99_ms", "completed_all")})
+            torch.cuda.empty_cache()
     if not big and not args.no_large:
         res["large_workload"] = run_large(args)
     print(json.dumps(res))
@@ -648,7 +811,7 @@ def run_large(args):
     import torch
     torch.cuda.empty_cache()
     log("large workload: 2048^2 image, 5e8 visibilities (child process)")
-    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "share2048", "--steps", "5", "--warmup", "1"]
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "share2048", "--steps", "20", "--warmup", "2"]
     if args.no_cpu_baseline:
         cmd.append("--no-cpu-baseline")
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
@@ -659,7 +822,7 @@ def run_large(args):
     child = json.loads(lines[-1])
     keep = ("value", "unit", "ms_per_step", "phi_pair_ms", "phi_ms", "phi_adjoint_ms", "stage_ms",
             "admm_iter_ms_fp32", "fista_iter_ms_fp32", "primal_dual_iter_ms_fp32",
-            "admm_local_balls_iter_ms_fp32", "roofline", "roofline_other", "copy_gbs", "config",
+            "admm_local_balls_iter_ms_fp32", "roofline", "roofline_other", "copy_gbs", "config", "roofline_admm",
             "cpu_baseline", "phi_rel_err_fp32_vs_oracle_sample", "steps", "warmup")
     return {k: child[k] for k in keep if k in child}
 

@@ -516,6 +516,26 @@ int pr_batch_phi_adjoint(pr_batch b, const void* const* y, void* const* x,
 /* FP64 diagnostics of a member's current iterate (synchronises `stream`). */
 int pr_batch_report(pr_batch b, int32_t slot, pr_admm_report* rep, void* stream);
 
+/* Fused form of pr_batch_phi_apply / pr_batch_phi_adjoint (the per-channel
+ * split of Section "Distributed Images" kept on one GPU): one launch per
+ * operator stage for all current members instead of one per member. The
+ * degridding, the gridding walk and the patch merge run once over every
+ * member's work items or tiles (each item carries its member), and each FFT
+ * pass once per image size; every item and line is computed as in the
+ * member's own launch, so results are bitwise those of per-member calls.
+ * pr_batch_fuse_bytes gives the device workspace the current members need;
+ * pr_batch_fuse builds the schedules and member tables in the caller's
+ * workspace (256-byte aligned, owned by the caller, kept until the batch is
+ * destroyed or fused again) and synchronises the stream once. The two calls
+ * then use the fused form when every member has both vectors; adding or
+ * removing a member drops it (the calls launch per member again until
+ * pr_batch_fuse). PR_EUNSUPPORTED if the members' plans differ in precision,
+ * J, D, lookup or tile, or J > 4; PR_EWORKSPACE if ws is too small. Each call
+ * uploads the members' vector pointers when they changed since the last call
+ * (synchronising the stream then). */
+int pr_batch_fuse_bytes(pr_batch b, size_t* bytes);
+int pr_batch_fuse(pr_batch b, void* workspace, size_t bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Serving: a request loop over imaging solves with continuous batching.
  * Requests are admitted in arrival order as the active-job limit and the

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "admm.hpp"
+#include "fused.hpp"
 #include "ops.hpp"
 
 struct pr_batch_t {
@@ -35,6 +36,11 @@ struct pr_batch_t {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
+  // fused operator stages over the members (pr_batch_fuse); dropped when the
+  // membership changes
+  bool fused_ok = false;
+  std::vector<int> fused_slots;     // member slot of each fused plan
+  pr::FusedStages fused;
 };
 
 namespace pr {
@@ -107,6 +113,24 @@ int check_slot(const pr_batch_t* b, int slot) {
 }  // namespace
 
 }  // namespace pr
+
+namespace {
+
+// The fused form applies when it is current and every member has both vectors.
+template <typename X, typename Y>
+bool fused_vectors(pr_batch_t* b, X* const* x, Y* const* y, std::vector<X*>& fx, std::vector<Y*>& fy) {
+  if (!b->fused_ok) return false;
+  fx.clear();
+  fy.clear();
+  for (int slot : b->fused_slots) {
+    if (!x[slot] || !y[slot]) return false;
+    fx.push_back(x[slot]);
+    fy.push_back(y[slot]);
+  }
+  return true;
+}
+
+}  // namespace
 
 using namespace pr;
 
@@ -203,6 +227,7 @@ int pr_batch_add(pr_batch b, pr_phi_plan phi, pr_psi_plan psi, const void* y, vo
   m.cost = member_cost(m.job);
   m.used = true;
   b->dirty = true;
+  b->fused_ok = false;
   *slot = free_slot;
   return PR_OK;
 }
@@ -213,6 +238,7 @@ int pr_batch_remove(pr_batch b, int32_t slot) {
   PR_TRY(check_slot(b, slot));
   b->members[slot].used = false;
   b->dirty = true;
+  b->fused_ok = false;
   return PR_OK;
 }
 
@@ -259,12 +285,47 @@ int pr_batch_step(pr_batch b, int32_t iters, int32_t use_graph, void* stream) {
   return PR_OK;
 }
 
+int pr_batch_fuse_bytes(pr_batch b, size_t* bytes) {
+  clear_error();
+  PR_NONNULL(b);
+  PR_NONNULL(bytes);
+  std::vector<pr_phi_plan_t*> plans;
+  for (auto& m : b->members)
+    if (m.used) plans.push_back(m.job.phi);
+  if (plans.empty()) { set_error("the batch has no members"); return PR_EINVAL; }
+  return fused_bytes(plans.data(), static_cast<int>(plans.size()), bytes);
+}
+
+int pr_batch_fuse(pr_batch b, void* workspace, size_t bytes, void* stream) {
+  clear_error();
+  PR_NONNULL(b);
+  PR_TRY(check_sticky());
+  std::vector<pr_phi_plan_t*> plans;
+  std::vector<int> slots;
+  for (int i = 0; i < static_cast<int>(b->members.size()); ++i) {
+    if (!b->members[i].used) continue;
+    plans.push_back(b->members[i].job.phi);
+    slots.push_back(i);
+  }
+  if (plans.empty()) { set_error("the batch has no members"); return PR_EINVAL; }
+  b->fused_ok = false;
+  PR_TRY(fused_build(plans.data(), static_cast<int>(plans.size()), workspace, bytes, &b->fused, as_stream(stream)));
+  b->fused_slots = slots;
+  b->fused_ok = true;
+  return PR_OK;
+}
+
 int pr_batch_phi_apply(pr_batch b, const void* const* x, void* const* y, void* stream) {
   clear_error();
   PR_NONNULL(b);
   PR_NONNULL(x);
   PR_NONNULL(y);
   PR_TRY(check_sticky());
+  {
+    std::vector<const void*> fx;
+    std::vector<void*> fy;
+    if (fused_vectors(b, x, y, fx, fy)) return fused_apply(&b->fused, fx.data(), fy.data(), as_stream(stream));
+  }
   return fork_join(b, as_stream(stream), [&](pr_batch_t::Member& m, hipStream_t ms) {
     const int i = static_cast<int>(&m - b->members.data());
     if (!x[i] || !y[i]) return static_cast<int>(PR_OK);
@@ -279,6 +340,11 @@ int pr_batch_phi_adjoint(pr_batch b, const void* const* y, void* const* x, void*
   PR_NONNULL(x);
   PR_NONNULL(y);
   PR_TRY(check_sticky());
+  {
+    std::vector<const void*> fy;
+    std::vector<void*> fx;
+    if (fused_vectors(b, y, x, fy, fx)) return fused_adjoint(&b->fused, fy.data(), fx.data(), as_stream(stream));
+  }
   return fork_join(b, as_stream(stream), [&](pr_batch_t::Member& m, hipStream_t ms) {
     const int i = static_cast<int>(&m - b->members.data());
     if (!x[i] || !y[i]) return static_cast<int>(PR_OK);

@@ -8,6 +8,10 @@
 // Layouts: image x[iy*n + ix]; intermediate A[iy*K + kx] (n rows of K);
 // grid[ky*K + kx], ky = v cell, kx = u cell. Pixel offset p = i - n/2 sits at
 // grid index p mod K.
+#include <cstring>
+#include <vector>
+
+#include "fused.hpp"
 #include "phi.hpp"
 
 namespace pr {
@@ -121,12 +125,34 @@ inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
   *threads = t;
 }
 
+}  // namespace
+
+// One plan's arrays in a fused FFT launch (several plans of one image size,
+// blockIdx.y = member): the kernels below take their pointers from here when
+// given a table.
+template <typename R>
+struct FftPtrs {
+  const R* x;          // forward: the image
+  const R* corr;
+  const cx_t<R>* tw;
+  cx_t<R>* A;          // n x K intermediate
+  cx_t<R>* grid;       // K x K
+  R* x_out;            // adjoint: the real image
+};
+
+namespace {
+
 // Forward row pass: image rows -> S Z -> FFT along u -> A.
 template <typename R>
 __global__ __launch_bounds__(kFftThreads) void fzs_rows_kernel(const R* __restrict__ x, const R* __restrict__ corr,
                                                              const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ A,
-                                                             int n, int K, int logK, int W, int LS) {
+                                                             int n, int K, int logK, int W, int LS,
+                                                             const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
+  if (mp) {
+    const FftPtrs<R>& m = mp[blockIdx.y];
+    x = m.x; corr = m.corr; tw = m.tw; A = m.A;
+  }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int row0 = blockIdx.x * W;
@@ -158,8 +184,13 @@ __device__ inline int xcd_group(int b, int nb) {
 template <typename R>
 __global__ __launch_bounds__(kFftThreads) void fzs_cols_kernel(const cx_t<R>* __restrict__ A,
                                                              const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ grid,
-                                                             int n, int K, int logK, int W, int LS) {
+                                                             int n, int K, int logK, int W, int LS,
+                                                             const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
+  if (mp) {
+    const FftPtrs<R>& m = mp[blockIdx.y];
+    A = m.A; tw = m.tw; grid = m.grid;
+  }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
@@ -183,8 +214,12 @@ template <typename R>
 __global__ __launch_bounds__(kFftThreads) void fzs_adj_cols_kernel(const cx_t<R>* __restrict__ grid,
                                                                  const cx_t<R>* __restrict__ tw,
                                                                  cx_t<R>* __restrict__ A, int n, int K, int logK,
-                                                                 int W, int LS) {
+                                                                 int W, int LS, const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
+  if (mp) {
+    const FftPtrs<R>& m = mp[blockIdx.y];
+    grid = m.grid; tw = m.tw; A = m.A;
+  }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
@@ -209,8 +244,13 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>
                                                                  const R* __restrict__ corr,
                                                                  const cx_t<R>* __restrict__ tw, R* __restrict__ x_out,
                                                                  const R* __restrict__ x_in, R* __restrict__ zbar,
-                                                                 R rho, int n, int K, int logK, int W, int LS) {
+                                                                 R rho, int n, int K, int logK, int W, int LS,
+                                                                 const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
+  if (mp) {   // plain adjoint only (MODE 0)
+    const FftPtrs<R>& m = mp[blockIdx.y];
+    A = m.A; corr = m.corr; tw = m.tw; x_out = m.x_out;
+  }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int row0 = blockIdx.x * W;
@@ -247,11 +287,12 @@ int fzs_impl(pr_phi_plan_t* p, const R* x, hipStream_t s) {
   const size_t lds_r = static_cast<size_t>(Wr) * LSr * sizeof(C);
   const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
   fzs_rows_kernel<R><<<(n + Wr - 1) / Wr, Tr, lds_r, s>>>(
-      x, static_cast<const R*>(p->corr), static_cast<const C*>(p->tw), static_cast<C*>(p->fft_tmp), n, K, logK, Wr, LSr);
+      x, static_cast<const R*>(p->corr), static_cast<const C*>(p->tw), static_cast<C*>(p->fft_tmp), n, K, logK, Wr, LSr,
+      nullptr);
   PR_TRY_LAUNCH();
   fzs_cols_kernel<R><<<K / Wc, Tc, lds_c, s>>>(static_cast<const C*>(p->fft_tmp),
                                                        static_cast<const C*>(p->tw), static_cast<C*>(p->grid), n, K,
-                                                       logK, Wc, LSc);
+                                                       logK, Wc, LSc, nullptr);
   PR_TRY_LAUNCH();
   return PR_OK;
 }
@@ -267,16 +308,132 @@ int fzs_adjoint_impl(pr_phi_plan_t* p, R* x_out, const R* x_in, R* zbar, double 
   const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
   fzs_adj_cols_kernel<R><<<K / Wc, Tc, lds_c, s>>>(static_cast<const C*>(p->grid),
                                                            static_cast<const C*>(p->tw), static_cast<C*>(p->fft_tmp),
-                                                           n, K, logK, Wc, LSc);
+                                                           n, K, logK, Wc, LSc, nullptr);
   PR_TRY_LAUNCH();
   fzs_adj_rows_kernel<R, MODE><<<(n + Wr - 1) / Wr, Tr, lds_r, s>>>(
       static_cast<const C*>(p->fft_tmp), static_cast<const R*>(p->corr), static_cast<const C*>(p->tw), x_out, x_in,
-      zbar, static_cast<R>(rho), n, K, logK, Wr, LSr);
+      zbar, static_cast<R>(rho), n, K, logK, Wr, LSr, nullptr);
   PR_TRY_LAUNCH();
   return PR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// fused passes: one launch per pass for all members of one image size
+// ---------------------------------------------------------------------------
+template <typename R>
+size_t fused_fft_bytes_t(const std::vector<int>& counts) {
+  Carver c(nullptr);
+  for (int k : counts) {
+    c.take<FftPtrs<R>>(k);
+    c.take<FftPtrs<R>>(k);
+  }
+  return c.bytes();
+}
+
+template <typename R>
+int fused_fft_build_t(FusedStages* f, Carver& c) {
+  using C = cx_t<R>;
+  for (FusedStages::Cls& k : f->cls) {
+    const int cnt = static_cast<int>(k.idx.size());
+    k.d_fwd = c.take<FftPtrs<R>>(cnt);
+    k.d_adj = c.take<FftPtrs<R>>(cnt);
+    k.h_fwd.assign(cnt * sizeof(FftPtrs<R>), 0);
+    k.h_adj.assign(cnt * sizeof(FftPtrs<R>), 0);
+    for (int i = 0; i < cnt; ++i) {
+      const pr_phi_plan_t* p = f->plans[k.idx[i]];
+      FftPtrs<R> q{};
+      q.corr = static_cast<const R*>(p->corr);
+      q.tw = static_cast<const C*>(p->tw);
+      q.A = static_cast<C*>(p->fft_tmp);
+      q.grid = static_cast<C*>(p->grid);
+      std::memcpy(k.h_fwd.data() + i * sizeof q, &q, sizeof q);
+      std::memcpy(k.h_adj.data() + i * sizeof q, &q, sizeof q);
+    }
+    k.up_fwd.assign(cnt, nullptr);
+    k.up_adj.assign(cnt, nullptr);
+  }
+  return PR_OK;
+}
+
+// Patch the members' image pointers into a class table; upload when changed
+// (then wait, so the host table may change on the next call).
+template <typename R, typename V>
+int upload_ptrs(std::vector<char>& h, std::vector<const void*>& up, void* dev, const std::vector<int>& idx,
+                V* const* vec, V* FftPtrs<R>::*field, hipStream_t s) {
+  bool changed = false;
+  for (size_t i = 0; i < idx.size(); ++i) {
+    FftPtrs<R>* q = reinterpret_cast<FftPtrs<R>*>(h.data() + i * sizeof(FftPtrs<R>));
+    q->*field = vec[idx[i]];
+    if (up[i] != static_cast<const void*>(vec[idx[i]])) changed = true;
+  }
+  if (!changed) return PR_OK;
+  PR_TRY_HIP(hipMemcpyAsync(dev, h.data(), h.size(), hipMemcpyHostToDevice, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));
+  for (size_t i = 0; i < idx.size(); ++i) up[i] = vec[idx[i]];
+  return PR_OK;
+}
+
+template <typename R>
+int fused_fzs_t(FusedStages* f, const void* const* x, hipStream_t s) {
+  using C = cx_t<R>;
+  for (FusedStages::Cls& k : f->cls) {
+    PR_TRY((upload_ptrs<R, const R>(k.h_fwd, k.up_fwd, k.d_fwd, k.idx, reinterpret_cast<const R* const*>(x),
+                                    &FftPtrs<R>::x, s)));
+    const int n = k.n, K = 2 * n, logK = ilog2(K);
+    const unsigned cnt = static_cast<unsigned>(k.idx.size());
+    int Wr, LSr, Wc, LSc, Tr, Tc;
+    lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
+    lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
+    const FftPtrs<R>* mp = static_cast<const FftPtrs<R>*>(k.d_fwd);
+    fzs_rows_kernel<R><<<dim3((n + Wr - 1) / Wr, cnt), Tr, static_cast<size_t>(Wr) * LSr * sizeof(C), s>>>(
+        nullptr, nullptr, nullptr, nullptr, n, K, logK, Wr, LSr, mp);
+    PR_TRY_LAUNCH();
+    fzs_cols_kernel<R><<<dim3(K / Wc, cnt), Tc, static_cast<size_t>(Wc) * LSc * sizeof(C), s>>>(
+        nullptr, nullptr, nullptr, n, K, logK, Wc, LSc, mp);
+    PR_TRY_LAUNCH();
+  }
+  return PR_OK;
+}
+
+template <typename R>
+int fused_fzs_adjoint_t(FusedStages* f, void* const* x, hipStream_t s) {
+  using C = cx_t<R>;
+  for (FusedStages::Cls& k : f->cls) {
+    PR_TRY((upload_ptrs<R, R>(k.h_adj, k.up_adj, k.d_adj, k.idx, reinterpret_cast<R* const*>(x), &FftPtrs<R>::x_out,
+                              s)));
+    const int n = k.n, K = 2 * n, logK = ilog2(K);
+    const unsigned cnt = static_cast<unsigned>(k.idx.size());
+    int Wr, LSr, Wc, LSc, Tr, Tc;
+    lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
+    lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
+    const FftPtrs<R>* mp = static_cast<const FftPtrs<R>*>(k.d_adj);
+    fzs_adj_cols_kernel<R><<<dim3(K / Wc, cnt), Tc, static_cast<size_t>(Wc) * LSc * sizeof(C), s>>>(
+        nullptr, nullptr, nullptr, n, K, logK, Wc, LSc, mp);
+    PR_TRY_LAUNCH();
+    fzs_adj_rows_kernel<R, 0><<<dim3((n + Wr - 1) / Wr, cnt), Tr, static_cast<size_t>(Wr) * LSr * sizeof(C), s>>>(
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, R(0), n, K, logK, Wr, LSr, mp);
+    PR_TRY_LAUNCH();
+  }
+  return PR_OK;
+}
+
 }  // namespace
+
+size_t fused_fft_bytes(const std::vector<int>& counts, int prec) {
+  return prec == PR_F32 ? fused_fft_bytes_t<float>(counts) : fused_fft_bytes_t<double>(counts);
+}
+
+int fused_fft_build(FusedStages* f, Carver& c) {
+  return f->prec == PR_F32 ? fused_fft_build_t<float>(f, c) : fused_fft_build_t<double>(f, c);
+}
+
+int fused_fzs(FusedStages* f, const void* const* x, hipStream_t s) {
+  return f->prec == PR_F32 ? fused_fzs_t<float>(f, x, s) : fused_fzs_t<double>(f, x, s);
+}
+
+int fused_fzs_adjoint(FusedStages* f, void* const* x, hipStream_t s) {
+  return f->prec == PR_F32 ? fused_fzs_adjoint_t<float>(f, x, s) : fused_fzs_adjoint_t<double>(f, x, s);
+}
 
 int phi_fzs(pr_phi_plan_t* p, const void* x, hipStream_t s) {
   if (p->prec == PR_F32) return fzs_impl<float>(p, static_cast<const float*>(x), s);

@@ -17,11 +17,13 @@
 // The item's patch value at cell q is sum_{a,b} m[q - (a,b)][a][b]. Patches are
 // written per item and a merge kernel adds the up to four overlapping tile
 // patches of each grid cell, items in order.
+#include <cstring>
 #include <mutex>
 #include <set>
 #include <type_traits>
 #include <utility>
 
+#include "fused.hpp"
 #include "phi.hpp"
 #include "taps.hpp"
 
@@ -46,6 +48,12 @@ __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size
 // from stored (tap word, w) pairs (FP32 plans; the taps were formed by the
 // plan with the same arithmetic).
 constexpr int kLkNearest = 0, kLkLinear = 1, kLkWords = 2;
+
+// Work-item tile field of a fused launch: tile | member << kMemberShift
+// (tiles < 2^20 for K <= 8192 and tiles >= 8; members < 4096).
+constexpr int kMemberShift = 20;
+__host__ __device__ inline int item_tile(const int4& it) { return it.x & ((1 << kMemberShift) - 1); }
+__host__ __device__ inline int item_member(const int4& it) { return static_cast<int>(static_cast<uint32_t>(it.x) >> kMemberShift); }
 
 // Complex zero written as one 64-bit pattern for FP32 (a single 64-bit move
 // per accumulator instead of two 32-bit ones).
@@ -118,6 +126,11 @@ struct GwArgs {
   const int32_t* sec;         // MODE 2: section of each visibility (plan order)
   cx_t<R>* t_out;
   double* partials;
+  // Fused launch over several plans (batched channels, plain operator only):
+  // member m's own arguments are mtab[m], and the tile field of each work item
+  // carries the member (tile | m << kMemberShift); the table, D and kappa of
+  // the launch are shared (every member has the same kernel).
+  const GwArgs* mtab;
 };
 
 constexpr int kDegridPer = 4;   // visibilities per thread per chunk
@@ -131,23 +144,25 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   extern __shared__ char smem_raw[];
   const int tid = threadIdx.x;
   C* patch = reinterpret_cast<C*>(smem_raw);
-  const int P = a.P, T = a.T, K = a.K;
+  const int P = a.P, T = a.T;          // the same for every member of a fused launch
+  // the arguments of the plan an item belongs to
+  auto mem = [&](const int4& it) -> const GwArgs<R>& { return a.mtab ? a.mtab[item_member(it)] : a; };
   double sum_t = 0.0, sum_r = 0.0;
   double sacc[MODE == 2 ? kSecAcc : 1] = {};   // MODE 2: ||t||^2 per section
   // inputs of this thread's visibilities for the current and the next chunk
   R cu_[kDegridPer], cv_[kDegridPer], cw_[kDegridPer], nu_[kDegridPer], nv_[kDegridPer], nw_[kDegridPer];
-  auto load = [&](int64_t c0, int64_t cend, R* u, R* v, R* w) {
+  auto load = [&](const R* uvp, int64_t c0, int64_t cend, R* u, R* v, R* w) {
 #pragma unroll
     for (int j = 0; j < kDegridPer; ++j) {
       const int64_t k = c0 + tid + j * kThreads;
-      if (k < cend) vis_load<TW>(a.uv, k, u[j], v[j], w[j]);
+      if (k < cend) vis_load<TW>(uvp, k, u[j], v[j], w[j]);
     }
   };
   const int kbeg = a.sched_off[blockIdx.x], kend = a.sched_off[blockIdx.x + 1];
   // the first item's visibilities are in flight while the table is copied
   if (kbeg < kend) {
     const int4 it0 = a.items[kbeg];
-    load(it0.y, it0.z, cu_, cv_, cw_);
+    load(mem(it0).uv, it0.y, it0.z, cu_, cv_, cw_);
   }
   const R* tab = a.table;
   if (TAB_LDS) {
@@ -157,18 +172,22 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   }
   for (int ks = kbeg; ks < kend; ++ks) {
     const int4 it = a.items[ks];
-    const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
-    if (ks > kbeg) load(it.y, it.z, cu_, cv_, cw_);
+    const GwArgs<R>& m = mem(it);
+    const int K = m.K;
+    const int tile = item_tile(it);
+    const int tv = tile >> m.lognT, tu = tile & (m.nT - 1);
+    const R iscale = a.mtab ? m.scale : scale;
+    if (ks > kbeg) load(m.uv, it.y, it.z, cu_, cv_, cw_);
     __syncthreads();
     const float invP = 1.0f / P;
     for (int i = tid; i < P * P; i += kThreads) {
       const int pv = small_div(i, P, invP), pu = i - pv * P;
       const int gv = (tv * T + pv) & (K - 1), gu = (tu * T + pu) & (K - 1);
-      patch[i] = a.grid[static_cast<int64_t>(gv) * K + gu];
+      patch[i] = m.grid[static_cast<int64_t>(gv) * K + gu];
     }
     __syncthreads();
     for (int64_t c0 = it.y; c0 < it.z; c0 += CH) {
-      if (c0 + CH < it.z) load(c0 + CH, it.z, nu_, nv_, nw_);
+      if (c0 + CH < it.z) load(m.uv, c0 + CH, it.z, nu_, nv_, nw_);
       // MODE 2: the chunk's y, s and section ids, issued before any of its stores
       // (for MODE 1 the same early issue measured slower: it loads them in place)
       constexpr int NA = MODE == 2 ? kDegridPer : 1;
@@ -191,11 +210,11 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
         if (k >= it.z) continue;
         AxisTaps xu, xv;
         int lu, lv;
-        vis_taps<TW>(cu_[j], cv_[j], a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
+        vis_taps<TW>(cu_[j], cv_[j], m.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
         if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
           // cannot happen for a plan's own sorted baselines; flag instead of reading out of the patch
           const R nan = R(NAN);
-          if (MODE == 0) a.y_out[k] = cmk<C>(nan, nan);
+          if (MODE == 0) m.y_out[k] = cmk<C>(nan, nan);
           else a.t_out[k] = cmk<C>(nan, nan);
           continue;
         }
@@ -216,10 +235,10 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
           accr += wv[b] * rr;
           acci += wv[b] * ri;
         }
-        const R ws = cw_[j] * scale;
+        const R ws = cw_[j] * iscale;
         const C yk = cmk<C>(accr * ws, acci * ws);
         if (MODE == 0) {
-          a.y_out[k] = yk;
+          m.y_out[k] = yk;
         } else {
           const C yo = MODE == 2 ? yo_[MODE == 2 ? j : 0] : a.y_obs[k];
           const C sk = MODE == 2 ? sk_[MODE == 2 ? j : 0] : (a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0)));
@@ -298,6 +317,7 @@ struct GwAdjArgs {
   const int32_t* sec;        // MODE 1, local balls: section of each visibility (plan order), or null
   const double* kappa_sec;   // MODE 1, local balls: kappa of each section
   cx_t<R>* patches;
+  const GwAdjArgs* mtab;     // fused launch over several plans (as GwArgs::mtab)
 };
 
 // LDS layout of the gridding kernel. Staged visibilities are stored
@@ -720,7 +740,9 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   unsigned long long* helpmask = nonmid + kThreads / 64;                                       // per wave
   const int tid = threadIdx.x;
   const R* tab = a.table;
-  const int T = TS ? TS : a.T, P = TS ? TS + J - 1 : a.P, K = a.K;
+  const int T = TS ? TS : a.T, P = TS ? TS + J - 1 : a.P;   // the same for every member of a fused launch
+  // the arguments of the plan an item belongs to
+  auto mem = [&](const int4& it) -> const GwAdjArgs<R>& { return a.mtab ? a.mtab[item_member(it)] : a; };
   const int TT = T * T;
   R kappa_ball = 1;
   if (ADMM) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
@@ -737,9 +759,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   // base) with 32-bit item-relative offsets (items hold fewer than 2^20).
   auto issue = [&](const int4& it, int L, int q0) {
     pf.ok = 0u;
+    const GwAdjArgs<R>& m = mem(it);
     const int n = it.z - it.y;
     const int64_t b0 = it.y;
-    const C* vi = (MODE == 0 ? a.y_in : a.t_in) + b0;
+    const C* vi = (MODE == 0 ? m.y_in : m.t_in) + b0;
 #pragma unroll
     for (int r = 0; r < PF; ++r) {
       const int q = q0 + lane_q;
@@ -748,16 +771,16 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       pf.ok |= static_cast<unsigned>(ok) << r;
       const uint32_t oc = ok ? static_cast<uint32_t>(o) : 0u;
       if constexpr (TW) {
-        const uint2 w2 = *byte_at(reinterpret_cast<const uint2*>(a.uv) + b0, oc * 8u);
+        const uint2 w2 = *byte_at(reinterpret_cast<const uint2*>(m.uv) + b0, oc * 8u);
         pf.uvw[r].u = __uint_as_float(w2.x);
         pf.uvw[r].v = R(0);
         pf.uvw[r].w = __uint_as_float(w2.y);
       } else {
-        vis_load<TW>(a.uv, b0 + oc, pf.uvw[r].u, pf.uvw[r].v, pf.uvw[r].w);
+        vis_load<TW>(m.uv, b0 + oc, pf.uvw[r].u, pf.uvw[r].v, pf.uvw[r].w);
       }
       pf.val[r] = *byte_at(vi, oc * static_cast<uint32_t>(sizeof(C)));
-      if (ADMM) pf.s[ADMM ? r : 0] = *byte_at(a.s_io + b0, oc * static_cast<uint32_t>(sizeof(C)));
-      if (SEC) pf.sec[SEC ? r : 0] = a.sec[b0 + oc];
+      if (ADMM) pf.s[ADMM ? r : 0] = *byte_at(m.s_io + b0, oc * static_cast<uint32_t>(sizeof(C)));
+      if (SEC) pf.sec[SEC ? r : 0] = m.sec[b0 + oc];
     }
   };
   // store chunk h of the prefetched pair (positions q0 + h WC ..) lane-
@@ -765,6 +788,8 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   // slot and only the stores are predicated, so every prefetched register is
   // consumed on every path (no conservative waits on them later).
   auto commit = [&](const int4& it, int L, int q0, int h) {
+    const GwAdjArgs<R>& m = mem(it);
+    const R iscale = a.mtab ? m.scale : scale;
 #pragma unroll
     for (int r = 0; r < PF; ++r) {
       const bool ok = ((pf.ok >> r) & 1u) && lane_h == h;
@@ -781,13 +806,13 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
         val = cmk<C>(a.vr_coef * vr.x + sn.x, a.vr_coef * vr.y + sn.y);
       }
-      const R ws = pf.uvw[r].w * scale;
+      const R ws = pf.uvw[r].w * iscale;
       const C uvr = cmk<C>(pf.uvw[r].u, pf.uvw[r].v);
       const C wv = cmk<C>(val.x * ws, val.y * ws);
       if (ok) {
         if (ADMM) {
           const uint32_t o = static_cast<uint32_t>((lane_t + r * kSegStride) * L + q0 + lane_q);
-          *byte_at(a.s_io + static_cast<int64_t>(it.y), o * static_cast<uint32_t>(sizeof(C))) = sn;
+          *byte_at(m.s_io + static_cast<int64_t>(it.y), o * static_cast<uint32_t>(sizeof(C))) = sn;
         }
         const int slot = (lane_q - h * WC) * kStagePitch + lane_t + r * kSegStride;
         st[slot] = Staged{uvr, wv};
@@ -820,7 +845,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     const bool has_next = ks + 1 < kend;
     const int4 itn = has_next ? a.items[ks + 1] : make_int4(0, 0, 0, 0);
     const int Ln = seg_len(itn);
-    const int tv = it.x >> a.lognT, tu = it.x & (a.nT - 1);
+    const GwAdjArgs<R>& mi = mem(it);
+    const int K = mi.K;
+    const int tile = item_tile(it);
+    const int tv = tile >> mi.lognT, tu = tile & (mi.nT - 1);
     const int segn = max(0, min(L, it.z - (it.y + tid * L)));   // this thread's positions
     __syncthreads();   // the previous item is done with the moments, side slots and cell lists
     for (int i = tid; i < TT * JJ; i += kThreads) mom[i] = cmk<C>(R(0), R(0));
@@ -847,7 +875,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
         C val = sp.val;
         AxisTaps xu, xv;
         int lu, lv;
-        vis_taps<TW>(sp.uv.x, sp.uv.y, a.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
+        vis_taps<TW>(sp.uv.x, sp.uv.y, mi.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
         if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
           // cannot happen for a plan's own sorted baselines: keep LDS indices in range, poison the value
           lu = lv = 0;
@@ -1015,7 +1043,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     }
     __syncthreads();
     // patch: cell q = c + (b, a) collects moment [a][b] of base cell c
-    C* out = a.patches + item * static_cast<int64_t>(P) * P;
+    C* out = mi.patches + item * static_cast<int64_t>(P) * P;
     const float invP = 1.0f / P;
     for (int pc = tid; pc < P * P; pc += kThreads) {
       const int pv = small_div(pc, P, invP), pu = pc - pv * P;
@@ -1059,11 +1087,37 @@ template <int J> struct GridSplit<double, J> { static constexpr int JA = J <= 2 
 // Grid cell = sum of the patches of the (up to four) tiles whose patch covers
 // it, neighbour tiles first, items of a tile in order. One block per output
 // tile, so the item ranges it walks are the same for all its threads.
+// One plan of a fused merge: block b of the launch is tile b - tile0 of the
+// member whose range [tile0, next member's tile0) holds b.
+template <typename R>
+struct MergeArgs {
+  const cx_t<R>* patches;
+  const int32_t* item_off;
+  cx_t<R>* grid;
+  int K, nT, tile0, pad;
+};
+
 template <typename R>
 __global__ void merge_patches_kernel(const cx_t<R>* __restrict__ patches, const int32_t* __restrict__ item_off,
-                                     cx_t<R>* __restrict__ grid, int K, int T, int P, int nT, int J) {
+                                     cx_t<R>* __restrict__ grid, int K, int T, int P, int nT, int J,
+                                     const MergeArgs<R>* __restrict__ mtab, int nmembers) {
   using C = cx_t<R>;
-  const int t = blockIdx.x;
+  int t = blockIdx.x;
+  if (mtab) {
+    // the member holding this block (binary search over the tile offsets)
+    int lo = 0, hi = nmembers - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (mtab[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    const MergeArgs<R> m = mtab[lo];
+    patches = m.patches;
+    item_off = m.item_off;
+    grid = m.grid;
+    K = m.K;
+    nT = m.nT;
+    t -= m.tile0;
+  }
   const int tv = t / nT, tu = t - tv * nT;
   const int64_t P2 = static_cast<int64_t>(P) * P;
   for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
@@ -1165,13 +1219,13 @@ int allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename R, int J, int MODE, int LK>
-int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s) {
+int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s, int G = 0) {
   using C = cx_t<R>;
   const size_t patch = align16(static_cast<size_t>(p->P) * p->P * sizeof(C));
   const size_t tabb = static_cast<size_t>(a.tlen) * sizeof(R);
   size_t lds = patch;
   if (MODE >= 1 && lds < kThreads * sizeof(double)) lds = kThreads * sizeof(double);
-  const int G = degrid_blocks(p);
+  if (G <= 0) G = degrid_blocks(p);
   if (lds + tabb <= kLdsSoft) {
     degrid_kernel<R, J, MODE, true, LK><<<G, kThreads, lds + tabb, s>>>(a);
   } else if (lds <= kLdsHard) {
@@ -1275,7 +1329,8 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
   PR_TRY_LAUNCH();
   if (parts & 2) {
     merge_patches_kernel<R><<<p->nTiles, p->T * p->T < kThreads ? p->T * p->T : kThreads, 0, s>>>(
-        static_cast<const C*>(p->patches), p->item_off, static_cast<C*>(p->grid), p->K, p->T, p->P, p->nT, p->J);
+        static_cast<const C*>(p->patches), p->item_off, static_cast<C*>(p->grid), p->K, p->T, p->P, p->nT, p->J,
+        nullptr, 0);
     PR_TRY_LAUNCH();
   }
   return PR_OK;
@@ -1444,6 +1499,164 @@ int gwadj_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) 
   });
 }
 
+// ---------------------------------------------------------------------------
+// fused launches over several plans (see fused.hpp)
+// ---------------------------------------------------------------------------
+template <typename R>
+size_t fused_vis_bytes_t(int n, int64_t items) {
+  Carver c(nullptr);
+  c.take<GwArgs<R>>(n);
+  c.take<GwAdjArgs<R>>(n);
+  c.take<MergeArgs<R>>(n);
+  c.take<int4>(items);
+  c.take<int32_t>(kDegridBlocks + 1);
+  c.take<int4>(items);
+  c.take<int32_t>(kGridBlocks + 1);
+  return c.bytes();
+}
+
+template <typename R>
+int fused_vis_build_t(FusedStages* f, Carver& c, hipStream_t s) {
+  const int n = static_cast<int>(f->plans.size());
+  int64_t total = 0;
+  for (const pr_phi_plan_t* p : f->plans) total += p->nItems;
+  f->d_dg = c.take<GwArgs<R>>(n);
+  f->d_ga = c.take<GwAdjArgs<R>>(n);
+  MergeArgs<R>* mg = c.take<MergeArgs<R>>(n);
+  f->d_mg = mg;
+  f->sched_d = c.take<int4>(total);
+  f->sched_d_off = c.take<int32_t>(kDegridBlocks + 1);
+  f->sched_g = c.take<int4>(total);
+  f->sched_g_off = c.take<int32_t>(kGridBlocks + 1);
+  // every member's items, the tile field tagged with the member
+  std::vector<int4> all, it;
+  std::vector<int32_t> local;
+  std::vector<MergeArgs<R>> hm(static_cast<size_t>(n));
+  all.reserve(static_cast<size_t>(total));
+  local.reserve(static_cast<size_t>(total));
+  int tiles = 0;
+  for (int m = 0; m < n; ++m) {
+    pr_phi_plan_t* p = f->plans[m];
+    it.resize(static_cast<size_t>(p->nItems));
+    if (p->nItems > 0) {
+      PR_TRY_HIP(hipMemcpyAsync(it.data(), p->items, p->nItems * sizeof(int4), hipMemcpyDeviceToHost, s));
+      PR_TRY_HIP(hipStreamSynchronize(s));
+    }
+    for (int64_t i = 0; i < p->nItems; ++i) {
+      int4 e = it[i];
+      e.x |= m << kMemberShift;
+      all.push_back(e);
+      local.push_back(static_cast<int32_t>(i));
+    }
+    hm[m] = MergeArgs<R>{static_cast<const cx_t<R>*>(p->patches), p->item_off, static_cast<cx_t<R>*>(p->grid), p->K,
+                         p->nT, tiles, 0};
+    tiles += p->nTiles;
+  }
+  f->tiles = tiles;
+  const pr_phi_plan_t* p0 = f->plans[0];
+  const int64_t P2 = static_cast<int64_t>(p0->P) * p0->P;
+  f->Gd = static_cast<int>(total < kDegridBlocks ? total : kDegridBlocks);
+  f->Gg = static_cast<int>(total < kGridBlocks ? total : kGridBlocks);
+  std::vector<int4> sd, sg;
+  std::vector<int32_t> sdo, sgo;
+  if (total > 0) {
+    lpt_schedule(all, f->Gd, P2 / 2, sd, sdo);
+    lpt_schedule(all, f->Gg, P2, sg, sgo);
+    for (int4& e : sd) e.w = local[e.w];
+    for (int4& e : sg) e.w = local[e.w];
+    PR_TRY_HIP(hipMemcpyAsync(f->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    PR_TRY_HIP(hipMemcpyAsync(f->sched_d_off, sdo.data(), sdo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PR_TRY_HIP(hipMemcpyAsync(f->sched_g, sg.data(), sg.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    PR_TRY_HIP(hipMemcpyAsync(f->sched_g_off, sgo.data(), sgo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  PR_TRY_HIP(hipMemcpyAsync(mg, hm.data(), hm.size() * sizeof(MergeArgs<R>), hipMemcpyHostToDevice, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
+  // host argument tables: every member's own launch arguments
+  f->h_dg.assign(static_cast<size_t>(n) * sizeof(GwArgs<R>), 0);
+  f->h_ga.assign(static_cast<size_t>(n) * sizeof(GwAdjArgs<R>), 0);
+  for (int m = 0; m < n; ++m) {
+    const GwArgs<R> g = gw_args<R>(f->plans[m], 1.0);
+    const GwAdjArgs<R> ga = gwadj_args<R>(f->plans[m], 1.0);
+    std::memcpy(f->h_dg.data() + m * sizeof(GwArgs<R>), &g, sizeof g);
+    std::memcpy(f->h_ga.data() + m * sizeof(GwAdjArgs<R>), &ga, sizeof ga);
+  }
+  f->up_dg.assign(static_cast<size_t>(n), nullptr);
+  f->up_ga.assign(static_cast<size_t>(n), nullptr);
+  return PR_OK;
+}
+
+// Patch each call's vector pointers into the host table; upload it when they
+// changed (then wait for the copy, so the host table may change next call).
+template <typename A, typename V>
+int upload_args(std::vector<char>& h, std::vector<const void*>& up, void* dev, V* const* vec, V* A::*field,
+                hipStream_t s) {
+  const size_t n = up.size();
+  bool changed = false;
+  for (size_t m = 0; m < n; ++m) {
+    A* a = reinterpret_cast<A*>(h.data() + m * sizeof(A));
+    a->*field = vec[m];
+    if (up[m] != static_cast<const void*>(vec[m])) changed = true;
+  }
+  if (!changed) return PR_OK;
+  PR_TRY_HIP(hipMemcpyAsync(dev, h.data(), h.size(), hipMemcpyHostToDevice, s));
+  PR_TRY_HIP(hipStreamSynchronize(s));
+  for (size_t m = 0; m < n; ++m) up[m] = vec[m];
+  return PR_OK;
+}
+
+template <typename R>
+int fused_gw_t(FusedStages* f, void* const* y, hipStream_t s) {
+  if (f->Gd == 0) return PR_OK;
+  using C = cx_t<R>;
+  PR_TRY((upload_args<GwArgs<R>, C>(f->h_dg, f->up_dg, f->d_dg, reinterpret_cast<C* const*>(y), &GwArgs<R>::y_out, s)));
+  pr_phi_plan_t* p0 = f->plans[0];
+  GwArgs<R> a = gw_args<R>(p0, 1.0);
+  a.items = f->sched_d;
+  a.sched_off = f->sched_d_off;
+  a.mtab = static_cast<const GwArgs<R>*>(f->d_dg);
+  return with_j(p0->J, [&](auto jj) {
+    return with_lk<R>(p0, [&](auto lk) {
+      return launch_degrid<R, decltype(jj)::value, 0, decltype(lk)::value>(p0, a, s, f->Gd);
+    });
+  });
+}
+
+template <typename R>
+int fused_gw_adjoint_t(FusedStages* f, const void* const* y, hipStream_t s) {
+  using C = cx_t<R>;
+  pr_phi_plan_t* p0 = f->plans[0];
+  if (f->Gg > 0) {
+    PR_TRY((upload_args<GwAdjArgs<R>, const C>(f->h_ga, f->up_ga, f->d_ga, reinterpret_cast<const C* const*>(y),
+                                               &GwAdjArgs<R>::y_in, s)));
+    GwAdjArgs<R> a = gwadj_args<R>(p0, 1.0);
+    a.items = f->sched_g;
+    a.sched_off = f->sched_g_off;
+    a.mtab = static_cast<const GwAdjArgs<R>*>(f->d_ga);
+    bool walked = false;
+    const int rc = with_j(p0->J, [&](auto jj) -> int {
+      constexpr int JJ = decltype(jj)::value;
+      if constexpr (JJ <= 4) {
+        return with_lk<R>(p0, [&](auto lk) {
+          return launch_walk<R, JJ, 0, decltype(lk)::value>(p0, a, s, f->Gg, &walked);
+        });
+      } else {
+        return static_cast<int>(PR_OK);
+      }
+    });
+    if (rc != PR_OK) return rc;
+    if (!walked) {
+      set_error("fused gridding needs the segment walk (J <= 4, tile fitting LDS)");
+      return PR_EUNSUPPORTED;
+    }
+    PR_TRY_LAUNCH();
+  }
+  merge_patches_kernel<R><<<f->tiles, p0->T * p0->T < kThreads ? p0->T * p0->T : kThreads, 0, s>>>(
+      nullptr, nullptr, nullptr, 0, p0->T, p0->P, 0, p0->J, static_cast<const MergeArgs<R>*>(f->d_mg),
+      static_cast<int>(f->plans.size()));
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
 template <typename R>
 __global__ void zero_cx_kernel(cx_t<R>* a, int64_t n) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -1502,6 +1715,22 @@ int phi_section_kappa(pr_phi_plan_t* p, int nsec, const double* eps, double* kap
   section_kappa_partials_kernel<<<nsec, kThreads, 0, s>>>(p->partials, degrid_blocks(p), eps, kappa, norm2);
   PR_TRY_LAUNCH();
   return PR_OK;
+}
+
+size_t fused_vis_bytes(int n, int64_t items, int prec) {
+  return prec == PR_F32 ? fused_vis_bytes_t<float>(n, items) : fused_vis_bytes_t<double>(n, items);
+}
+
+int fused_vis_build(FusedStages* f, Carver& c, hipStream_t s) {
+  return f->prec == PR_F32 ? fused_vis_build_t<float>(f, c, s) : fused_vis_build_t<double>(f, c, s);
+}
+
+int fused_gw(FusedStages* f, void* const* y, hipStream_t s) {
+  return f->prec == PR_F32 ? fused_gw_t<float>(f, y, s) : fused_gw_t<double>(f, y, s);
+}
+
+int fused_gw_adjoint(FusedStages* f, const void* const* y, hipStream_t s) {
+  return f->prec == PR_F32 ? fused_gw_adjoint_t<float>(f, y, s) : fused_gw_adjoint_t<double>(f, y, s);
 }
 
 int phi_gw_adjoint_admm(pr_phi_plan_t* p, const AdmmVis& v, double scale, hipStream_t s) {

@@ -492,7 +492,7 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
 // block the loads even out by themselves and block b takes items b, b + G,
 // b + 2G, ...: the blocks running at one time then read neighbouring parts of
 // the visibility arrays (address-translation locality).
-static void lpt_schedule(const std::vector<int4>& items, int G, int64_t overhead, std::vector<int4>& sched,
+void lpt_schedule(const std::vector<int4>& items, int G, int64_t overhead, std::vector<int4>& sched,
                          std::vector<int32_t>& off) {
   auto entry = [&](int64_t i) { return make_int4(items[i].x, items[i].y, items[i].z, static_cast<int>(i)); };
   const int64_t n = static_cast<int64_t>(items.size());

@@ -135,6 +135,8 @@ _SIGS = {
     "pr_batch_phi_apply": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), _VP]),
     "pr_batch_phi_adjoint": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), _VP]),
     "pr_batch_report": (C.c_int, [_VP, _I32, C.POINTER(pr_admm_report), _VP]),
+    "pr_batch_fuse_bytes": (C.c_int, [_VP, C.POINTER(_SZ)]),
+    "pr_batch_fuse": (C.c_int, [_VP, _VP, _SZ, _VP]),
     "pr_server_job_bytes": (C.c_int, [C.POINTER(pr_job_desc), C.POINTER(_SZ)]),
     "pr_server_create": (C.c_int, [_VP, _SZ, _I32, _I32, C.POINTER(_VP)]),
     "pr_server_destroy": (C.c_int, [_VP]),
@@ -436,6 +438,17 @@ def pr_batch_report(b, slot: int, stream=None) -> pr_admm_report:
     rep = pr_admm_report()
     _check(lib().pr_batch_report(b, slot, C.byref(rep), stream if stream is not None else _stream()))
     return rep
+
+
+def pr_batch_fuse_bytes(b) -> int:
+    v = _SZ()
+    _check(lib().pr_batch_fuse_bytes(b, C.byref(v)))
+    return v.value
+
+
+def pr_batch_fuse(b, workspace, stream=None):
+    _check(lib().pr_batch_fuse(b, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                               stream if stream is not None else _stream()))
 
 
 def pr_server_job_bytes(desc: pr_job_desc) -> int:
@@ -762,6 +775,12 @@ class Batch:
 
     def step(self, iters=1, use_graph=True):
         pr_batch_step(self.handle, iters, use_graph)
+
+    def fuse(self, device="cuda"):
+        """One launch per operator stage for pr_batch_phi_apply / _adjoint over
+        the current members (the workspace is kept by this object)."""
+        self._fuse_ws = _workspace(max(256, pr_batch_fuse_bytes(self.handle)), torch.device(device))
+        pr_batch_fuse(self.handle, self._fuse_ws)
 
     def report(self, slot: int) -> pr_admm_report:
         return pr_batch_report(self.handle, slot)
