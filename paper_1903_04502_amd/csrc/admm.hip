@@ -149,6 +149,7 @@ int admm_step(AdmmJob* j, hipStream_t s) {
 }
 
 int admm_report(AdmmJob* j, pr_admm_report* rep, hipStream_t s) {
+  PR_TRY(no_capture(s, "the report"));
   pr_phi_plan_t* phi = j->phi;
   pr_psi_plan_t* psi = j->psi;
   const int64_t n2 = static_cast<int64_t>(phi->n) * phi->n;
@@ -199,6 +200,7 @@ namespace {
 // (or fewer once the relative change drops below rel_tol), then the device
 // iteration count advances by the steps taken.
 int admm_run(AdmmJob& j, const pr_admm_params& prm, pr_admm_report* rep, hipStream_t s) {
+  if (prm.rel_tol > 0 || rep) PR_TRY(no_capture(s, "an ADMM solve with rel_tol or a report"));
   double host_sums[kSumSlots] = {0};
   const int start = j.iters_done;
   for (int it = 0; it < prm.iters; ++it) {
@@ -296,6 +298,7 @@ size_t admm_state_bytes(const pr_phi_plan_t* phi, const pr_psi_plan_t* psi) { re
 
 int admm_state_export(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* ws, const void* x, void* state,
                       hipStream_t s) {
+  PR_TRY(no_capture(s, "pr_admm_state_export"));
   AdmmWs w{};
   admm_layout(phi, psi, const_cast<void*>(ws), &w);
   const StateParts p = state_parts(phi, psi);
@@ -314,6 +317,7 @@ int admm_state_export(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* ws, co
 
 int admm_state_import(pr_phi_plan_t* phi, pr_psi_plan_t* psi, const void* state, void* ws, void* x,
                       hipStream_t s) {
+  PR_TRY(no_capture(s, "pr_admm_state_import"));
   const char* src = static_cast<const char*>(state);
   StateHeader h{};
   PR_TRY_HIP(hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDefault, s));

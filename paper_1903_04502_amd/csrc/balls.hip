@@ -241,6 +241,7 @@ int pr_balls_create(int64_t M, int32_t nsec, const int32_t* section, void* persi
   }
   PR_TRY(check_sticky());
   hipStream_t s = as_stream(stream);
+  PR_TRY(no_capture(s, "pr_balls_create"));
   BallsLayout L;
   BallsScratch S;
   balls_layout(M, nsec, persistent, &L);
@@ -309,6 +310,7 @@ int pr_balls_norms(pr_balls b, double* norms, void* stream) {
   PR_NONNULL(b);
   PR_NONNULL(norms);
   hipStream_t s = as_stream(stream);
+  PR_TRY(no_capture(s, "pr_balls_norms"));
   std::vector<double> n2(static_cast<size_t>(b->nsec));
   PR_TRY_HIP(hipMemcpyAsync(n2.data(), b->norm2, n2.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   PR_TRY_HIP(hipStreamSynchronize(s));
@@ -338,6 +340,7 @@ int pr_admm_local_solve(pr_phi_plan phi, pr_psi_plan psi, pr_balls balls, const 
   PR_TRY(admm_check_params(&prm));
   PR_TRY(check_sticky());
   hipStream_t s = as_stream(stream);
+  PR_TRY(no_capture(s, "pr_admm_local_solve"));
   // the radii go to the device before the call returns (the caller's array may be freed)
   PR_TRY_HIP(hipMemcpyAsync(balls->eps, eps, balls->nsec * sizeof(double), hipMemcpyHostToDevice, s));
   PR_TRY_HIP(hipStreamSynchronize(s));

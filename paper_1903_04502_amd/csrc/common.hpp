@@ -53,6 +53,23 @@ inline int check_sticky() {
   return PR_OK;
 }
 
+// Calls that copy to or from host memory and wait for the stream refuse a
+// stream under graph capture: a captured copy would replay into whatever the
+// host address holds later (a stack frame or a freed buffer).
+inline int no_capture(hipStream_t s, const char* what) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(s, &st);
+  if (e != hipSuccess) {
+    set_error("%s: hipStreamIsCapturing: %s", what, hipGetErrorString(e));
+    return PR_EHIP;
+  }
+  if (st != hipStreamCaptureStatusNone) {
+    set_error("%s reads results back to the host: not allowed on a stream under graph capture", what);
+    return PR_EINVAL;
+  }
+  return PR_OK;
+}
+
 // Bump allocator over a caller-provided workspace. With base == nullptr it
 // only measures, so size queries and carving share one code path.
 struct Carver {

@@ -224,6 +224,7 @@ size_t ball_scratch_bytes() { return (kRedBlocks + 8) * sizeof(double); }
 
 int proj_l2ball(const void* in, const void* center, void* out, int64_t len, int prec, double eps, void* scratch,
                 double* dist, hipStream_t s) {
+  if (dist) PR_TRY(no_capture(s, "the ball projection with a host distance"));
   double* partials = static_cast<double*>(scratch);
   double* d2 = partials + kRedBlocks;
   // ||in - center||^2 over the real and imaginary parts: 2 len real values
@@ -326,6 +327,7 @@ int phi_norm_device(pr_phi_plan_t* p, int iters, void* vis, double* inv_norm, hi
 }
 
 int phi_norm(pr_phi_plan_t* p, int iters, double rtol, void* vis, double* norm, hipStream_t s) {
+  PR_TRY(no_capture(s, "pr_phi_norm"));
   const int64_t N = static_cast<int64_t>(p->n) * p->n;
   double* s2 = p->scalars + 8;
   PR_TRY(fill_real(p->img_a, N, p->prec, 1.0 / p->n, s));

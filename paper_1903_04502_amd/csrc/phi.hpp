@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "host/schedule.hpp"
 
 struct pr_phi_plan_t {
   pr_phi_desc desc;
@@ -75,14 +76,6 @@ int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s);
 // Set the LDS limits of the plan's gridding kernels (once per process and
 // device), so that later launches, also under stream capture, set nothing.
 int phi_gridding_setup(pr_phi_plan_t* p);
-
-// Block schedule of work items over G blocks (fixed, so sums keep their order
-// from launch to launch): longest first onto the least loaded block when there
-// are fewer than 8 items per block, else block b takes items b, b + G, ...
-// Each scheduled entry carries its item's index in .w; off[b] .. off[b + 1]
-// are block b's entries.
-void lpt_schedule(const std::vector<int4>& items, int G, int64_t overhead, std::vector<int4>& sched,
-                  std::vector<int32_t>& off);
 
 // Stable LSD radix sort of M (key, value) pairs on the low `bits` bits of the
 // keys, ping-ponging between (k0, v0) and (k1, v1); *kout / *vout name the

@@ -484,48 +484,6 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   return PR_OK;
 }
 
-// Block schedule of the work items over G blocks, fixed at plan time (so
-// every launch, and its floating-point summation order, is the same).
-// With few items per block, longest-processing-time: items in decreasing cost
-// (visibilities plus a per-item overhead, ties by index) each go to the block
-// with the least load so far (ties to the lower block). With many items per
-// block the loads even out by themselves and block b takes items b, b + G,
-// b + 2G, ...: the blocks running at one time then read neighbouring parts of
-// the visibility arrays (address-translation locality).
-void lpt_schedule(const std::vector<int4>& items, int G, int64_t overhead, std::vector<int4>& sched,
-                         std::vector<int32_t>& off) {
-  auto entry = [&](int64_t i) { return make_int4(items[i].x, items[i].y, items[i].z, static_cast<int>(i)); };
-  const int64_t n = static_cast<int64_t>(items.size());
-  if (n >= 8 * static_cast<int64_t>(G)) {
-    sched.clear();
-    off.assign(static_cast<size_t>(G) + 1, 0);
-    for (int b = 0; b < G; ++b) {
-      for (int64_t i = b; i < n; i += G) sched.push_back(entry(i));
-      off[b + 1] = static_cast<int32_t>(sched.size());
-    }
-    return;
-  }
-  std::vector<int32_t> order(static_cast<size_t>(n));
-  for (int64_t i = 0; i < n; ++i) order[i] = static_cast<int32_t>(i);
-  auto cost = [&](int32_t i) { return static_cast<int64_t>(items[i].z - items[i].y) + overhead; };
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
-  using Load = std::pair<int64_t, int>;
-  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-  for (int b = 0; b < G; ++b) heap.push(Load(0, b));
-  std::vector<std::vector<int32_t>> per(static_cast<size_t>(G));
-  for (int32_t i : order) {
-    Load l = heap.top();
-    heap.pop();
-    per[l.second].push_back(i);
-    heap.push(Load(l.first + cost(i), l.second));
-  }
-  sched.clear();
-  off.assign(static_cast<size_t>(G) + 1, 0);
-  for (int b = 0; b < G; ++b) {
-    for (int32_t i : per[b]) sched.push_back(entry(i));
-    off[b + 1] = static_cast<int32_t>(sched.size());
-  }
-}
 
 static int build_schedules(pr_phi_plan_t* p, hipStream_t s) {
   const int64_t n = p->nItems;
@@ -619,6 +577,7 @@ static int create_impl(pr_phi_plan_t* p, const R* uv, const R* w, hipStream_t s)
 }
 
 int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s) {
+  PR_TRY(no_capture(s, "plan creation"));
   PR_TRY(phi_gridding_setup(p));
   if (p->prec == PR_F32)
     return create_impl<float>(p, static_cast<const float*>(uv), static_cast<const float*>(w), s);

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "admm.hpp"
+#include "host/arena.hpp"
 #include "ops.hpp"
 
 namespace pr {
@@ -113,7 +114,7 @@ struct pr_server_t {
   };
   char* arena = nullptr;
   size_t arena_bytes = 0;
-  std::map<size_t, size_t> free_list;   // offset -> length
+  pr::ArenaFreeList free_list;          // free byte ranges of the arena
   int max_active = 0;
   int active = 0;
   std::vector<hipStream_t> streams;
@@ -127,35 +128,9 @@ struct pr_server_t {
 namespace pr {
 namespace {
 
-bool arena_alloc(pr_server_t* s, size_t bytes, size_t* off) {
-  for (auto it = s->free_list.begin(); it != s->free_list.end(); ++it) {
-    if (it->second >= bytes) {
-      *off = it->first;
-      const size_t rest = it->second - bytes;
-      const size_t roff = it->first + bytes;
-      s->free_list.erase(it);
-      if (rest) s->free_list[roff] = rest;
-      return true;
-    }
-  }
-  return false;
-}
+bool arena_alloc(pr_server_t* s, size_t bytes, size_t* off) { return s->free_list.alloc(bytes, off); }
 
-void arena_free(pr_server_t* s, size_t off, size_t bytes) {
-  auto it = s->free_list.emplace(off, bytes).first;
-  auto next = std::next(it);
-  if (next != s->free_list.end() && it->first + it->second == next->first) {
-    it->second += next->second;
-    s->free_list.erase(next);
-  }
-  if (it != s->free_list.begin()) {
-    auto prev = std::prev(it);
-    if (prev->first + prev->second == it->first) {
-      prev->second += it->second;
-      s->free_list.erase(it);
-    }
-  }
-}
+void arena_free(pr_server_t* s, size_t off, size_t bytes) { s->free_list.release(off, bytes); }
 
 void release(pr_server_t* s, pr_server_t::Job* j) {
   if (j->phi) pr_phi_plan_destroy(j->phi);
@@ -244,7 +219,7 @@ int pr_server_create(void* arena, size_t arena_bytes, int32_t max_active, int32_
   if (!s) { set_error("out of host memory"); return PR_EINVAL; }
   s->arena = static_cast<char*>(arena);
   s->arena_bytes = arena_bytes & ~size_t(255);
-  s->free_list[0] = s->arena_bytes;
+  s->free_list.reset(s->arena_bytes);
   s->max_active = max_active;
   hipError_t e = hipStreamCreateWithFlags(&s->adm, hipStreamNonBlocking);
   for (int k = 0; e == hipSuccess && k < nstreams; ++k) {
@@ -413,13 +388,8 @@ int pr_server_fetch(pr_server s, int64_t job_id, void* x_out, pr_admm_report* re
 int pr_server_free_bytes(pr_server s, size_t* free_bytes, size_t* largest) {
   clear_error();
   PR_NONNULL(s);
-  size_t f = 0, l = 0;
-  for (const auto& kv : s->free_list) {
-    f += kv.second;
-    l = std::max(l, kv.second);
-  }
-  if (free_bytes) *free_bytes = f;
-  if (largest) *largest = l;
+  if (free_bytes) *free_bytes = s->free_list.free_bytes();
+  if (largest) *largest = s->free_list.largest();
   return PR_OK;
 }
 
