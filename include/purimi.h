@@ -90,7 +90,14 @@ typedef struct {
   int32_t interp;     /* kernel lookup (Section "Kernel Pre-Sampling"):
                          0 = nearest sample (zeroth order), 1 = linear
                          between the two samples around the tap distance
-                         (first order)                                       */
+                         (first order), 2 = nearest sample with the taps
+                         recomputed from (u, v) in every launch. With 0, an
+                         FP32 plan whose tile is at most 16 cells and whose
+                         D is at most 2047 stores, per visibility, the
+                         sample indices of its taps (32 bits) beside w
+                         instead of (u, v, w): the same samples, so results
+                         equal to those of 2 bitwise; other plans keep the
+                         triples. Any other value: PR_EINVAL.              */
 } pr_phi_desc;
 
 typedef struct pr_phi_plan_t* pr_phi_plan;
@@ -589,6 +596,11 @@ int pr_server_job_state(pr_server s, int64_t job_id, int32_t* state,
  * `stream` and release the job's arena memory. */
 int pr_server_fetch(pr_server s, int64_t job_id, void* x_out,
                     pr_admm_report* rep, void* stream);
+/* Cancel a job in any state: a queued job leaves the queue; a running job is
+ * given no further iterations, the call waits for the ones in flight (on the
+ * job's own stream) and releases its arena memory; a finished or failed job
+ * is released without a fetch. The id is unknown afterwards. */
+int pr_server_cancel(pr_server s, int64_t job_id);
 int pr_server_free_bytes(pr_server s, size_t* free_bytes, size_t* largest);
 
 #ifdef __cplusplus

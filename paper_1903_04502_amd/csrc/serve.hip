@@ -385,6 +385,26 @@ int pr_server_fetch(pr_server s, int64_t job_id, void* x_out, pr_admm_report* re
   return PR_OK;
 }
 
+int pr_server_cancel(pr_server s, int64_t job_id) {
+  clear_error();
+  PR_NONNULL(s);
+  auto it = s->jobs.find(job_id);
+  if (it == s->jobs.end()) { set_error("no job %lld", static_cast<long long>(job_id)); return PR_EINVAL; }
+  pr_server_t::Job* j = it->second;
+  if (j->state == 0) {
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), job_id), s->queue.end());
+  } else if (j->state == 1) {
+    // no further iterations; the ones in flight finish on the job's stream
+    if (j->enq > 0) PR_TRY_HIP(hipEventSynchronize(j->ev[(j->enq - 1) % kDepth]));
+    --s->active;
+    s->load[j->stream] -= j->cost * j->d.params.iters;
+  }
+  release(s, j);
+  delete j;
+  s->jobs.erase(it);
+  return PR_OK;
+}
+
 int pr_server_free_bytes(pr_server s, size_t* free_bytes, size_t* largest) {
   clear_error();
   PR_NONNULL(s);

@@ -144,6 +144,7 @@ _SIGS = {
     "pr_server_tick": (C.c_int, [_VP, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32)]),
     "pr_server_job_state": (C.c_int, [_VP, _I64, C.POINTER(_I32), C.POINTER(_I32)]),
     "pr_server_fetch": (C.c_int, [_VP, _I64, _VP, C.POINTER(pr_admm_report), _VP]),
+    "pr_server_cancel": (C.c_int, [_VP, C.c_int64]),
     "pr_server_free_bytes": (C.c_int, [_VP, C.POINTER(_SZ), C.POINTER(_SZ)]),
 }
 
@@ -492,6 +493,10 @@ def pr_server_fetch(srv, job_id: int, x_out=None, want_report=True, stream=None)
     return rep if want_report else None
 
 
+def pr_server_cancel(srv, job_id: int):
+    _check(lib().pr_server_cancel(srv, int(job_id)))
+
+
 def pr_server_free_bytes(srv):
     f, l = _SZ(), _SZ()
     _check(lib().pr_server_free_bytes(srv, C.byref(f), C.byref(l)))
@@ -825,6 +830,10 @@ class Server:
         x = torch.empty((n, n), dtype=dtype, device=self.arena.device)
         rep = pr_server_fetch(self.handle, jid, x, want_report)
         return x, rep
+
+    def cancel(self, jid: int):
+        pr_server_cancel(self.handle, jid)
+        self._inputs.pop(jid, None)
 
     def __del__(self):
         h = getattr(self, "handle", None)

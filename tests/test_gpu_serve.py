@@ -166,3 +166,54 @@ def test_served_fp64_job_matches_oracle(P):
     x, rep = srv.fetch(j, w.n, dtype=torch.float64)
     assert rep.op_norm == pytest.approx(nrm, rel=1e-12)
     assert rel_l2(x.cpu().numpy(), x_ref) <= 1e-10
+
+
+def test_cancel_queued_and_running_jobs(P):
+    """A queued job leaves the queue, a running one is stopped and its arena
+    memory released; the other jobs still give their solo results bitwise."""
+    say("serve cancel")
+    reqs = [request(P, *j) for j in (JOBS[2], JOBS[0], JOBS[1])]    # largest first
+    # solo results
+    solo = []
+    for r in reqs:
+        s1 = P.Server(1 << 30, max_active=4, nstreams=2)
+        j = s1.submit(r["desc"], keep=(r["uv_d"], r["y_d"]))
+        drain(s1, [j])
+        solo.append(s1.fetch(j, r["n"])[0])
+    need = [P.pr_server_job_bytes(r["desc"]) for r in reqs]
+    # the first (largest) job fits; what it leaves is less than the smallest job
+    srv = P.Server(need[0] + (min(need) // 2 & ~255), max_active=4, nstreams=2)
+    total, _ = P.pr_server_free_bytes(srv.handle)
+    ids = [srv.submit(r["desc"], keep=(r["uv_d"], r["y_d"])) for r in reqs]
+    srv.tick()
+    assert [srv.state(j) for j in ids] == [1, 0, 0]
+    srv.cancel(ids[1])                                  # queued
+    with pytest.raises(P.PrError):
+        srv.state(ids[1])
+    srv.cancel(ids[0])                                  # running
+    with pytest.raises(P.PrError):
+        srv.state(ids[0])
+    assert P.pr_server_free_bytes(srv.handle)[0] == total
+    drain(srv, [ids[2]])
+    x, rep = srv.fetch(ids[2], reqs[2]["n"])
+    assert torch.equal(x, solo[2]) and rep.nonfinite == 0
+    with pytest.raises(P.PrError):
+        srv.cancel(ids[2])                              # fetched: unknown
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_nonfinite_data_is_flagged(P, bad):
+    """A NaN or an infinity in the observed visibilities reaches the FP64
+    diagnostics: the report says so instead of returning a silent image."""
+    say(f"nonfinite flag {bad}")
+    x, uv, _, spec = problem(32, 3000, seed=7, prec="f32")
+    plan, perm = make_plan(P, 32, uv, None, 4, 2000, "f32")
+    psi = P.PsiPlan(32, 3, 0x1FF, P.PR_F32, DEV)
+    y = plan.apply(to_dev(x, torch.float32))
+    prm = P.admm_params(0.1 * float(torch.linalg.vector_norm(y).item()), 1e-3, iters=3, op_norm=1.0)
+    _, rep = P.admm_solve(plan, psi, y, prm)
+    assert rep.nonfinite == 0
+    y_bad = y.clone()
+    y_bad[1234] = complex(bad, 0.0)
+    _, rep = P.admm_solve(plan, psi, y_bad, prm)
+    assert rep.nonfinite != 0
