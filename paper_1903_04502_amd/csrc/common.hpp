@@ -88,6 +88,20 @@ struct Carver {
 
 inline bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
+// Pointers read from a table in device memory are generic to the compiler,
+// which then emits flat loads and stores; those also count against the LDS
+// wait counter, so each wait on an LDS read would wait for memory as well.
+// The tables hold global-memory pointers: read them as such. (A kernel that
+// chose at run time between such a pointer and a kernel argument would make
+// the argument generic too: the kernels that take tables are separate
+// instances.)
+template <typename T>
+__device__ __forceinline__ T* global_ptr_at(T* const* slot) {
+  using G = __attribute__((address_space(1))) T*;
+  const G g = (G)(*reinterpret_cast<const uintptr_t*>(slot));
+  return (T*)g;
+}
+
 template <typename R> struct Cx;
 template <> struct Cx<float> { using T = float2; };
 template <> struct Cx<double> { using T = double2; };

@@ -24,7 +24,7 @@ constexpr int kFftThreads = 256;
 // of the block cooperate on the W lines; each stage reads every butterfly's
 // inputs into registers, synchronises, then writes (in place).
 template <typename R, bool INV, int PB4>
-__device__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t<R>* __restrict__ tw) {
+__device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t<R>* __restrict__ tw) {
   using C = cx_t<R>;
   const int tid = threadIdx.x, nth = blockDim.x;
   int Ns = 1;
@@ -142,35 +142,64 @@ struct FftPtrs {
 
 namespace {
 
-// Forward row pass: image rows -> S Z -> FFT along u -> A.
-template <typename R>
+// Moves `count` elements between global memory and LDS, element e by
+// thread e mod blockDim.x. A batch of U elements per thread issues all its
+// loads before its first store, so a thread waits for memory once per batch
+// instead of once per element.
+template <int U, typename T, typename Ld, typename St>
+__device__ __forceinline__ void batched_move(int count, Ld ld, St st) {
+  const int nth = blockDim.x;
+  for (int base = threadIdx.x; base < count; base += U * nth) {
+    T r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * nth;
+      if (e < count) r[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * nth;
+      if (e < count) st(e, r[u]);
+    }
+  }
+}
+
+// Elements in flight per thread in the global <-> LDS moves.
+template <typename R> struct MoveCfg;
+template <> struct MoveCfg<float> { static constexpr int U = 16; };
+template <> struct MoveCfg<double> { static constexpr int U = 8; };
+
+// Forward row pass: image rows -> S Z -> FFT along u -> A. Grid columns
+// [n/2, K - n/2) of a line receive no pixel and are zeroed; the others are
+// written by the load, so the two need no barrier between them.
+template <typename R, bool FUSED = false>
 __global__ __launch_bounds__(kFftThreads) void fzs_rows_kernel(const R* __restrict__ x, const R* __restrict__ corr,
                                                              const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ A,
                                                              int n, int K, int logK, int W, int LS,
                                                              const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  if (mp) {
-    const FftPtrs<R>& m = mp[blockIdx.y];
-    x = m.x; corr = m.corr; tw = m.tw; A = m.A;
+  constexpr int U = MoveCfg<R>::U;
+  if constexpr (FUSED) {
+    const FftPtrs<R>* m = mp + blockIdx.y;
+    x = global_ptr_at(&m->x); corr = global_ptr_at(&m->corr); tw = global_ptr_at(&m->tw); A = global_ptr_at(&m->A);
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
+  const int logn = logK - 1, h = n >> 1;
   const int row0 = blockIdx.x * W;
   const int lines = min(W, n - row0);
-  for (int i = threadIdx.x; i < lines * LS; i += blockDim.x) buf[i] = cmk<C>(R(0), R(0));
-  __syncthreads();
-  for (int i = threadIdx.x; i < lines * n; i += blockDim.x) {
-    const int l = i / n, ix = i - l * n;
-    const int iy = row0 + l;
-    const int gx = (ix - n / 2) & (K - 1);
-    buf[l * LS + gx] = cmk<C>(x[static_cast<int64_t>(iy) * n + ix] * corr[ix] * corr[iy], R(0));
-  }
+  for (int i = threadIdx.x; i < lines * n; i += blockDim.x)
+    buf[(i >> logn) * LS + h + (i & (n - 1))] = cmk<C>(R(0), R(0));
+  const R* xr = x + static_cast<int64_t>(row0) * n;
+  batched_move<U, R>(
+      lines * n,
+      [&](int e) { return xr[e] * corr[e & (n - 1)] * corr[row0 + (e >> logn)]; },
+      [&](int e, R v) { buf[(e >> logn) * LS + (((e & (n - 1)) - h) & (K - 1))] = cmk<C>(v, R(0)); });
   __syncthreads();
   fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
-  for (int i = threadIdx.x; i < lines * K; i += blockDim.x) {
-    const int l = i / K, k = i - l * K;
-    A[static_cast<int64_t>(row0 + l) * K + k] = buf[l * LS + k];
-  }
+  C* Ar = A + static_cast<int64_t>(row0) * K;
+  batched_move<U, C>(
+      lines * K, [&](int e) { return buf[(e >> logK) * LS + (e & (K - 1))]; }, [&](int e, C v) { Ar[e] = v; });
 }
 
 // Column groups are laid out so that blocks on one XCD (blockIdx mod 8) take
@@ -181,65 +210,69 @@ __device__ inline int xcd_group(int b, int nb) {
 }
 
 // Forward column pass: A (n nonzero rows at p mod K) -> FFT along v -> grid.
-template <typename R>
+// W (a power of two, 2^logW) columns per block; element e of a row-major
+// sweep is row e >> logW, column e & (W - 1).
+template <typename R, bool FUSED = false>
 __global__ __launch_bounds__(kFftThreads) void fzs_cols_kernel(const cx_t<R>* __restrict__ A,
                                                              const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ grid,
                                                              int n, int K, int logK, int W, int LS,
                                                              const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  if (mp) {
-    const FftPtrs<R>& m = mp[blockIdx.y];
-    A = m.A; tw = m.tw; grid = m.grid;
+  constexpr int U = MoveCfg<R>::U;
+  if constexpr (FUSED) {
+    const FftPtrs<R>* m = mp + blockIdx.y;
+    A = global_ptr_at(&m->A); tw = global_ptr_at(&m->tw); grid = global_ptr_at(&m->grid);
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
+  const int logn = logK - 1, h = n >> 1, logW = __builtin_ctz(W);
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
-  for (int i = threadIdx.x; i < W * LS; i += blockDim.x) buf[i] = cmk<C>(R(0), R(0));
-  __syncthreads();
-  for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
-    const int iy = i / W, l = i - iy * W;
-    const int gy = (iy - n / 2) & (K - 1);
-    buf[l * LS + gy] = A[static_cast<int64_t>(iy) * K + kx0 + l];
-  }
+  for (int i = threadIdx.x; i < W * n; i += blockDim.x)
+    buf[(i >> logn) * LS + h + (i & (n - 1))] = cmk<C>(R(0), R(0));
+  const C* Ac = A + kx0;
+  batched_move<U, C>(
+      n * W, [&](int e) { return Ac[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))]; },
+      [&](int e, C v) { buf[(e & (W - 1)) * LS + (((e >> logW) - h) & (K - 1))] = v; });
   __syncthreads();
   fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
-  for (int i = threadIdx.x; i < K * W; i += blockDim.x) {
-    const int ky = i / W, l = i - ky * W;
-    grid[static_cast<int64_t>(ky) * K + kx0 + l] = buf[l * LS + ky];
-  }
+  C* gc = grid + kx0;
+  batched_move<U, C>(
+      K * W, [&](int e) { return buf[(e & (W - 1)) * LS + (e >> logW)]; },
+      [&](int e, C v) { gc[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))] = v; });
 }
 
 // Adjoint column pass: grid -> inverse FFT along v -> keep the n rows at p mod K -> A.
-template <typename R>
+template <typename R, bool FUSED = false>
 __global__ __launch_bounds__(kFftThreads) void fzs_adj_cols_kernel(const cx_t<R>* __restrict__ grid,
                                                                  const cx_t<R>* __restrict__ tw,
                                                                  cx_t<R>* __restrict__ A, int n, int K, int logK,
                                                                  int W, int LS, const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  if (mp) {
-    const FftPtrs<R>& m = mp[blockIdx.y];
-    grid = m.grid; tw = m.tw; A = m.A;
+  constexpr int U = MoveCfg<R>::U;
+  if constexpr (FUSED) {
+    const FftPtrs<R>* m = mp + blockIdx.y;
+    grid = global_ptr_at(&m->grid); tw = global_ptr_at(&m->tw); A = global_ptr_at(&m->A);
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
+  const int h = n >> 1, logW = __builtin_ctz(W);
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
-  for (int i = threadIdx.x; i < K * W; i += blockDim.x) {
-    const int ky = i / W, l = i - ky * W;
-    buf[l * LS + ky] = grid[static_cast<int64_t>(ky) * K + kx0 + l];
-  }
+  const C* gc = grid + kx0;
+  batched_move<U, C>(
+      K * W, [&](int e) { return gc[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))]; },
+      [&](int e, C v) { buf[(e & (W - 1)) * LS + (e >> logW)] = v; });
   __syncthreads();
   fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
-  for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
-    const int iy = i / W, l = i - iy * W;
-    const int gy = (iy - n / 2) & (K - 1);
-    A[static_cast<int64_t>(iy) * K + kx0 + l] = buf[l * LS + gy];
-  }
+  C* Ac = A + kx0;
+  batched_move<U, C>(
+      n * W, [&](int e) { return buf[(e & (W - 1)) * LS + (((e >> logW) - h) & (K - 1))]; },
+      [&](int e, C v) { Ac[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))] = v; });
 }
 
 // Adjoint row pass: A rows -> inverse FFT along u -> crop, correct, real part.
 // MODE 0: x = Re(.). MODE 1 (gradient step of Algorithm 1):
 // x_out = x_in - rho Re(.), zbar = max(x_out, 0).
-template <typename R, int MODE>
+template <typename R, int MODE, bool FUSED = false>
 __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>* __restrict__ A,
                                                                  const R* __restrict__ corr,
                                                                  const cx_t<R>* __restrict__ tw, R* __restrict__ x_out,
@@ -247,34 +280,40 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>
                                                                  R rho, int n, int K, int logK, int W, int LS,
                                                                  const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  if (mp) {   // plain adjoint only (MODE 0)
-    const FftPtrs<R>& m = mp[blockIdx.y];
-    A = m.A; corr = m.corr; tw = m.tw; x_out = m.x_out;
+  constexpr int U = MoveCfg<R>::U;
+  if constexpr (FUSED) {   // plain adjoint only (MODE 0)
+    const FftPtrs<R>* m = mp + blockIdx.y;
+    A = global_ptr_at(&m->A); corr = global_ptr_at(&m->corr); tw = global_ptr_at(&m->tw);
+    x_out = global_ptr_at(&m->x_out);
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
+  const int logn = logK - 1, h = n >> 1;
   const int row0 = blockIdx.x * W;
   const int lines = min(W, n - row0);
-  for (int i = threadIdx.x; i < lines * K; i += blockDim.x) {
-    const int l = i / K, k = i - l * K;
-    buf[l * LS + k] = A[static_cast<int64_t>(row0 + l) * K + k];
-  }
+  const C* Ar = A + static_cast<int64_t>(row0) * K;
+  batched_move<U, C>(
+      lines * K, [&](int e) { return Ar[e]; }, [&](int e, C v) { buf[(e >> logK) * LS + (e & (K - 1))] = v; });
   __syncthreads();
   fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
-  for (int i = threadIdx.x; i < lines * n; i += blockDim.x) {
-    const int l = i / n, ix = i - l * n;
-    const int iy = row0 + l;
-    const int gx = (ix - n / 2) & (K - 1);
-    const R val = buf[l * LS + gx].x * corr[ix] * corr[iy];
-    const int64_t o = static_cast<int64_t>(iy) * n + ix;
-    if (MODE == 0) {
-      x_out[o] = val;
-    } else {
-      const R xo = x_in[o] - rho * val;
-      x_out[o] = xo;
-      zbar[o] = xo > R(0) ? xo : R(0);
-    }
-  }
+  const int64_t o0 = static_cast<int64_t>(row0) * n;
+  // (pixel value, x_in) per element; x_in is read only by MODE 1
+  batched_move<U, C>(
+      lines * n,
+      [&](int e) {
+        const int l = e >> logn, ix = e & (n - 1);
+        const R val = buf[l * LS + ((ix - h) & (K - 1))].x * corr[ix] * corr[row0 + l];
+        return cmk<C>(val, MODE == 0 ? R(0) : x_in[o0 + e]);
+      },
+      [&](int e, C v) {
+        if (MODE == 0) {
+          x_out[o0 + e] = v.x;
+        } else {
+          const R xo = v.y - rho * v.x;
+          x_out[o0 + e] = xo;
+          zbar[o0 + e] = xo > R(0) ? xo : R(0);
+        }
+      });
 }
 
 template <typename R>
@@ -385,10 +424,10 @@ int fused_fzs_t(FusedStages* f, const void* const* x, hipStream_t s) {
     lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
     lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
     const FftPtrs<R>* mp = static_cast<const FftPtrs<R>*>(k.d_fwd);
-    fzs_rows_kernel<R><<<dim3((n + Wr - 1) / Wr, cnt), Tr, static_cast<size_t>(Wr) * LSr * sizeof(C), s>>>(
+    fzs_rows_kernel<R, true><<<dim3((n + Wr - 1) / Wr, cnt), Tr, static_cast<size_t>(Wr) * LSr * sizeof(C), s>>>(
         nullptr, nullptr, nullptr, nullptr, n, K, logK, Wr, LSr, mp);
     PR_TRY_LAUNCH();
-    fzs_cols_kernel<R><<<dim3(K / Wc, cnt), Tc, static_cast<size_t>(Wc) * LSc * sizeof(C), s>>>(
+    fzs_cols_kernel<R, true><<<dim3(K / Wc, cnt), Tc, static_cast<size_t>(Wc) * LSc * sizeof(C), s>>>(
         nullptr, nullptr, nullptr, n, K, logK, Wc, LSc, mp);
     PR_TRY_LAUNCH();
   }
@@ -407,10 +446,10 @@ int fused_fzs_adjoint_t(FusedStages* f, void* const* x, hipStream_t s) {
     lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
     lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
     const FftPtrs<R>* mp = static_cast<const FftPtrs<R>*>(k.d_adj);
-    fzs_adj_cols_kernel<R><<<dim3(K / Wc, cnt), Tc, static_cast<size_t>(Wc) * LSc * sizeof(C), s>>>(
+    fzs_adj_cols_kernel<R, true><<<dim3(K / Wc, cnt), Tc, static_cast<size_t>(Wc) * LSc * sizeof(C), s>>>(
         nullptr, nullptr, nullptr, n, K, logK, Wc, LSc, mp);
     PR_TRY_LAUNCH();
-    fzs_adj_rows_kernel<R, 0><<<dim3((n + Wr - 1) / Wr, cnt), Tr, static_cast<size_t>(Wr) * LSr * sizeof(C), s>>>(
+    fzs_adj_rows_kernel<R, 0, true><<<dim3((n + Wr - 1) / Wr, cnt), Tr, static_cast<size_t>(Wr) * LSr * sizeof(C), s>>>(
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, R(0), n, K, logK, Wr, LSr, mp);
     PR_TRY_LAUNCH();
   }

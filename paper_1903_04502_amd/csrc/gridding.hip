@@ -135,7 +135,7 @@ struct GwArgs {
 
 constexpr int kDegridPer = 4;   // visibilities per thread per chunk
 
-template <typename R, int J, int MODE, bool TAB_LDS, int LK>
+template <typename R, int J, int MODE, bool TAB_LDS, int LK, bool FUSED = false>
 __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   using C = cx_t<R>;
   constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
@@ -145,8 +145,24 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   const int tid = threadIdx.x;
   C* patch = reinterpret_cast<C*>(smem_raw);
   const int P = a.P, T = a.T;          // the same for every member of a fused launch
-  // the arguments of the plan an item belongs to
-  auto mem = [&](const int4& it) -> const GwArgs<R>& { return a.mtab ? a.mtab[item_member(it)] : a; };
+  // the arguments of the plan an item belongs to (FUSED: from the member
+  // table). The solo kernels are separate instances that read the kernel
+  // arguments only: a run-time choice between the two would leave every
+  // pointer generic, and flat accesses also count against the LDS wait
+  // counter, so each wait on an LDS read would wait for memory as well.
+  auto mem = [&](const int4& it) -> GwArgs<R> {
+    if constexpr (FUSED) {
+      const GwArgs<R>* t = a.mtab + item_member(it);
+      GwArgs<R> m = *t;
+      m.grid = global_ptr_at(&t->grid);
+      m.uv = global_ptr_at(&t->uv);
+      m.y_out = global_ptr_at(&t->y_out);
+      return m;
+    } else {
+      (void)it;
+      return a;
+    }
+  };
   double sum_t = 0.0, sum_r = 0.0;
   double sacc[MODE == 2 ? kSecAcc : 1] = {};   // MODE 2: ||t||^2 per section
   // inputs of this thread's visibilities for the current and the next chunk
@@ -172,11 +188,11 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   }
   for (int ks = kbeg; ks < kend; ++ks) {
     const int4 it = a.items[ks];
-    const GwArgs<R>& m = mem(it);
+    const GwArgs<R> m = mem(it);
     const int K = m.K;
     const int tile = item_tile(it);
     const int tv = tile >> m.lognT, tu = tile & (m.nT - 1);
-    const R iscale = a.mtab ? m.scale : scale;
+    const R iscale = FUSED ? m.scale : scale;
     if (ks > kbeg) load(m.uv, it.y, it.z, cu_, cv_, cw_);
     __syncthreads();
     const float invP = 1.0f / P;
@@ -714,7 +730,7 @@ struct WalkPrefetch {
 // the moments, and stores the total.
 // TS: the tile side when fixed at compile time (16 for the stored-tap plans:
 // moment and patch offsets become immediates), else 0 (read from the args).
-template <typename R, int J, int MODE, bool TAB_LDS, int LK, int TS>
+template <typename R, int J, int MODE, bool TAB_LDS, int LK, int TS, bool FUSED = false>
 __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   using C = cx_t<R>;
   constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
@@ -741,8 +757,20 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   const int tid = threadIdx.x;
   const R* tab = a.table;
   const int T = TS ? TS : a.T, P = TS ? TS + J - 1 : a.P;   // the same for every member of a fused launch
-  // the arguments of the plan an item belongs to
-  auto mem = [&](const int4& it) -> const GwAdjArgs<R>& { return a.mtab ? a.mtab[item_member(it)] : a; };
+  // the arguments of the plan an item belongs to (as in the degridding)
+  auto mem = [&](const int4& it) -> GwAdjArgs<R> {
+    if constexpr (FUSED) {
+      const GwAdjArgs<R>* t = a.mtab + item_member(it);
+      GwAdjArgs<R> m = *t;
+      m.uv = global_ptr_at(&t->uv);
+      m.y_in = global_ptr_at(&t->y_in);
+      m.patches = global_ptr_at(&t->patches);
+      return m;
+    } else {
+      (void)it;
+      return a;
+    }
+  };
   const int TT = T * T;
   R kappa_ball = 1;
   if (ADMM) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
@@ -759,7 +787,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   // base) with 32-bit item-relative offsets (items hold fewer than 2^20).
   auto issue = [&](const int4& it, int L, int q0) {
     pf.ok = 0u;
-    const GwAdjArgs<R>& m = mem(it);
+    const GwAdjArgs<R> m = mem(it);
     const int n = it.z - it.y;
     const int64_t b0 = it.y;
     const C* vi = (MODE == 0 ? m.y_in : m.t_in) + b0;
@@ -788,8 +816,8 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   // slot and only the stores are predicated, so every prefetched register is
   // consumed on every path (no conservative waits on them later).
   auto commit = [&](const int4& it, int L, int q0, int h) {
-    const GwAdjArgs<R>& m = mem(it);
-    const R iscale = a.mtab ? m.scale : scale;
+    const GwAdjArgs<R> m = mem(it);
+    const R iscale = FUSED ? m.scale : scale;
 #pragma unroll
     for (int r = 0; r < PF; ++r) {
       const bool ok = ((pf.ok >> r) & 1u) && lane_h == h;
@@ -845,7 +873,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     const bool has_next = ks + 1 < kend;
     const int4 itn = has_next ? a.items[ks + 1] : make_int4(0, 0, 0, 0);
     const int Ln = seg_len(itn);
-    const GwAdjArgs<R>& mi = mem(it);
+    const GwAdjArgs<R> mi = mem(it);
     const int K = mi.K;
     const int tile = item_tile(it);
     const int tv = tile >> mi.lognT, tu = tile & (mi.nT - 1);
@@ -1097,13 +1125,13 @@ struct MergeArgs {
   int K, nT, tile0, pad;
 };
 
-template <typename R>
+template <typename R, bool FUSED = false>
 __global__ void merge_patches_kernel(const cx_t<R>* __restrict__ patches, const int32_t* __restrict__ item_off,
                                      cx_t<R>* __restrict__ grid, int K, int T, int P, int nT, int J,
                                      const MergeArgs<R>* __restrict__ mtab, int nmembers) {
   using C = cx_t<R>;
   int t = blockIdx.x;
-  if (mtab) {
+  if constexpr (FUSED) {
     // the member holding this block (binary search over the tile offsets)
     int lo = 0, hi = nmembers - 1;
     while (lo < hi) {
@@ -1111,9 +1139,9 @@ __global__ void merge_patches_kernel(const cx_t<R>* __restrict__ patches, const 
       if (mtab[mid].tile0 <= t) lo = mid; else hi = mid - 1;
     }
     const MergeArgs<R> m = mtab[lo];
-    patches = m.patches;
-    item_off = m.item_off;
-    grid = m.grid;
+    patches = global_ptr_at(&mtab[lo].patches);
+    item_off = global_ptr_at(&mtab[lo].item_off);
+    grid = global_ptr_at(&mtab[lo].grid);
     K = m.K;
     nT = m.nT;
     t -= m.tile0;
@@ -1218,7 +1246,7 @@ int allow_lds(K kernel, size_t bytes) {
   return PR_OK;
 }
 
-template <typename R, int J, int MODE, int LK>
+template <typename R, int J, int MODE, int LK, bool FUSED = false>
 int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s, int G = 0) {
   using C = cx_t<R>;
   const size_t patch = align16(static_cast<size_t>(p->P) * p->P * sizeof(C));
@@ -1227,10 +1255,10 @@ int launch_degrid(pr_phi_plan_t* p, GwArgs<R> a, hipStream_t s, int G = 0) {
   if (MODE >= 1 && lds < kThreads * sizeof(double)) lds = kThreads * sizeof(double);
   if (G <= 0) G = degrid_blocks(p);
   if (lds + tabb <= kLdsSoft) {
-    degrid_kernel<R, J, MODE, true, LK><<<G, kThreads, lds + tabb, s>>>(a);
+    degrid_kernel<R, J, MODE, true, LK, FUSED><<<G, kThreads, lds + tabb, s>>>(a);
   } else if (lds <= kLdsHard) {
-    PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false, LK>, lds));
-    degrid_kernel<R, J, MODE, false, LK><<<G, kThreads, lds, s>>>(a);
+    PR_TRY(allow_lds(degrid_kernel<R, J, MODE, false, LK, FUSED>, lds));
+    degrid_kernel<R, J, MODE, false, LK, FUSED><<<G, kThreads, lds, s>>>(a);
   } else {
     set_error("degridding patch of tile %d does not fit in LDS", p->T);
     return PR_EUNSUPPORTED;
@@ -1266,7 +1294,7 @@ bool pick_grid_lds(int T, int tlen, int* B, bool* tab_lds, size_t* bytes) {
 // Segment walk (J <= 4): table in LDS if that keeps two blocks per CU, or if
 // one block per CU is all that fits either way. Returns false if it does not
 // fit in LDS at all (the caller then uses the J-lane kernel).
-template <typename R, int J, int WMODE, int LK>
+template <typename R, int J, int WMODE, int LK, bool FUSED = false>
 int launch_walk(pr_phi_plan_t* p, GwAdjArgs<R>& a, hipStream_t s, int G, bool* walked) {
   const WalkLds<R, J> with(a.T, a.tlen, true), without(a.T, a.tlen, false);
   const bool tl = with.total <= kLdsSoft || (without.total > kLdsSoft && with.total <= kLdsHard);
@@ -1275,18 +1303,18 @@ int launch_walk(pr_phi_plan_t* p, GwAdjArgs<R>& a, hipStream_t s, int G, bool* w
   if (bytes > kLdsHard) return PR_OK;
   if (LK == kLkWords && a.T == 16) {
     if (tl) {
-      PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, true, LK, 16>, bytes));
-      grid_walk_kernel<R, J, WMODE, true, LK, 16><<<G, kThreads, bytes, s>>>(a);
+      PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, true, LK, 16, FUSED>, bytes));
+      grid_walk_kernel<R, J, WMODE, true, LK, 16, FUSED><<<G, kThreads, bytes, s>>>(a);
     } else {
-      PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, false, LK, 16>, bytes));
-      grid_walk_kernel<R, J, WMODE, false, LK, 16><<<G, kThreads, bytes, s>>>(a);
+      PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, false, LK, 16, FUSED>, bytes));
+      grid_walk_kernel<R, J, WMODE, false, LK, 16, FUSED><<<G, kThreads, bytes, s>>>(a);
     }
   } else if (tl) {
-    PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, true, LK, 0>, bytes));
-    grid_walk_kernel<R, J, WMODE, true, LK, 0><<<G, kThreads, bytes, s>>>(a);
+    PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, true, LK, 0, FUSED>, bytes));
+    grid_walk_kernel<R, J, WMODE, true, LK, 0, FUSED><<<G, kThreads, bytes, s>>>(a);
   } else {
-    PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, false, LK, 0>, bytes));
-    grid_walk_kernel<R, J, WMODE, false, LK, 0><<<G, kThreads, bytes, s>>>(a);
+    PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, false, LK, 0, FUSED>, bytes));
+    grid_walk_kernel<R, J, WMODE, false, LK, 0, FUSED><<<G, kThreads, bytes, s>>>(a);
   }
   *walked = true;
   return PR_OK;
@@ -1616,7 +1644,7 @@ int fused_gw_t(FusedStages* f, void* const* y, hipStream_t s) {
   a.mtab = static_cast<const GwArgs<R>*>(f->d_dg);
   return with_j(p0->J, [&](auto jj) {
     return with_lk<R>(p0, [&](auto lk) {
-      return launch_degrid<R, decltype(jj)::value, 0, decltype(lk)::value>(p0, a, s, f->Gd);
+      return launch_degrid<R, decltype(jj)::value, 0, decltype(lk)::value, true>(p0, a, s, f->Gd);
     });
   });
 }
@@ -1637,7 +1665,7 @@ int fused_gw_adjoint_t(FusedStages* f, const void* const* y, hipStream_t s) {
       constexpr int JJ = decltype(jj)::value;
       if constexpr (JJ <= 4) {
         return with_lk<R>(p0, [&](auto lk) {
-          return launch_walk<R, JJ, 0, decltype(lk)::value>(p0, a, s, f->Gg, &walked);
+          return launch_walk<R, JJ, 0, decltype(lk)::value, true>(p0, a, s, f->Gg, &walked);
         });
       } else {
         return static_cast<int>(PR_OK);
@@ -1650,7 +1678,7 @@ int fused_gw_adjoint_t(FusedStages* f, const void* const* y, hipStream_t s) {
     }
     PR_TRY_LAUNCH();
   }
-  merge_patches_kernel<R><<<f->tiles, p0->T * p0->T < kThreads ? p0->T * p0->T : kThreads, 0, s>>>(
+  merge_patches_kernel<R, true><<<f->tiles, p0->T * p0->T < kThreads ? p0->T * p0->T : kThreads, 0, s>>>(
       nullptr, nullptr, nullptr, 0, p0->T, p0->P, 0, p0->J, static_cast<const MergeArgs<R>*>(f->d_mg),
       static_cast<int>(f->plans.size()));
   PR_TRY_LAUNCH();

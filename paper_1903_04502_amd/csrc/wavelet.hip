@@ -317,6 +317,8 @@ __global__ __launch_bounds__(kTailThreads) void idwt_tail_kernel(const R* __rest
   const Filt<R>& f = filt[bi];
   const R* cb = coef + bi * n2;
   R* out = dst + bi * dst_basis_stride;
+  const __attribute__((address_space(3))) R* ll_s = (const __attribute__((address_space(3))) R*)ll;
+  const __attribute__((address_space(1))) R* cb_g = (const __attribute__((address_space(1))) R*)cb;
   int lg = lgd;
   for (int lv = 0; lv < nlev; ++lv, ++lg) {
     const int L = 1 << lg, half = L >> 1;
@@ -329,7 +331,9 @@ __global__ __launch_bounds__(kTailThreads) void idwt_tail_kernel(const R* __rest
       for (int q = 0; q < kTapsMax; ++q) {
         if (q < f.taps && ((q ^ r) & 1) == 0) {
           const int m = ((r - q) & (L - 1)) >> 1;
-          const R lo = (c < half && !deepest) ? ll[m * half + c] : cb[static_cast<int64_t>(m) * n + c];
+          // the two sources as LDS and global pointers: a choice between
+          // two generic pointers would become a flat load
+          const R lo = (c < half && !deepest) ? ll_s[m * half + c] : cb_g[static_cast<int64_t>(m) * n + c];
           const R hi = cb[static_cast<int64_t>(half + m) * n + c];
           acc += f.h[q] * lo + f.g[q] * hi;
         }
