@@ -785,7 +785,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   // are not moved and nothing waits for them before the commit.
   // Positions are addressed from the item's first visibility (a block-uniform
   // base) with 32-bit item-relative offsets (items hold fewer than 2^20).
-  auto issue = [&](const int4& it, int L, int q0) {
+  auto issue = [&](const int4& it, int L, int d, int q0) {
     pf.ok = 0u;
     const GwAdjArgs<R> m = mem(it);
     const int n = it.z - it.y;
@@ -794,8 +794,8 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 #pragma unroll
     for (int r = 0; r < PF; ++r) {
       const int q = q0 + lane_q;
-      const int o = (lane_t + r * kSegStride) * L + q;
-      const bool ok = q < L && o < n;
+      const int o = (lane_t + r * kSegStride) * L + q - d;
+      const bool ok = q < L && o >= 0 && o < n;
       pf.ok |= static_cast<unsigned>(ok) << r;
       const uint32_t oc = ok ? static_cast<uint32_t>(o) : 0u;
       if constexpr (TW) {
@@ -815,7 +815,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   // transposed (ADMM prologue applied here). The values are formed for every
   // slot and only the stores are predicated, so every prefetched register is
   // consumed on every path (no conservative waits on them later).
-  auto commit = [&](const int4& it, int L, int q0, int h) {
+  auto commit = [&](const int4& it, int L, int d, int q0, int h) {
     const GwAdjArgs<R> m = mem(it);
     const R iscale = FUSED ? m.scale : scale;
 #pragma unroll
@@ -839,7 +839,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       const C wv = cmk<C>(val.x * ws, val.y * ws);
       if (ok) {
         if (ADMM) {
-          const uint32_t o = static_cast<uint32_t>((lane_t + r * kSegStride) * L + q0 + lane_q);
+          const uint32_t o = static_cast<uint32_t>((lane_t + r * kSegStride) * L + q0 + lane_q - d);
           *byte_at(m.s_io + static_cast<int64_t>(it.y), o * static_cast<uint32_t>(sizeof(C))) = sn;
         }
         const int slot = (lane_q - h * WC) * kStagePitch + lane_t + r * kSegStride;
@@ -852,15 +852,36 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     // prefetch on its own registers
     __builtin_amdgcn_s_waitcnt(0x0F70);
   };
-  auto seg_len = [](const int4& it) { return (it.z - it.y + kThreads - 1) / kThreads; };
+  // Segments of an item: thread t owns frame positions [t L, (t + 1) L), frame
+  // position f being item position f - d. With d = 0 and L = ceil(n / 256)
+  // a prefetch of PF positions per segment starts anywhere in a 128-byte line;
+  // when an item needs two prefetches per segment, the two halves of a line
+  // would be read by different prefetches and the line fetched twice. So, for
+  // the 8-byte-per-array walks (PF values of 8 bytes fill one line), long
+  // items use a frame aligned to the line (d = first position mod PF) and a
+  // multiple of PF for L: every prefetch then reads whole lines.
+  constexpr bool LINE_FRAME = TW && PF * sizeof(C) == 128;
+  auto seg_len = [](const int4& it) {
+    const int n = it.z - it.y;
+    if (LINE_FRAME && n > PF * (kThreads - 1)) {
+      const int d = it.y & (PF - 1);
+      return PF * ((n + d + PF * kThreads - 1) / (PF * kThreads));
+    }
+    return (n + kThreads - 1) / kThreads;
+  };
+  auto seg_shift = [](const int4& it) {
+    const int n = it.z - it.y;
+    return LINE_FRAME && n > PF * (kThreads - 1) ? it.y & (PF - 1) : 0;
+  };
 
   const int kbeg = a.sched_off[blockIdx.x], kend = a.sched_off[blockIdx.x + 1];
   int4 it = make_int4(0, 0, 0, 0);
-  int L = 0;
+  int L = 0, d = 0;
   if (kbeg < kend) {
     it = a.items[kbeg];
     L = seg_len(it);
-    issue(it, L, 0);
+    d = seg_shift(it);
+    issue(it, L, d, 0);
   }
   // the table copy overlaps the first chunk's loads
   if (TAB_LDS) {
@@ -872,12 +893,14 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     const int64_t item = it.w;
     const bool has_next = ks + 1 < kend;
     const int4 itn = has_next ? a.items[ks + 1] : make_int4(0, 0, 0, 0);
-    const int Ln = seg_len(itn);
+    const int Ln = seg_len(itn), dn = seg_shift(itn);
     const GwAdjArgs<R> mi = mem(it);
     const int K = mi.K;
     const int tile = item_tile(it);
     const int tv = tile >> mi.lognT, tu = tile & (mi.nT - 1);
-    const int segn = max(0, min(L, it.z - (it.y + tid * L)));   // this thread's positions
+    // this thread's frame positions [sb, segn) (only thread 0 skips the shift)
+    const int segn = max(0, min(L, d + (it.z - it.y) - tid * L));
+    const int sb = tid == 0 ? d : 0;
     __syncthreads();   // the previous item is done with the moments, side slots and cell lists
     for (int i = tid; i < TT * JJ; i += kThreads) mom[i] = cmk<C>(R(0), R(0));
     if (TAB_LDS && lay.borrow) {
@@ -889,7 +912,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 
     // the item's first pair was prefetched during the previous item's last
     // pair (or before the loop)
-    commit(it, L, 0, 0);
+    commit(it, L, d, 0, 0);
 
     C acc[JJ];
     int first = -1, cur = -1, nruns = 0;
@@ -898,7 +921,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     // walk the staged chunk at positions q0 .. q0 + WC - 1 of this thread's segment
     auto walk = [&](int q0) {
       const int qn = min(WC, segn - q0);
-      for (int i = 0; i < qn; ++i) {
+      for (int i = max(0, sb - q0); i < qn; ++i) {
         const Staged sp = st[i * kStagePitch + tid];
         C val = sp.val;
         AxisTaps xu, xv;
@@ -953,16 +976,16 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
       walk(p0);
       if (second) {
         __syncthreads();   // the first chunk has been walked
-        commit(it, L, p0, 1);
+        commit(it, L, d, p0, 1);
       }
-      issue(next || !has_next ? it : itn, next || !has_next ? L : Ln, next ? p0 + PF : 0);
+      issue(next || !has_next ? it : itn, next || !has_next ? L : Ln, next || !has_next ? d : dn, next ? p0 + PF : 0);
       if (second) {
         __syncthreads();   // the second chunk is staged
         walk(p0 + WC);
       }
       if (next) {
         __syncthreads();   // the second chunk has been walked
-        commit(it, L, p0 + PF, 0);
+        commit(it, L, d, p0 + PF, 0);
       }
     }
     if (TAB_LDS && lay.borrow) __syncthreads();   // every walk done with the table head
@@ -1102,6 +1125,7 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
     }
     it = itn;
     L = Ln;
+    d = dn;
   }
 }
 

@@ -284,15 +284,23 @@ __global__ void tile_bounds_kernel(const uint32_t* keys, int64_t M, int nTiles, 
   tile_start[t] = static_cast<int32_t>(lo);
 }
 
+// Work items of a tile [b, b + c): cut at the positions (b rounded down to a
+// multiple of kItemAlign) + i chunk, so that every item but a tile's first
+// starts on a multiple of kItemAlign positions and every item spans at most
+// chunk positions counted from the multiple of kItemAlign at or below its
+// start (the gridding walk lays its segments out from there).
+constexpr int kItemAlign = 16;
+
 __global__ void item_count_kernel(const int32_t* tile_start, int nTiles, int chunk, uint32_t* counts) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > nTiles) return;
   if (t == nTiles) { counts[t] = 0; return; }
-  const int c = tile_start[t + 1] - tile_start[t];
-  counts[t] = c == 0 ? 0u : static_cast<uint32_t>((c + chunk - 1) / chunk);
+  const int b = tile_start[t], c = tile_start[t + 1] - b;
+  const int d = b & (kItemAlign - 1);
+  counts[t] = c == 0 ? 0u : static_cast<uint32_t>((c + d + chunk - 1) / chunk);
 }
 
-__global__ void item_fill_kernel(const int32_t* tile_start, const uint32_t* item_off_u, int nTiles,
+__global__ void item_fill_kernel(const int32_t* tile_start, const uint32_t* item_off_u, int nTiles, int chunk,
                                  int4* items, int32_t* item_off) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > nTiles) return;
@@ -300,9 +308,10 @@ __global__ void item_fill_kernel(const int32_t* tile_start, const uint32_t* item
   if (t == nTiles) return;
   const int b = tile_start[t], c = tile_start[t + 1] - b;
   const int q = static_cast<int>(item_off_u[t + 1] - item_off_u[t]);
+  const int b0 = b & ~(kItemAlign - 1);
   for (int i = 0; i < q; ++i) {
-    const int lo = b + static_cast<int>((static_cast<int64_t>(c) * i) / q);
-    const int hi = b + static_cast<int>((static_cast<int64_t>(c) * (i + 1)) / q);
+    const int lo = i == 0 ? b : b0 + i * chunk;
+    const int hi = i == q - 1 ? b + c : b0 + (i + 1) * chunk;
     items[item_off_u[t] + i] = make_int4(t, lo, hi, 0);
   }
 }
@@ -410,13 +419,15 @@ int phi_prepare(pr_phi_plan_t* p, const pr_phi_desc* d) {
   p->nTiles = p->nT * p->nT;
   // Work-item size: about M / 2048 visibilities (a power of two in [2048, 8192])
   // so that dense tiles split over many blocks while the fixed cost of an item
-  // (patch load or assembly, carries between segments) stays small.
+  // (patch load or assembly, carries between segments) stays small. A tile is
+  // cut into full items and a remainder (see item_count_kernel).
   {
     int64_t c = 2048;
     while (c < 8192 && c * 2048 < p->M) c *= 2;
     p->chunk = static_cast<int>(c);
   }
-  p->nItemsMax = p->nTiles + (p->M + p->chunk - 1) / p->chunk;
+  // items per tile: ceil((count + shift) / chunk), shift < kItemAlign
+  p->nItemsMax = p->nTiles + (p->M + static_cast<int64_t>(kItemAlign - 1) * p->nTiles + p->chunk - 1) / p->chunk;
   p->kappa = static_cast<double>(p->K) / (2.0 * M_PI);
   const double alpha = static_cast<double>(d->oversample);
   p->beta = M_PI * std::sqrt((p->J / alpha) * (p->J / alpha) * (alpha - 0.5) * (alpha - 0.5) - 0.8);
@@ -561,8 +572,8 @@ static int create_impl(pr_phi_plan_t* p, const R* uv, const R* w, hipStream_t s)
   item_count_kernel<<<(nt1 + 255) / 256, 256, 0, s>>>(cs.tile_start, p->nTiles, p->chunk, cs.counts);
   PR_TRY_LAUNCH();
   PR_TRY(scan_exclusive(cs.counts, cs.counts_scan, nt1, cs.scan_tmp, s));
-  item_fill_kernel<<<(nt1 + 255) / 256, 256, 0, s>>>(cs.tile_start, cs.counts_scan, p->nTiles, p->items,
-                                                      p->item_off);
+  item_fill_kernel<<<(nt1 + 255) / 256, 256, 0, s>>>(cs.tile_start, cs.counts_scan, p->nTiles, p->chunk,
+                                                      p->items, p->item_off);
   PR_TRY_LAUNCH();
   int32_t nitems = 0;
   PR_TRY_HIP(hipMemcpyAsync(&nitems, p->item_off + p->nTiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
