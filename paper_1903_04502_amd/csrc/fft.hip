@@ -18,7 +18,7 @@ namespace pr {
 
 namespace {
 
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 512;
 
 // Lines of length K held in LDS at stride LS (complex elements). All threads
 // of the block cooperate on the W lines; each stage reads every butterfly's
@@ -101,9 +101,10 @@ __device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, in
   }
 }
 
-// Butterflies per thread per radix-4 stage: W * K / 4 <= kFftThreads * PB4.
+// Butterflies per thread per radix-4 stage: W * K / 4 <= kFftThreads * PB4
+// (checked by fft_shape_ok).
 template <typename R> struct FftCfg;
-template <> struct FftCfg<float> { static constexpr int PB4 = 8; };
+template <> struct FftCfg<float> { static constexpr int PB4 = 4; };
 template <> struct FftCfg<double> { static constexpr int PB4 = 4; };
 
 inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
@@ -112,7 +113,7 @@ inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
 // (the pad spreads column accesses over banks; a single line uses stride K),
 // small enough to give at least 256 blocks when there are enough lines. The
 // block has W * K / 4 threads (one radix-4 butterfly each), clamped to
-// [64, 256]; this keeps W * K / 4 <= threads * PB4.
+// [64, 512]: for every K up to 8192 this keeps W * K / 4 <= threads * PB4.
 template <typename R>
 inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
   const size_t per = static_cast<size_t>(K + 1) * sizeof(cx_t<R>);
@@ -123,6 +124,15 @@ inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
   int t = w * K / 4;
   t = t < 64 ? 64 : (t > kFftThreads ? kFftThreads : t);
   *threads = t;
+}
+
+template <typename R>
+int fft_shape_ok(int K, int W, int threads) {
+  if (static_cast<int64_t>(W) * K / 4 > static_cast<int64_t>(threads) * FftCfg<R>::PB4) {
+    set_error("internal: FFT of %d lines of %d points needs more than %d threads", W, K, threads);
+    return PR_EUNSUPPORTED;
+  }
+  return PR_OK;
 }
 
 }  // namespace
@@ -323,6 +333,8 @@ int fzs_impl(pr_phi_plan_t* p, const R* x, hipStream_t s) {
   int Wr, LSr, Wc, LSc, Tr, Tc;
   lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
   lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
+  PR_TRY(fft_shape_ok<R>(K, Wr, Tr));
+  PR_TRY(fft_shape_ok<R>(K, Wc, Tc));
   const size_t lds_r = static_cast<size_t>(Wr) * LSr * sizeof(C);
   const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
   fzs_rows_kernel<R><<<(n + Wr - 1) / Wr, Tr, lds_r, s>>>(
@@ -343,6 +355,8 @@ int fzs_adjoint_impl(pr_phi_plan_t* p, R* x_out, const R* x_in, R* zbar, double 
   int Wr, LSr, Wc, LSc, Tr, Tc;
   lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
   lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
+  PR_TRY(fft_shape_ok<R>(K, Wr, Tr));
+  PR_TRY(fft_shape_ok<R>(K, Wc, Tc));
   const size_t lds_r = static_cast<size_t>(Wr) * LSr * sizeof(C);
   const size_t lds_c = static_cast<size_t>(Wc) * LSc * sizeof(C);
   fzs_adj_cols_kernel<R><<<K / Wc, Tc, lds_c, s>>>(static_cast<const C*>(p->grid),
@@ -423,6 +437,8 @@ int fused_fzs_t(FusedStages* f, const void* const* x, hipStream_t s) {
     int Wr, LSr, Wc, LSc, Tr, Tc;
     lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
     lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
+    PR_TRY(fft_shape_ok<R>(K, Wr, Tr));
+    PR_TRY(fft_shape_ok<R>(K, Wc, Tc));
     const FftPtrs<R>* mp = static_cast<const FftPtrs<R>*>(k.d_fwd);
     fzs_rows_kernel<R, true><<<dim3((n + Wr - 1) / Wr, cnt), Tr, static_cast<size_t>(Wr) * LSr * sizeof(C), s>>>(
         nullptr, nullptr, nullptr, nullptr, n, K, logK, Wr, LSr, mp);
@@ -445,6 +461,8 @@ int fused_fzs_adjoint_t(FusedStages* f, void* const* x, hipStream_t s) {
     int Wr, LSr, Wc, LSc, Tr, Tc;
     lines_per_block<R>(K, n, &Wr, &LSr, &Tr);
     lines_per_block<R>(K, K, &Wc, &LSc, &Tc);
+    PR_TRY(fft_shape_ok<R>(K, Wr, Tr));
+    PR_TRY(fft_shape_ok<R>(K, Wc, Tc));
     const FftPtrs<R>* mp = static_cast<const FftPtrs<R>*>(k.d_adj);
     fzs_adj_cols_kernel<R, true><<<dim3(K / Wc, cnt), Tc, static_cast<size_t>(Wc) * LSc * sizeof(C), s>>>(
         nullptr, nullptr, nullptr, n, K, logK, Wc, LSc, mp);

@@ -30,6 +30,26 @@ def _cdt(prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_phi_parity_at_the_largest_image(P, prec):
+    """n = 4096 (K = 8192), the largest image a plan accepts: every FFT pass
+    holds one line of 8192 points per block (2048 radix-4 butterflies per
+    stage), in both precisions."""
+    n, M, J = 4096, 3000, 4
+    say(f"phi parity largest image prec={prec}")
+    x, uv, w, spec = problem(n, M, J, 2000, seed=4096, prec=prec, weights=False)
+    plan, perm = make_plan(P, n, uv, w, J, 2000, prec, 0)
+    y_gpu = plan.apply(to_dev(x, _rdt(prec))).cpu().numpy()
+    uv64 = uv.astype(np.float64)
+    y_ref = ms.phi(x, uv64, None, spec)[perm]
+    assert rel_l2(y_gpu, y_ref) <= TOL[prec]
+    rng = np.random.default_rng(7)
+    yy = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    x_gpu = plan.adjoint(to_dev(yy[perm], _cdt(prec))).cpu().numpy()
+    x_ref = ms.phi_adjoint(yy, uv64, None, spec)
+    assert rel_l2(x_gpu, x_ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("n,M,J,tile,weights", [
     (64, 8192, 4, 0, False),      # the 64^2 / 8192-visibility workload
     (64, 12345, 4, 8, True),      # ragged M, weights
