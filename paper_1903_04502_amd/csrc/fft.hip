@@ -20,15 +20,65 @@ namespace {
 
 constexpr int kFftThreads = 512;
 
-// Lines of length K held in LDS at stride LS (complex elements). All threads
-// of the block cooperate on the W lines; each stage reads every butterfly's
-// inputs into registers, synchronises, then writes (in place).
+// Lines of length K held in LDS at stride LS (complex elements); element i
+// of a line sits at lds_at(i) = i + i / 16, one pad slot per 16 elements, so
+// that the strided stores of the first stages spread over the banks. All
+// threads of the block cooperate on the W lines. Stockham stages, each
+// reading every butterfly's inputs into registers, synchronising, then
+// writing in place: radix 2 first if log2 K is odd, radix 4 if a factor 4 is
+// left over, then radix 16 (a 4 x 4 split in registers), so K = 4096 takes
+// three passes over LDS instead of six radix-4 ones.
+__device__ __forceinline__ int lds_at(int i) { return i + (i >> 4); }
+
+template <typename C, bool INV>
+__device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+  const C s0 = cadd(a0, a2), d0 = csub(a0, a2);
+  const C s1 = cadd(a1, a3), d1 = csub(a1, a3);
+  // the rotation by -i (forward) or +i (inverse)
+  const C rd1 = INV ? cmk<C>(-d1.y, d1.x) : cmk<C>(d1.y, -d1.x);
+  a0 = cadd(s0, s1);
+  a2 = csub(s0, s1);
+  a1 = cadd(d0, rd1);
+  a3 = csub(d0, rd1);
+}
+
+// 16-point DFT of v[0..15] in place, output in natural order: X[k1 + 4 k2] =
+// sum_n2 W16^(n2 k1) W4^(n2 k2) sum_n1 W4^(n1 k1) v[4 n1 + n2].
+template <typename C, bool INV>
+__device__ __forceinline__ void dft16(C* v) {
+  using R = typename CxOf<C>::R;
+  constexpr R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173), h = R(0.70710678118654752440);
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<C, INV>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+  // v[n2 + 4 k1] *= W16^(n2 k1), W16^m = exp(-+ 2 pi i m / 16)
+  const R sg = INV ? R(1) : R(-1);
+  v[5] = cmul(v[5], cmk<C>(c1, sg * s1));     // m = 1
+  v[9] = cmul(v[9], cmk<C>(h, sg * h));       // m = 2
+  v[13] = cmul(v[13], cmk<C>(s1, sg * c1));   // m = 3
+  v[6] = cmul(v[6], cmk<C>(h, sg * h));       // m = 2
+  v[10] = INV ? cmk<C>(-v[10].y, v[10].x) : cmk<C>(v[10].y, -v[10].x);   // m = 4
+  v[14] = cmul(v[14], cmk<C>(-h, sg * h));    // m = 6
+  v[7] = cmul(v[7], cmk<C>(s1, sg * c1));     // m = 3
+  v[11] = cmul(v[11], cmk<C>(-h, sg * h));    // m = 6
+  v[15] = cmul(v[15], cmk<C>(-c1, -sg * s1)); // m = 9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<C, INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index
+  C t[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
 template <typename R, bool INV, int PB4>
 __device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t<R>* __restrict__ tw) {
   using C = cx_t<R>;
   const int tid = threadIdx.x, nth = blockDim.x;
-  int Ns = 1;
-  if (logK & 1) {
+  int Ns = 1, rem = logK;
+  if (rem & 1) {
     const int half = K >> 1, nbf = W * half;
     C a[2 * PB4], b[2 * PB4];
 #pragma unroll
@@ -37,8 +87,8 @@ __device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, in
       if (bf < nbf) {
         const int line = bf / half, j = bf - line * half;
         const C* L = buf + line * LS;
-        a[i] = L[j];
-        b[i] = L[j + half];
+        a[i] = L[lds_at(j)];
+        b[i] = L[lds_at(j + half)];
       }
     }
     __syncthreads();
@@ -48,15 +98,16 @@ __device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, in
       if (bf < nbf) {
         const int line = bf / half, j = bf - line * half;
         C* L = buf + line * LS;
-        L[2 * j] = cadd(a[i], b[i]);
-        L[2 * j + 1] = csub(a[i], b[i]);
+        L[lds_at(2 * j)] = cadd(a[i], b[i]);
+        L[lds_at(2 * j + 1)] = csub(a[i], b[i]);
       }
     }
     __syncthreads();
     Ns = 2;
+    rem -= 1;
   }
-  const int q = K >> 2, nbf = W * q;
-  for (; Ns < K; Ns <<= 2) {
+  if (rem & 2) {
+    const int q = K >> 2, nbf = W * q;
     const int stride = K / (4 * Ns);
     C v[PB4][4];
 #pragma unroll
@@ -66,7 +117,7 @@ __device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, in
         const int line = bf / q, j = bf - line * q;
         const C* L = buf + line * LS;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[i][r] = L[j + r * q];
+        for (int r = 0; r < 4; ++r) v[i][r] = L[lds_at(j + r * q)];
         const int k = j & (Ns - 1);
 #pragma unroll
         for (int r = 1; r < 4; ++r) {
@@ -74,14 +125,7 @@ __device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, in
           if (INV) w = cconj(w);
           v[i][r] = cmul(v[i][r], w);
         }
-        // 4-point DFT; the rotation by -i (forward) or +i (inverse)
-        const C s0 = cadd(v[i][0], v[i][2]), d0 = csub(v[i][0], v[i][2]);
-        const C s1 = cadd(v[i][1], v[i][3]), d1 = csub(v[i][1], v[i][3]);
-        const C rd1 = INV ? cmk<C>(-d1.y, d1.x) : cmk<C>(d1.y, -d1.x);
-        v[i][0] = cadd(s0, s1);
-        v[i][2] = csub(s0, s1);
-        v[i][1] = cadd(d0, rd1);
-        v[i][3] = csub(d0, rd1);
+        dft4<C, INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
       }
     }
     __syncthreads();
@@ -94,8 +138,39 @@ __device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, in
         C* L = buf + line * LS;
         const int idxD = (j - k) * 4 + k;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) L[idxD + r * Ns] = v[i][r];
+        for (int r = 0; r < 4; ++r) L[lds_at(idxD + r * Ns)] = v[i][r];
       }
+    }
+    __syncthreads();
+    Ns *= 4;
+    rem -= 2;
+  }
+  // radix 16: W K / 16 <= blockDim.x butterflies (one per thread at most)
+  const int q = K >= 16 ? K >> 4 : 1, nbf = rem > 0 ? W * q : 0;
+  const int bf = tid;
+  const int line = bf / q, j = bf - line * q;
+  for (; rem > 0; rem -= 4, Ns *= 16) {
+    const int stride = K / (16 * Ns);
+    C v[16];
+    const int k = j & (Ns - 1);
+    if (bf < nbf) {
+      const C* L = buf + line * LS;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = L[lds_at(j + r * q)];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) {
+        C w = tw[k * r * stride];
+        if (INV) w = cconj(w);
+        v[r] = cmul(v[r], w);
+      }
+      dft16<C, INV>(v);
+    }
+    __syncthreads();
+    if (bf < nbf) {
+      C* L = buf + line * LS;
+      const int idxD = (j - k) * 16 + k;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) L[lds_at(idxD + r * Ns)] = v[r];
     }
     __syncthreads();
   }
@@ -109,18 +184,21 @@ template <> struct FftCfg<double> { static constexpr int PB4 = 4; };
 
 inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
 
-// Lines per block: a power of two that fits 128 KB of LDS at stride K + 1
-// (the pad spreads column accesses over banks; a single line uses stride K),
-// small enough to give at least 256 blocks when there are enough lines. The
-// block has W * K / 4 threads (one radix-4 butterfly each), clamped to
-// [64, 512]: for every K up to 8192 this keeps W * K / 4 <= threads * PB4.
+// Lines per block: a power of two that fits 128 KB of LDS at stride
+// K + K/16 + 1 (the padded line plus one slot, so that neighbouring lines
+// start on different banks), small enough to give at least 256 blocks when
+// there are enough lines (one line may take up to 139 KB: FP64, K = 8192).
+// The block has W * K / 4 threads (one radix-4 butterfly each), clamped to
+// [64, 512]: for every K up to 8192 this keeps W * K / 4 <= threads * PB4
+// and W * K / 16 <= threads (one radix-16 butterfly per thread).
 template <typename R>
 inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
-  const size_t per = static_cast<size_t>(K + 1) * sizeof(cx_t<R>);
+  const int ls = K + K / 16 + 1;
+  const size_t per = static_cast<size_t>(ls) * sizeof(cx_t<R>);
   int w = 1;
   while (static_cast<size_t>(2 * w) * per <= 131072 && 2 * w <= nlines && nlines / (2 * w) >= 256) w *= 2;
   *W = w;
-  *LS = w > 1 ? K + 1 : K;
+  *LS = ls;
   int t = w * K / 4;
   t = t < 64 ? 64 : (t > kFftThreads ? kFftThreads : t);
   *threads = t;
@@ -128,7 +206,8 @@ inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
 
 template <typename R>
 int fft_shape_ok(int K, int W, int threads) {
-  if (static_cast<int64_t>(W) * K / 4 > static_cast<int64_t>(threads) * FftCfg<R>::PB4) {
+  if (static_cast<int64_t>(W) * K / 4 > static_cast<int64_t>(threads) * FftCfg<R>::PB4 ||
+      static_cast<int64_t>(W) * K / 16 > threads) {
     set_error("internal: FFT of %d lines of %d points needs more than %d threads", W, K, threads);
     return PR_EUNSUPPORTED;
   }
@@ -199,17 +278,17 @@ __global__ __launch_bounds__(kFftThreads) void fzs_rows_kernel(const R* __restri
   const int row0 = blockIdx.x * W;
   const int lines = min(W, n - row0);
   for (int i = threadIdx.x; i < lines * n; i += blockDim.x)
-    buf[(i >> logn) * LS + h + (i & (n - 1))] = cmk<C>(R(0), R(0));
+    buf[(i >> logn) * LS + lds_at(h + (i & (n - 1)))] = cmk<C>(R(0), R(0));
   const R* xr = x + static_cast<int64_t>(row0) * n;
   batched_move<U, R>(
       lines * n,
       [&](int e) { return xr[e] * corr[e & (n - 1)] * corr[row0 + (e >> logn)]; },
-      [&](int e, R v) { buf[(e >> logn) * LS + (((e & (n - 1)) - h) & (K - 1))] = cmk<C>(v, R(0)); });
+      [&](int e, R v) { buf[(e >> logn) * LS + lds_at(((e & (n - 1)) - h) & (K - 1))] = cmk<C>(v, R(0)); });
   __syncthreads();
   fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
   C* Ar = A + static_cast<int64_t>(row0) * K;
   batched_move<U, C>(
-      lines * K, [&](int e) { return buf[(e >> logK) * LS + (e & (K - 1))]; }, [&](int e, C v) { Ar[e] = v; });
+      lines * K, [&](int e) { return buf[(e >> logK) * LS + lds_at(e & (K - 1))]; }, [&](int e, C v) { Ar[e] = v; });
 }
 
 // Column groups are laid out so that blocks on one XCD (blockIdx mod 8) take
@@ -238,16 +317,16 @@ __global__ __launch_bounds__(kFftThreads) void fzs_cols_kernel(const cx_t<R>* __
   const int logn = logK - 1, h = n >> 1, logW = __builtin_ctz(W);
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
   for (int i = threadIdx.x; i < W * n; i += blockDim.x)
-    buf[(i >> logn) * LS + h + (i & (n - 1))] = cmk<C>(R(0), R(0));
+    buf[(i >> logn) * LS + lds_at(h + (i & (n - 1)))] = cmk<C>(R(0), R(0));
   const C* Ac = A + kx0;
   batched_move<U, C>(
       n * W, [&](int e) { return Ac[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))]; },
-      [&](int e, C v) { buf[(e & (W - 1)) * LS + (((e >> logW) - h) & (K - 1))] = v; });
+      [&](int e, C v) { buf[(e & (W - 1)) * LS + lds_at(((e >> logW) - h) & (K - 1))] = v; });
   __syncthreads();
   fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
   C* gc = grid + kx0;
   batched_move<U, C>(
-      K * W, [&](int e) { return buf[(e & (W - 1)) * LS + (e >> logW)]; },
+      K * W, [&](int e) { return buf[(e & (W - 1)) * LS + lds_at(e >> logW)]; },
       [&](int e, C v) { gc[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))] = v; });
 }
 
@@ -270,12 +349,12 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_cols_kernel(const cx_t<R>
   const C* gc = grid + kx0;
   batched_move<U, C>(
       K * W, [&](int e) { return gc[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))]; },
-      [&](int e, C v) { buf[(e & (W - 1)) * LS + (e >> logW)] = v; });
+      [&](int e, C v) { buf[(e & (W - 1)) * LS + lds_at(e >> logW)] = v; });
   __syncthreads();
   fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
   C* Ac = A + kx0;
   batched_move<U, C>(
-      n * W, [&](int e) { return buf[(e & (W - 1)) * LS + (((e >> logW) - h) & (K - 1))]; },
+      n * W, [&](int e) { return buf[(e & (W - 1)) * LS + lds_at(((e >> logW) - h) & (K - 1))]; },
       [&](int e, C v) { Ac[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))] = v; });
 }
 
@@ -303,7 +382,7 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>
   const int lines = min(W, n - row0);
   const C* Ar = A + static_cast<int64_t>(row0) * K;
   batched_move<U, C>(
-      lines * K, [&](int e) { return Ar[e]; }, [&](int e, C v) { buf[(e >> logK) * LS + (e & (K - 1))] = v; });
+      lines * K, [&](int e) { return Ar[e]; }, [&](int e, C v) { buf[(e >> logK) * LS + lds_at(e & (K - 1))] = v; });
   __syncthreads();
   fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
   const int64_t o0 = static_cast<int64_t>(row0) * n;
@@ -312,7 +391,7 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>
       lines * n,
       [&](int e) {
         const int l = e >> logn, ix = e & (n - 1);
-        const R val = buf[l * LS + ((ix - h) & (K - 1))].x * corr[ix] * corr[row0 + l];
+        const R val = buf[l * LS + lds_at((ix - h) & (K - 1))].x * corr[ix] * corr[row0 + l];
         return cmk<C>(val, MODE == 0 ? R(0) : x_in[o0 + e]);
       },
       [&](int e, C v) {
