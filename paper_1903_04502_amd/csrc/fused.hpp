@@ -23,8 +23,10 @@ struct FusedStages {
   void* d_mg = nullptr;          // per-member merge arguments
   int4* sched_d = nullptr;
   int32_t* sched_d_off = nullptr;
-  int4* sched_g = nullptr;
+  int4* sched_g = nullptr;        // the walk's items (more than kSmallItem visibilities)
   int32_t* sched_g_off = nullptr;
+  int4* small = nullptr;          // the small-item kernel's items
+  int64_t nSmall = 0;
   int Gd = 0, Gg = 0, tiles = 0;
   std::vector<char> h_dg, h_ga;  // host copies; each call's vector pointers patched in
   std::vector<const void*> up_dg, up_ga;   // pointers of the last upload

@@ -1129,6 +1129,129 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
   }
 }
 
+// Gridding of the small items (at most kSmallItem visibilities), one wave
+// per item: lane l takes visibility l of the item (with the ADMM prologue of
+// the walk in MODE 1 / 3), evaluates its base cell and J + J weights once
+// into LDS, then each lane forms patch cells l, l + 64, ... directly as the
+// sum, in visibility order, of w_v (q w_u) over the visibilities whose
+// footprint covers the cell. No runs and no moments: for a handful of
+// visibilities the walk's per-item steps (clearing, segment carries, block
+// barriers, the wait for the next item's loads) cost far more than the
+// arithmetic. Blocks of four waves share the table; all four take their
+// next items together, so the block barriers stay uniform.
+template <typename R, int J, int MODE, int LK, bool FUSED = false>
+__global__ __launch_bounds__(kThreads) void grid_small_kernel(GwAdjArgs<R> a, const int4* __restrict__ small,
+                                                              int nsmall) {
+  using C = cx_t<R>;
+  constexpr bool LIN = LK == kLkLinear, TW = LK == kLkWords;
+  constexpr bool ADMM = MODE != 0, SEC = MODE == 3;
+  constexpr int kWaves = kThreads / 64;
+  struct Entry {
+    int lu, lv;
+    R wu[J], wv[J];
+    C val;
+  };
+  extern __shared__ char smem_raw[];
+  R* tab = reinterpret_cast<R*>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  Entry* ent = reinterpret_cast<Entry*>(smem_raw + align16(static_cast<size_t>(a.tlen) * sizeof(R))) + wave * 64;
+  for (int i = tid; i < a.tlen; i += kThreads) tab[i] = a.table[i];
+  const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
+  R kappa_ball = 1;
+  if (ADMM) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
+  const int T = a.T, P = a.P;   // the same for every member of a fused launch
+  auto mem = [&](const int4& it) -> GwAdjArgs<R> {
+    if constexpr (FUSED) {
+      const GwAdjArgs<R>* t = a.mtab + item_member(it);
+      GwAdjArgs<R> m = *t;
+      m.uv = global_ptr_at(&t->uv);
+      m.y_in = global_ptr_at(&t->y_in);
+      m.patches = global_ptr_at(&t->patches);
+      return m;
+    } else {
+      (void)it;
+      return a;
+    }
+  };
+  const int step = kWaves * static_cast<int>(gridDim.x);
+  const int rounds = (nsmall + step - 1) / step;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int idx = rd * step + static_cast<int>(blockIdx.x) * kWaves + wave;
+    const bool have = idx < nsmall;
+    const int4 it = have ? small[idx] : make_int4(0, 0, 0, 0);
+    const int n = it.z - it.y;
+    const GwAdjArgs<R> m = mem(it);
+    __syncthreads();   // the table is in LDS; the previous round is done with the entries
+    if (have && lane < n) {
+      const int64_t k = static_cast<int64_t>(it.y) + lane;
+      R u, v, w;
+      if constexpr (TW) {
+        const uint2 w2 = reinterpret_cast<const uint2*>(m.uv)[k];
+        u = __uint_as_float(w2.x);
+        v = R(0);
+        w = __uint_as_float(w2.y);
+      } else {
+        vis_load<TW>(m.uv, k, u, v, w);
+      }
+      C val;
+      if constexpr (MODE == 0) {
+        val = m.y_in[k];
+      } else {
+        // ball projection and multiplier update of Algorithm 1, as in the walk
+        const C tt = m.t_in[k], sk = m.s_io[k];
+        const R omk = R(1) - (SEC ? static_cast<R>(a.kappa_sec[m.sec[k]]) : kappa_ball);
+        const C vr = cmk<C>(omk * tt.x - sk.x, omk * tt.y - sk.y);
+        const C sn = cmk<C>(sk.x + a.varrho * vr.x, sk.y + a.varrho * vr.y);
+        m.s_io[k] = sn;
+        val = cmk<C>(a.vr_coef * vr.x + sn.x, a.vr_coef * vr.y + sn.y);
+      }
+      const R ws = w * (FUSED ? m.scale : scale);
+      Entry e;
+      e.val = cmk<C>(val.x * ws, val.y * ws);
+      const int tile = item_tile(it);
+      const int tv = tile >> m.lognT, tu = tile & (m.nT - 1);
+      AxisTaps xu, xv;
+      int lu, lv;
+      vis_taps<TW>(u, v, m.kappa, J, a.D, m.K, T, tu, tv, xu, xv, lu, lv);
+      if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
+        // cannot happen for a plan's own sorted baselines: poison the value
+        lu = lv = 0;
+        e.val = cmk<C>(R(NAN), R(NAN));
+      }
+      e.lu = lu;
+      e.lv = lv;
+      axis_weights<LIN, J>(tab, xu, a.D, a.tlen, e.wu);
+      axis_weights<LIN, J>(tab, xv, a.D, a.tlen, e.wv);
+      ent[lane] = e;
+    }
+    __syncthreads();   // the entries are written
+    if (have) {
+      C* out = m.patches + static_cast<int64_t>(it.w) * P * P;
+      const float invP = 1.0f / P;
+      for (int pc = lane; pc < P * P; pc += 64) {
+        const int pv = small_div(pc, P, invP), pu = pc - pv * P;
+        R sr = 0, si = 0;
+        for (int q = 0; q < n; ++q) {
+          const int du = pu - ent[q].lu, dv = pv - ent[q].lv;
+          if (static_cast<unsigned>(du) < static_cast<unsigned>(J) && static_cast<unsigned>(dv) < static_cast<unsigned>(J)) {
+            const R g = ent[q].wu[du], gv = ent[q].wv[dv];
+            const C y = ent[q].val;
+            sr += gv * (y.x * g);
+            si += gv * (y.y * g);
+          }
+        }
+        out[pc] = cmk<C>(sr, si);
+      }
+    }
+  }
+}
+
+template <typename R, int J>
+size_t small_lds_bytes(int tlen) {
+  struct EntrySize { int lu, lv; R wu[J], wv[J]; cx_t<R> val; };
+  return align16(static_cast<size_t>(tlen) * sizeof(R)) + static_cast<size_t>(kThreads) * sizeof(EntrySize);
+}
+
 // Columns of the moments held per gridding thread (JA): FP32 keeps at most 8
 // complex accumulators per thread for J <= 4 (two threads per segment), FP64
 // at most 8.
@@ -1250,7 +1373,7 @@ int degrid_blocks(const pr_phi_plan_t* p) {
 }
 
 int grid_blocks(const pr_phi_plan_t* p) {
-  return static_cast<int>(p->nItems < kGridBlocks ? p->nItems : kGridBlocks);
+  return static_cast<int>(p->nGrid < kGridBlocks ? p->nGrid : kGridBlocks);
 }
 
 // Raise a kernel's dynamic LDS limit to the full 160 KB, once per kernel and
@@ -1325,6 +1448,10 @@ int launch_walk(pr_phi_plan_t* p, GwAdjArgs<R>& a, hipStream_t s, int G, bool* w
   const size_t bytes = tl ? with.total : without.total;
   *walked = false;
   if (bytes > kLdsHard) return PR_OK;
+  if (G == 0) {   // every item is a small one
+    *walked = true;
+    return PR_OK;
+  }
   if (LK == kLkWords && a.T == 16) {
     if (tl) {
       PR_TRY(allow_lds(grid_walk_kernel<R, J, WMODE, true, LK, 16, FUSED>, bytes));
@@ -1344,6 +1471,19 @@ int launch_walk(pr_phi_plan_t* p, GwAdjArgs<R>& a, hipStream_t s, int G, bool* w
   return PR_OK;
 }
 
+// The small items of a walk plan (none: no launch).
+template <typename R, int J, int WMODE, int LK, bool FUSED = false>
+int launch_small(const GwAdjArgs<R>& a, const int4* small, int64_t nsmall, hipStream_t s) {
+  if (nsmall <= 0) return PR_OK;
+  const size_t bytes = small_lds_bytes<R, J>(a.tlen);
+  const int64_t blocks = (nsmall + kThreads / 64 - 1) / (kThreads / 64);
+  const int G = static_cast<int>(blocks < kDegridBlocks ? blocks : kDegridBlocks);
+  PR_TRY(allow_lds(grid_small_kernel<R, J, WMODE, LK, FUSED>, bytes));
+  grid_small_kernel<R, J, WMODE, LK, FUSED><<<G, kThreads, bytes, s>>>(a, small, static_cast<int>(nsmall));
+  PR_TRY_LAUNCH();
+  return PR_OK;
+}
+
 template <typename R, int J, int MODE, int LK>
 int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) {
   using C = cx_t<R>;
@@ -1356,8 +1496,10 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
       // the ADMM prologue with section balls is its own walk instance (MODE 3)
       if (MODE == 1 && a.sec) {
         PR_TRY((launch_walk<R, J, MODE == 1 ? 3 : MODE, LK>(p, a, s, G, &walked)));
+        if (walked) PR_TRY((launch_small<R, J, MODE == 1 ? 3 : MODE, LK>(a, p->small, p->nSmall, s)));
       } else {
         PR_TRY((launch_walk<R, J, MODE, LK>(p, a, s, G, &walked)));
+        if (walked) PR_TRY((launch_small<R, J, MODE, LK>(a, p->small, p->nSmall, s)));
       }
     }
   }
@@ -1399,6 +1541,8 @@ int setup_mode() {
     PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], false, LK, 0>, kLdsHard)));
     PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], true, LK, 0>, kLdsHard)));
     PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], false, LK, 0>, kLdsHard)));
+    PR_TRY((allow_lds(grid_small_kernel<R, J, WM[0], LK>, kLdsHard)));
+    PR_TRY((allow_lds(grid_small_kernel<R, J, WM[1], LK>, kLdsHard)));
     if constexpr (LK == kLkWords) {
       PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], true, LK, 16>, kLdsHard)));
       PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], false, LK, 16>, kLdsHard)));
@@ -1564,6 +1708,7 @@ size_t fused_vis_bytes_t(int n, int64_t items) {
   c.take<int32_t>(kDegridBlocks + 1);
   c.take<int4>(items);
   c.take<int32_t>(kGridBlocks + 1);
+  c.take<int4>(items);
   return c.bytes();
 }
 
@@ -1580,6 +1725,7 @@ int fused_vis_build_t(FusedStages* f, Carver& c, hipStream_t s) {
   f->sched_d_off = c.take<int32_t>(kDegridBlocks + 1);
   f->sched_g = c.take<int4>(total);
   f->sched_g_off = c.take<int32_t>(kGridBlocks + 1);
+  f->small = c.take<int4>(total);
   // every member's items, the tile field tagged with the member
   std::vector<int4> all, it;
   std::vector<int32_t> local;
@@ -1607,20 +1753,41 @@ int fused_vis_build_t(FusedStages* f, Carver& c, hipStream_t s) {
   f->tiles = tiles;
   const pr_phi_plan_t* p0 = f->plans[0];
   const int64_t P2 = static_cast<int64_t>(p0->P) * p0->P;
+  // the gridding items split as in a member's own plan: small ones to the
+  // small-item kernel (own index in .w), the others to the walk's schedule
+  std::vector<int4> big, smallv;
+  std::vector<int32_t> bigl;
+  const bool split = phi_walk_fits(p0);
+  for (size_t i = 0; i < all.size(); ++i) {
+    int4 e = all[i];
+    if (split && e.z - e.y <= kSmallItem) {
+      e.w = local[i];
+      smallv.push_back(e);
+    } else {
+      big.push_back(e);
+      bigl.push_back(local[i]);
+    }
+  }
+  const int64_t nbig = static_cast<int64_t>(big.size());
+  f->nSmall = static_cast<int64_t>(smallv.size());
   f->Gd = static_cast<int>(total < kDegridBlocks ? total : kDegridBlocks);
-  f->Gg = static_cast<int>(total < kGridBlocks ? total : kGridBlocks);
+  f->Gg = static_cast<int>(nbig < kGridBlocks ? nbig : kGridBlocks);
   std::vector<int4> sd, sg;
   std::vector<int32_t> sdo, sgo;
   if (total > 0) {
     lpt_schedule(all, f->Gd, P2 / 2, sd, sdo);
-    lpt_schedule(all, f->Gg, P2, sg, sgo);
     for (int4& e : sd) e.w = local[e.w];
-    for (int4& e : sg) e.w = local[e.w];
     PR_TRY_HIP(hipMemcpyAsync(f->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
     PR_TRY_HIP(hipMemcpyAsync(f->sched_d_off, sdo.data(), sdo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  if (nbig > 0) {
+    lpt_schedule(big, f->Gg, P2, sg, sgo);
+    for (int4& e : sg) e.w = bigl[e.w];
     PR_TRY_HIP(hipMemcpyAsync(f->sched_g, sg.data(), sg.size() * sizeof(int4), hipMemcpyHostToDevice, s));
     PR_TRY_HIP(hipMemcpyAsync(f->sched_g_off, sgo.data(), sgo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   }
+  if (!smallv.empty())
+    PR_TRY_HIP(hipMemcpyAsync(f->small, smallv.data(), smallv.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   PR_TRY_HIP(hipMemcpyAsync(mg, hm.data(), hm.size() * sizeof(MergeArgs<R>), hipMemcpyHostToDevice, s));
   PR_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
   // host argument tables: every member's own launch arguments
@@ -1677,7 +1844,7 @@ template <typename R>
 int fused_gw_adjoint_t(FusedStages* f, const void* const* y, hipStream_t s) {
   using C = cx_t<R>;
   pr_phi_plan_t* p0 = f->plans[0];
-  if (f->Gg > 0) {
+  if (f->Gg > 0 || f->nSmall > 0) {
     PR_TRY((upload_args<GwAdjArgs<R>, const C>(f->h_ga, f->up_ga, f->d_ga, reinterpret_cast<const C* const*>(y),
                                                &GwAdjArgs<R>::y_in, s)));
     GwAdjArgs<R> a = gwadj_args<R>(p0, 1.0);
@@ -1688,8 +1855,11 @@ int fused_gw_adjoint_t(FusedStages* f, const void* const* y, hipStream_t s) {
     const int rc = with_j(p0->J, [&](auto jj) -> int {
       constexpr int JJ = decltype(jj)::value;
       if constexpr (JJ <= 4) {
-        return with_lk<R>(p0, [&](auto lk) {
-          return launch_walk<R, JJ, 0, decltype(lk)::value, true>(p0, a, s, f->Gg, &walked);
+        return with_lk<R>(p0, [&](auto lk) -> int {
+          constexpr int LK = decltype(lk)::value;
+          PR_TRY((launch_walk<R, JJ, 0, LK, true>(p0, a, s, f->Gg, &walked)));
+          if (walked) PR_TRY((launch_small<R, JJ, 0, LK, true>(a, f->small, f->nSmall, s)));
+          return PR_OK;
         });
       } else {
         return static_cast<int>(PR_OK);
@@ -1717,6 +1887,25 @@ __global__ void zero_cx_kernel(cx_t<R>* a, int64_t n) {
 }
 
 }  // namespace
+
+bool phi_walk_fits(const pr_phi_plan_t* p) {
+  if (p->J > 4) return false;
+  const int tlen = p->J == 4 && !p->interp ? 2 * p->D + 2 : p->J * p->D / 2 + 1;
+  auto fits = [&](auto r, auto jj) {
+    using R = decltype(r);
+    constexpr int J = decltype(jj)::value;
+    const WalkLds<R, J> with(p->T, tlen, true), without(p->T, tlen, false);
+    return (with.total < without.total ? with.total : without.total) <= kLdsHard;
+  };
+  auto by_j = [&](auto r) {
+    switch (p->J) {
+      case 2: return fits(r, std::integral_constant<int, 2>{});
+      case 4: return fits(r, std::integral_constant<int, 4>{});
+      default: return false;
+    }
+  };
+  return p->prec == PR_F32 ? by_j(0.0f) : by_j(0.0);
+}
 
 int phi_gridding_setup(pr_phi_plan_t* p) {
   return p->prec == PR_F32 ? setup_prec<float>(p) : setup_prec<double>(p);

@@ -37,6 +37,12 @@ struct pr_phi_plan_t {
   int32_t* sched_d_off = nullptr;  // [kDegridBlocks + 1]
   int4* sched_g = nullptr;         // gridding, [nItemsMax]
   int32_t* sched_g_off = nullptr;  // [kGridBlocks + 1]
+  // Plans whose gridding uses the segment walk split the items: sched_g
+  // then holds the items of more than kSmallItem visibilities, and the
+  // smaller ones, in item order, go to their own kernel.
+  int4* small = nullptr;           // [nItemsMax]
+  int64_t nGrid = 0;               // entries of sched_g
+  int64_t nSmall = 0;              // entries of small
   void* table = nullptr;       // Real[J*D/2 + 1]
   void* table2 = nullptr;      // J = 4: pairs (T[i], T[D + i]), i = 0..D (Real[2D + 2]); else unused
   void* corr = nullptr;        // Real[n]
@@ -61,6 +67,7 @@ constexpr int64_t kMaxVisibilities = (int64_t(1) << 31) - (int64_t(1) << 20);
 constexpr int kPartialsMax = 4096;     // per-block partials, per quantity slot
 constexpr int kDegridBlocks = 2048;    // persistent degridding blocks (8 per CU); <= kPartialsMax
 constexpr int kGridBlocks = 512;       // persistent gridding blocks (2 per CU, bound by LDS)
+constexpr int kSmallItem = 64;         // items of at most this many visibilities: the small-item gridding
 constexpr int kSecAcc = 8;           // local balls: sections summed in the degridding epilogue
 constexpr int kSlotSec0 = 4;         // their per-block partials: slots kSlotSec0 .. kSlotSec0 + kSecAcc - 1
 constexpr int kPartialSlots = kSlotSec0 + kSecAcc;
@@ -76,6 +83,10 @@ int phi_create(pr_phi_plan_t* p, const void* uv, const void* w, hipStream_t s);
 // Set the LDS limits of the plan's gridding kernels (once per process and
 // device), so that later launches, also under stream capture, set nothing.
 int phi_gridding_setup(pr_phi_plan_t* p);
+// Whether the plan's gridding uses the segment walk (J <= 4 and its LDS
+// fits); those plans split their items between the walk and the
+// small-item kernel.
+bool phi_walk_fits(const pr_phi_plan_t* p);
 
 // Stable LSD radix sort of M (key, value) pairs on the low `bits` bits of the
 // keys, ping-ponging between (k0, v0) and (k1, v1); *kout / *vout name the

@@ -472,6 +472,7 @@ int phi_layout(pr_phi_plan_t* p, void* persistent, void* scratch, size_t* persis
   p->sched_d_off = a.take<int32_t>(kDegridBlocks + 1);
   p->sched_g = a.take<int4>(p->nItemsMax);
   p->sched_g_off = a.take<int32_t>(kGridBlocks + 1);
+  p->small = a.take<int4>(p->nItemsMax);
   p->table = a.take<char>((p->J * static_cast<int64_t>(p->D) / 2 + 1) * rs);
   p->table2 = a.take<char>(p->J == 4 ? (2 * static_cast<int64_t>(p->D) + 2) * rs : 0);
   p->corr = a.take<char>(p->n * rs);
@@ -503,16 +504,37 @@ static int build_schedules(pr_phi_plan_t* p, hipStream_t s) {
   PR_TRY_HIP(hipMemcpyAsync(items.data(), p->items, n * sizeof(int4), hipMemcpyDeviceToHost, s));
   PR_TRY_HIP(hipStreamSynchronize(s));
   const int64_t P2 = static_cast<int64_t>(p->P) * p->P;
-  std::vector<int4> sd, sg;
-  std::vector<int32_t> sdo, sgo;
+  std::vector<int4> sd, sg, big, small;
+  std::vector<int32_t> sdo, sgo, bigi;
   const int Gd = static_cast<int>(n < kDegridBlocks ? n : kDegridBlocks);
-  const int Gg = static_cast<int>(n < kGridBlocks ? n : kGridBlocks);
   lpt_schedule(items, Gd, P2 / 2, sd, sdo);     // per item: the patch load
-  lpt_schedule(items, Gg, P2, sg, sgo);         // per item: clearing, assembly, patch store
+  // gridding: with the walk, items of at most kSmallItem visibilities go to
+  // the small-item kernel (item order, own index in .w)
+  const bool split = phi_walk_fits(p);
+  for (int64_t i = 0; i < n; ++i) {
+    int4 e = items[static_cast<size_t>(i)];
+    if (split && e.z - e.y <= kSmallItem) {
+      e.w = static_cast<int>(i);
+      small.push_back(e);
+    } else {
+      big.push_back(e);
+      bigi.push_back(static_cast<int32_t>(i));
+    }
+  }
+  const int64_t nb = static_cast<int64_t>(big.size());
+  const int Gg = static_cast<int>(nb < kGridBlocks ? nb : kGridBlocks);
+  lpt_schedule(big, Gg, P2, sg, sgo);           // per item: clearing, assembly, patch store
+  for (int4& e : sg) e.w = bigi[static_cast<size_t>(e.w)];
+  p->nGrid = nb;
+  p->nSmall = static_cast<int64_t>(small.size());
   PR_TRY_HIP(hipMemcpyAsync(p->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   PR_TRY_HIP(hipMemcpyAsync(p->sched_d_off, sdo.data(), sdo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  PR_TRY_HIP(hipMemcpyAsync(p->sched_g, sg.data(), sg.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-  PR_TRY_HIP(hipMemcpyAsync(p->sched_g_off, sgo.data(), sgo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (nb > 0) {
+    PR_TRY_HIP(hipMemcpyAsync(p->sched_g, sg.data(), sg.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    PR_TRY_HIP(hipMemcpyAsync(p->sched_g_off, sgo.data(), sgo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  if (!small.empty())
+    PR_TRY_HIP(hipMemcpyAsync(p->small, small.data(), small.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   PR_TRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
   return PR_OK;
 }
