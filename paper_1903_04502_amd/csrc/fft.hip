@@ -1,9 +1,12 @@
 // F Z S and its adjoint (eq. matrix_equation): gridding correction, zero
 // padding to the oversampled K x K grid and the unnormalised 2-D FFT, as two
-// passes of in-LDS Stockham FFTs (radix 4, one radix-2 stage when log2 K is
-// odd). The zero padding is pruned: the forward row pass transforms only the
-// n image rows, and the adjoint column pass keeps only the n rows the crop
-// Z^T needs.
+// passes of Stockham FFTs over lines held in LDS (radix 16, then radix 4 and
+// 2 for what remains of log2 K). The zero padding is pruned: the forward row
+// pass transforms only the n image rows, and the adjoint column pass keeps
+// only the n rows the crop Z^T needs; within a line, the first stage reads
+// its inputs straight from memory (the padding's zeros are never loaded) and
+// the last stage writes straight to memory (cropped outputs are never
+// stored).
 //
 // Layouts: image x[iy*n + ix]; intermediate A[iy*K + kx] (n rows of K);
 // grid[ky*K + kx], ky = v cell, kx = u cell. Pixel offset p = i - n/2 sits at
@@ -22,12 +25,13 @@ constexpr int kFftThreads = 512;
 
 // Lines of length K held in LDS at stride LS (complex elements); element i
 // of a line sits at lds_at(i) = i + i / 16, one pad slot per 16 elements, so
-// that the strided stores of the first stages spread over the banks. All
-// threads of the block cooperate on the W lines. Stockham stages, each
-// reading every butterfly's inputs into registers, synchronising, then
-// writing in place: radix 2 first if log2 K is odd, radix 4 if a factor 4 is
-// left over, then radix 16 (a 4 x 4 split in registers), so K = 4096 takes
-// three passes over LDS instead of six radix-4 ones.
+// that the strided stores of the early stages spread over the banks. All
+// threads of the block cooperate on the W lines. Stockham stages: radix 16
+// (a 4 x 4 split in registers) while four factors of two remain, then radix
+// 4 and radix 2; K = 4096 takes three stages. The first stage reads through
+// the caller's load function, the last writes through its store function,
+// the stages between go through LDS (each reads its inputs into registers,
+// synchronises, then writes in place).
 __device__ __forceinline__ int lds_at(int i) { return i + (i >> 4); }
 
 template <typename C, bool INV>
@@ -73,114 +77,109 @@ __device__ __forceinline__ void dft16(C* v) {
   for (int i = 0; i < 16; ++i) v[i] = t[i];
 }
 
-template <typename R, bool INV, int PB4>
-__device__ __forceinline__ void fft_lds(cx_t<R>* buf, int K, int logK, int W, int LS, const cx_t<R>* __restrict__ tw) {
-  using C = cx_t<R>;
+
+// One Stockham stage of radix RX over W lines: butterfly j of a line reads
+// elements j + r K / RX, multiplies by w^(k r) (k = j mod Ns, w the
+// (Ns RX)-th root of unity), transforms, and writes element
+// (j - k) RX + k + r Ns. FROM: read through ld(line, i, v) (false: zero);
+// TO: write through st(line, i, v); else LDS. LF: consecutive threads take
+// consecutive lines of one butterfly index (column passes: neighbouring
+// columns share each row's memory), else consecutive butterflies of a line.
+template <int RX, bool INV, bool FROM, bool TO, bool LF, int PER, typename C, typename Ld, typename St>
+__device__ __forceinline__ void fft_stage(C* buf, int K, int W, int LS, int Ns, const C* __restrict__ tw, Ld& ld,
+                                          St& st) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  int Ns = 1, rem = logK;
-  if (rem & 1) {
-    const int half = K >> 1, nbf = W * half;
-    C a[2 * PB4], b[2 * PB4];
+  const int q = K / RX, nbf = W * q, stride = K / (RX * Ns);
+  const int logq = __builtin_ctz(q), logW = __builtin_ctz(W);   // powers of two
+  C v[PER][RX];
 #pragma unroll
-    for (int i = 0; i < 2 * PB4; ++i) {
-      const int bf = tid + i * nth;
-      if (bf < nbf) {
-        const int line = bf / half, j = bf - line * half;
-        const C* L = buf + line * LS;
-        a[i] = L[lds_at(j)];
-        b[i] = L[lds_at(j + half)];
+  for (int i = 0; i < PER; ++i) {
+    const int bf = tid + i * nth;
+    if (bf < nbf) {
+      const int line = LF ? bf & (W - 1) : bf >> logq, j = LF ? bf >> logW : bf & (q - 1);
+      const C* L = buf + line * LS;
+#pragma unroll
+      for (int r = 0; r < RX; ++r) {
+        if constexpr (FROM) {
+          if (!ld(line, j + r * q, v[i][r])) v[i][r] = cmk<C>(0, 0);
+        } else {
+          v[i][r] = L[lds_at(j + r * q)];
+        }
       }
-    }
-    __syncthreads();
+      const int k = j & (Ns - 1);
+      if (Ns > 1) {
 #pragma unroll
-    for (int i = 0; i < 2 * PB4; ++i) {
-      const int bf = tid + i * nth;
-      if (bf < nbf) {
-        const int line = bf / half, j = bf - line * half;
-        C* L = buf + line * LS;
-        L[lds_at(2 * j)] = cadd(a[i], b[i]);
-        L[lds_at(2 * j + 1)] = csub(a[i], b[i]);
-      }
-    }
-    __syncthreads();
-    Ns = 2;
-    rem -= 1;
-  }
-  if (rem & 2) {
-    const int q = K >> 2, nbf = W * q;
-    const int stride = K / (4 * Ns);
-    C v[PB4][4];
-#pragma unroll
-    for (int i = 0; i < PB4; ++i) {
-      const int bf = tid + i * nth;
-      if (bf < nbf) {
-        const int line = bf / q, j = bf - line * q;
-        const C* L = buf + line * LS;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[i][r] = L[lds_at(j + r * q)];
-        const int k = j & (Ns - 1);
-#pragma unroll
-        for (int r = 1; r < 4; ++r) {
+        for (int r = 1; r < RX; ++r) {
           C w = tw[k * r * stride];
           if (INV) w = cconj(w);
           v[i][r] = cmul(v[i][r], w);
         }
+      }
+      if constexpr (RX == 16) {
+        dft16<C, INV>(v[i]);
+      } else if constexpr (RX == 4) {
         dft4<C, INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
+      } else {
+        const C a0 = v[i][0];
+        v[i][0] = cadd(a0, v[i][1]);
+        v[i][1] = csub(a0, v[i][1]);
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PB4; ++i) {
-      const int bf = tid + i * nth;
-      if (bf < nbf) {
-        const int line = bf / q, j = bf - line * q;
-        const int k = j & (Ns - 1);
-        C* L = buf + line * LS;
-        const int idxD = (j - k) * 4 + k;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) L[lds_at(idxD + r * Ns)] = v[i][r];
-      }
-    }
-    __syncthreads();
-    Ns *= 4;
-    rem -= 2;
   }
-  // radix 16: W K / 16 <= blockDim.x butterflies (one per thread at most)
-  const int q = K >= 16 ? K >> 4 : 1, nbf = rem > 0 ? W * q : 0;
-  const int bf = tid;
-  const int line = bf / q, j = bf - line * q;
-  for (; rem > 0; rem -= 4, Ns *= 16) {
-    const int stride = K / (16 * Ns);
-    C v[16];
-    const int k = j & (Ns - 1);
-    if (bf < nbf) {
-      const C* L = buf + line * LS;
+  if constexpr (!FROM && !TO) __syncthreads();   // in place: every read done before the writes
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = L[lds_at(j + r * q)];
-#pragma unroll
-      for (int r = 1; r < 16; ++r) {
-        C w = tw[k * r * stride];
-        if (INV) w = cconj(w);
-        v[r] = cmul(v[r], w);
-      }
-      dft16<C, INV>(v);
-    }
-    __syncthreads();
+  for (int i = 0; i < PER; ++i) {
+    const int bf = tid + i * nth;
     if (bf < nbf) {
+      const int line = LF ? bf & (W - 1) : bf >> logq, j = LF ? bf >> logW : bf & (q - 1);
+      const int k = j & (Ns - 1);
+      const int idxD = (j - k) * RX + k;
       C* L = buf + line * LS;
-      const int idxD = (j - k) * 16 + k;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) L[lds_at(idxD + r * Ns)] = v[r];
+      for (int r = 0; r < RX; ++r) {
+        if constexpr (TO) st(line, idxD + r * Ns, v[i][r]);
+        else L[lds_at(idxD + r * Ns)] = v[i][r];
+      }
     }
-    __syncthreads();
   }
 }
 
-// Butterflies per thread per radix-4 stage: W * K / 4 <= kFftThreads * PB4
-// (checked by fft_shape_ok).
-template <typename R> struct FftCfg;
-template <> struct FftCfg<float> { static constexpr int PB4 = 4; };
-template <> struct FftCfg<double> { static constexpr int PB4 = 4; };
+// Butterflies per thread per stage (checked by fft_shape_ok): radix 16 one,
+// radix 4 four, radix 2 eight.
+constexpr int kPer16 = 1, kPer4 = 4, kPer2 = 8;
+
+// The W lines' FFTs (K >= 16): ld gives the inputs, st takes the outputs.
+template <bool INV, bool LF, typename C, typename Ld, typename St>
+__device__ __forceinline__ void fft_lines(C* buf, int K, int logK, int W, int LS, const C* __restrict__ tw, Ld ld,
+                                          St st) {
+  const int n16 = logK >> 2;
+  const bool r4 = (logK & 2) != 0, r2 = (logK & 1) != 0;
+  const int nst = n16 + (r4 ? 1 : 0) + (r2 ? 1 : 0);
+  int Ns = 1;
+  for (int s = 0; s < n16; ++s, Ns *= 16) {
+    const bool first = s == 0, last = s == nst - 1;
+    if (first && last) {
+      fft_stage<16, INV, true, true, LF, kPer16>(buf, K, W, LS, Ns, tw, ld, st);
+    } else if (first) {
+      fft_stage<16, INV, true, false, LF, kPer16>(buf, K, W, LS, Ns, tw, ld, st);
+    } else if (last) {
+      fft_stage<16, INV, false, true, LF, kPer16>(buf, K, W, LS, Ns, tw, ld, st);
+    } else {
+      fft_stage<16, INV, false, false, LF, kPer16>(buf, K, W, LS, Ns, tw, ld, st);
+    }
+    if (!last) __syncthreads();
+  }
+  if (r4) {
+    if (!r2) {
+      fft_stage<4, INV, false, true, LF, kPer4>(buf, K, W, LS, Ns, tw, ld, st);
+    } else {
+      fft_stage<4, INV, false, false, LF, kPer4>(buf, K, W, LS, Ns, tw, ld, st);
+      __syncthreads();
+    }
+    Ns *= 4;
+  }
+  if (r2) fft_stage<2, INV, false, true, LF, kPer2>(buf, K, W, LS, Ns, tw, ld, st);
+}
 
 inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
 
@@ -188,9 +187,9 @@ inline int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
 // K + K/16 + 1 (the padded line plus one slot, so that neighbouring lines
 // start on different banks), small enough to give at least 256 blocks when
 // there are enough lines (one line may take up to 139 KB: FP64, K = 8192).
-// The block has W * K / 4 threads (one radix-4 butterfly each), clamped to
-// [64, 512]: for every K up to 8192 this keeps W * K / 4 <= threads * PB4
-// and W * K / 16 <= threads (one radix-16 butterfly per thread).
+// The block has W * K / 16 threads (one radix-16 butterfly each), clamped
+// to [64, 512]; W K <= 8192 for every K up to 8192, so the radix-4 and
+// radix-2 stages fit in four and eight butterflies per thread.
 template <typename R>
 inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
   const int ls = K + K / 16 + 1;
@@ -199,15 +198,16 @@ inline void lines_per_block(int K, int nlines, int* W, int* LS, int* threads) {
   while (static_cast<size_t>(2 * w) * per <= 131072 && 2 * w <= nlines && nlines / (2 * w) >= 256) w *= 2;
   *W = w;
   *LS = ls;
-  int t = w * K / 4;
+  int t = w * K / 16;
   t = t < 64 ? 64 : (t > kFftThreads ? kFftThreads : t);
   *threads = t;
 }
 
 template <typename R>
 int fft_shape_ok(int K, int W, int threads) {
-  if (static_cast<int64_t>(W) * K / 4 > static_cast<int64_t>(threads) * FftCfg<R>::PB4 ||
-      static_cast<int64_t>(W) * K / 16 > threads) {
+  const int64_t wk = static_cast<int64_t>(W) * K;
+  if (K < 16 || wk / 16 > static_cast<int64_t>(threads) * kPer16 || wk / 4 > static_cast<int64_t>(threads) * kPer4 ||
+      wk / 2 > static_cast<int64_t>(threads) * kPer2) {
     set_error("internal: FFT of %d lines of %d points needs more than %d threads", W, K, threads);
     return PR_EUNSUPPORTED;
   }
@@ -231,64 +231,32 @@ struct FftPtrs {
 
 namespace {
 
-// Moves `count` elements between global memory and LDS, element e by
-// thread e mod blockDim.x. A batch of U elements per thread issues all its
-// loads before its first store, so a thread waits for memory once per batch
-// instead of once per element.
-template <int U, typename T, typename Ld, typename St>
-__device__ __forceinline__ void batched_move(int count, Ld ld, St st) {
-  const int nth = blockDim.x;
-  for (int base = threadIdx.x; base < count; base += U * nth) {
-    T r[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = base + u * nth;
-      if (e < count) r[u] = ld(e);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = base + u * nth;
-      if (e < count) st(e, r[u]);
-    }
-  }
-}
-
-// Elements in flight per thread in the global <-> LDS moves.
-template <typename R> struct MoveCfg;
-template <> struct MoveCfg<float> { static constexpr int U = 16; };
-template <> struct MoveCfg<double> { static constexpr int U = 8; };
-
-// Forward row pass: image rows -> S Z -> FFT along u -> A. Grid columns
-// [n/2, K - n/2) of a line receive no pixel and are zeroed; the others are
-// written by the load, so the two need no barrier between them.
+// Forward row pass: image rows -> S Z -> FFT along u -> A. Element g of a
+// line is pixel (g + n/2) mod K of the image row, zero unless that is < n.
 template <typename R, bool FUSED = false>
 __global__ __launch_bounds__(kFftThreads) void fzs_rows_kernel(const R* __restrict__ x, const R* __restrict__ corr,
                                                              const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ A,
                                                              int n, int K, int logK, int W, int LS,
                                                              const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  constexpr int U = MoveCfg<R>::U;
   if constexpr (FUSED) {
     const FftPtrs<R>* m = mp + blockIdx.y;
     x = global_ptr_at(&m->x); corr = global_ptr_at(&m->corr); tw = global_ptr_at(&m->tw); A = global_ptr_at(&m->A);
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const int logn = logK - 1, h = n >> 1;
+  const int h = n >> 1;
   const int row0 = blockIdx.x * W;
   const int lines = min(W, n - row0);
-  for (int i = threadIdx.x; i < lines * n; i += blockDim.x)
-    buf[(i >> logn) * LS + lds_at(h + (i & (n - 1)))] = cmk<C>(R(0), R(0));
-  const R* xr = x + static_cast<int64_t>(row0) * n;
-  batched_move<U, R>(
-      lines * n,
-      [&](int e) { return xr[e] * corr[e & (n - 1)] * corr[row0 + (e >> logn)]; },
-      [&](int e, R v) { buf[(e >> logn) * LS + lds_at(((e & (n - 1)) - h) & (K - 1))] = cmk<C>(v, R(0)); });
-  __syncthreads();
-  fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
-  C* Ar = A + static_cast<int64_t>(row0) * K;
-  batched_move<U, C>(
-      lines * K, [&](int e) { return buf[(e >> logK) * LS + lds_at(e & (K - 1))]; }, [&](int e, C v) { Ar[e] = v; });
+  auto ld = [&](int l, int g, C& v) {
+    const int ix = (g + h) & (K - 1);
+    if (ix >= n) return false;
+    const int iy = row0 + l;
+    v = cmk<C>(x[static_cast<int64_t>(iy) * n + ix] * corr[ix] * corr[iy], R(0));
+    return true;
+  };
+  auto st = [&](int l, int g, C v) { A[static_cast<int64_t>(row0 + l) * K + g] = v; };
+  fft_lines<false, false>(buf, K, logK, lines, LS, tw, ld, st);
 }
 
 // Column groups are laid out so that blocks on one XCD (blockIdx mod 8) take
@@ -299,35 +267,32 @@ __device__ inline int xcd_group(int b, int nb) {
 }
 
 // Forward column pass: A (n nonzero rows at p mod K) -> FFT along v -> grid.
-// W (a power of two, 2^logW) columns per block; element e of a row-major
-// sweep is row e >> logW, column e & (W - 1).
+// W neighbouring columns per block; element g of a line is row
+// (g + n/2) mod K of A, zero unless that is < n.
 template <typename R, bool FUSED = false>
 __global__ __launch_bounds__(kFftThreads) void fzs_cols_kernel(const cx_t<R>* __restrict__ A,
                                                              const cx_t<R>* __restrict__ tw, cx_t<R>* __restrict__ grid,
                                                              int n, int K, int logK, int W, int LS,
                                                              const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  constexpr int U = MoveCfg<R>::U;
   if constexpr (FUSED) {
     const FftPtrs<R>* m = mp + blockIdx.y;
     A = global_ptr_at(&m->A); tw = global_ptr_at(&m->tw); grid = global_ptr_at(&m->grid);
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const int logn = logK - 1, h = n >> 1, logW = __builtin_ctz(W);
+  const int h = n >> 1;
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
-  for (int i = threadIdx.x; i < W * n; i += blockDim.x)
-    buf[(i >> logn) * LS + lds_at(h + (i & (n - 1)))] = cmk<C>(R(0), R(0));
   const C* Ac = A + kx0;
-  batched_move<U, C>(
-      n * W, [&](int e) { return Ac[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))]; },
-      [&](int e, C v) { buf[(e & (W - 1)) * LS + lds_at(((e >> logW) - h) & (K - 1))] = v; });
-  __syncthreads();
-  fft_lds<R, false, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
   C* gc = grid + kx0;
-  batched_move<U, C>(
-      K * W, [&](int e) { return buf[(e & (W - 1)) * LS + lds_at(e >> logW)]; },
-      [&](int e, C v) { gc[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))] = v; });
+  auto ld = [&](int l, int g, C& v) {
+    const int iy = (g + h) & (K - 1);
+    if (iy >= n) return false;
+    v = Ac[static_cast<int64_t>(iy) * K + l];
+    return true;
+  };
+  auto st = [&](int l, int g, C v) { gc[static_cast<int64_t>(g) * K + l] = v; };
+  fft_lines<false, true>(buf, K, logK, W, LS, tw, ld, st);
 }
 
 // Adjoint column pass: grid -> inverse FFT along v -> keep the n rows at p mod K -> A.
@@ -337,25 +302,25 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_cols_kernel(const cx_t<R>
                                                                  cx_t<R>* __restrict__ A, int n, int K, int logK,
                                                                  int W, int LS, const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  constexpr int U = MoveCfg<R>::U;
   if constexpr (FUSED) {
     const FftPtrs<R>* m = mp + blockIdx.y;
     grid = global_ptr_at(&m->grid); tw = global_ptr_at(&m->tw); A = global_ptr_at(&m->A);
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const int h = n >> 1, logW = __builtin_ctz(W);
+  const int h = n >> 1;
   const int kx0 = xcd_group(blockIdx.x, gridDim.x) * W;
   const C* gc = grid + kx0;
-  batched_move<U, C>(
-      K * W, [&](int e) { return gc[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))]; },
-      [&](int e, C v) { buf[(e & (W - 1)) * LS + lds_at(e >> logW)] = v; });
-  __syncthreads();
-  fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, W, LS, tw);
   C* Ac = A + kx0;
-  batched_move<U, C>(
-      n * W, [&](int e) { return buf[(e & (W - 1)) * LS + lds_at(((e >> logW) - h) & (K - 1))]; },
-      [&](int e, C v) { Ac[static_cast<int64_t>(e >> logW) * K + (e & (W - 1))] = v; });
+  auto ld = [&](int l, int g, C& v) {
+    v = gc[static_cast<int64_t>(g) * K + l];
+    return true;
+  };
+  auto st = [&](int l, int g, C v) {
+    const int iy = (g + h) & (K - 1);
+    if (iy < n) Ac[static_cast<int64_t>(iy) * K + l] = v;
+  };
+  fft_lines<true, true>(buf, K, logK, W, LS, tw, ld, st);
 }
 
 // Adjoint row pass: A rows -> inverse FFT along u -> crop, correct, real part.
@@ -369,7 +334,6 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>
                                                                  R rho, int n, int K, int logK, int W, int LS,
                                                                  const FftPtrs<R>* __restrict__ mp) {
   using C = cx_t<R>;
-  constexpr int U = MoveCfg<R>::U;
   if constexpr (FUSED) {   // plain adjoint only (MODE 0)
     const FftPtrs<R>* m = mp + blockIdx.y;
     A = global_ptr_at(&m->A); corr = global_ptr_at(&m->corr); tw = global_ptr_at(&m->tw);
@@ -377,32 +341,28 @@ __global__ __launch_bounds__(kFftThreads) void fzs_adj_rows_kernel(const cx_t<R>
   }
   extern __shared__ char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const int logn = logK - 1, h = n >> 1;
+  const int h = n >> 1;
   const int row0 = blockIdx.x * W;
   const int lines = min(W, n - row0);
-  const C* Ar = A + static_cast<int64_t>(row0) * K;
-  batched_move<U, C>(
-      lines * K, [&](int e) { return Ar[e]; }, [&](int e, C v) { buf[(e >> logK) * LS + lds_at(e & (K - 1))] = v; });
-  __syncthreads();
-  fft_lds<R, true, FftCfg<R>::PB4>(buf, K, logK, lines, LS, tw);
-  const int64_t o0 = static_cast<int64_t>(row0) * n;
-  // (pixel value, x_in) per element; x_in is read only by MODE 1
-  batched_move<U, C>(
-      lines * n,
-      [&](int e) {
-        const int l = e >> logn, ix = e & (n - 1);
-        const R val = buf[l * LS + lds_at((ix - h) & (K - 1))].x * corr[ix] * corr[row0 + l];
-        return cmk<C>(val, MODE == 0 ? R(0) : x_in[o0 + e]);
-      },
-      [&](int e, C v) {
-        if (MODE == 0) {
-          x_out[o0 + e] = v.x;
-        } else {
-          const R xo = v.y - rho * v.x;
-          x_out[o0 + e] = xo;
-          zbar[o0 + e] = xo > R(0) ? xo : R(0);
-        }
-      });
+  auto ld = [&](int l, int g, C& v) {
+    v = A[static_cast<int64_t>(row0 + l) * K + g];
+    return true;
+  };
+  auto st = [&](int l, int g, C v) {
+    const int ix = (g + h) & (K - 1);
+    if (ix >= n) return;
+    const int iy = row0 + l;
+    const R val = v.x * corr[ix] * corr[iy];
+    const int64_t o = static_cast<int64_t>(iy) * n + ix;
+    if (MODE == 0) {
+      x_out[o] = val;
+    } else {
+      const R xo = x_in[o] - rho * val;
+      x_out[o] = xo;
+      zbar[o] = xo > R(0) ? xo : R(0);
+    }
+  };
+  fft_lines<true, false>(buf, K, logK, lines, LS, tw, ld, st);
 }
 
 template <typename R>
