@@ -1137,8 +1137,10 @@ __global__ __launch_bounds__(kThreads) void grid_walk_kernel(GwAdjArgs<R> a) {
 // footprint covers the cell. No runs and no moments: for a handful of
 // visibilities the walk's per-item steps (clearing, segment carries, block
 // barriers, the wait for the next item's loads) cost far more than the
-// arithmetic. Blocks of four waves share the table; all four take their
-// next items together, so the block barriers stay uniform.
+// arithmetic. The weights read the table through the caches (a block would
+// otherwise copy the whole table to LDS for a few hundred lookups); the four
+// waves of a block take their next items together, so the block barriers
+// stay uniform.
 template <typename R, int J, int MODE, int LK, bool FUSED = false>
 __global__ __launch_bounds__(kThreads) void grid_small_kernel(GwAdjArgs<R> a, const int4* __restrict__ small,
                                                               int nsmall) {
@@ -1152,10 +1154,9 @@ __global__ __launch_bounds__(kThreads) void grid_small_kernel(GwAdjArgs<R> a, co
     C val;
   };
   extern __shared__ char smem_raw[];
-  R* tab = reinterpret_cast<R*>(smem_raw);
+  const R* tab = a.table;   // read through the caches: each visibility's weights once
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  Entry* ent = reinterpret_cast<Entry*>(smem_raw + align16(static_cast<size_t>(a.tlen) * sizeof(R))) + wave * 64;
-  for (int i = tid; i < a.tlen; i += kThreads) tab[i] = a.table[i];
+  Entry* ent = reinterpret_cast<Entry*>(smem_raw) + wave * 64;
   const R scale = a.scale_dev ? static_cast<R>(*a.scale_dev) : a.scale;
   R kappa_ball = 1;
   if (ADMM) kappa_ball = static_cast<R>(a.scalars[kSlotKappa]);
@@ -1247,9 +1248,9 @@ __global__ __launch_bounds__(kThreads) void grid_small_kernel(GwAdjArgs<R> a, co
 }
 
 template <typename R, int J>
-size_t small_lds_bytes(int tlen) {
+size_t small_lds_bytes() {
   struct EntrySize { int lu, lv; R wu[J], wv[J]; cx_t<R> val; };
-  return align16(static_cast<size_t>(tlen) * sizeof(R)) + static_cast<size_t>(kThreads) * sizeof(EntrySize);
+  return static_cast<size_t>(kThreads) * sizeof(EntrySize);
 }
 
 // Columns of the moments held per gridding thread (JA): FP32 keeps at most 8
@@ -1475,7 +1476,7 @@ int launch_walk(pr_phi_plan_t* p, GwAdjArgs<R>& a, hipStream_t s, int G, bool* w
 template <typename R, int J, int WMODE, int LK, bool FUSED = false>
 int launch_small(const GwAdjArgs<R>& a, const int4* small, int64_t nsmall, hipStream_t s) {
   if (nsmall <= 0) return PR_OK;
-  const size_t bytes = small_lds_bytes<R, J>(a.tlen);
+  const size_t bytes = small_lds_bytes<R, J>();
   const int64_t blocks = (nsmall + kThreads / 64 - 1) / (kThreads / 64);
   const int G = static_cast<int>(blocks < kDegridBlocks ? blocks : kDegridBlocks);
   PR_TRY(allow_lds(grid_small_kernel<R, J, WMODE, LK, FUSED>, bytes));
@@ -1757,9 +1758,11 @@ int fused_vis_build_t(FusedStages* f, Carver& c, hipStream_t s) {
   // small-item kernel (own index in .w), the others to the walk's schedule
   std::vector<int4> big, smallv;
   std::vector<int32_t> bigl;
-  const bool split = phi_walk_fits(p0);
+  // (an item goes to the small-item kernel exactly when its member's own
+  // plan sends it there, so that the results stay those of the members)
   for (size_t i = 0; i < all.size(); ++i) {
     int4 e = all[i];
+    const bool split = f->plans[item_member(e)]->nSmall > 0;
     if (split && e.z - e.y <= kSmallItem) {
       e.w = local[i];
       smallv.push_back(e);

@@ -509,8 +509,12 @@ static int build_schedules(pr_phi_plan_t* p, hipStream_t s) {
   const int Gd = static_cast<int>(n < kDegridBlocks ? n : kDegridBlocks);
   lpt_schedule(items, Gd, P2 / 2, sd, sdo);     // per item: the patch load
   // gridding: with the walk, items of at most kSmallItem visibilities go to
-  // the small-item kernel (item order, own index in .w)
-  const bool split = phi_walk_fits(p);
+  // the small-item kernel (item order, own index in .w) when there are
+  // enough of them to pay for its launch; a few hundred ride along in the
+  // walk's schedule, hidden among its blocks
+  int64_t nsmall_items = 0;
+  for (const int4& e : items) nsmall_items += e.z - e.y <= kSmallItem ? 1 : 0;
+  const bool split = phi_walk_fits(p) && nsmall_items >= kSmallSplitMin;
   for (int64_t i = 0; i < n; ++i) {
     int4 e = items[static_cast<size_t>(i)];
     if (split && e.z - e.y <= kSmallItem) {

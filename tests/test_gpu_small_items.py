@@ -1,0 +1,87 @@
+"""Plans with many small gridding items: a large grid sparsely covered, so
+that most tiles hold a few visibilities. Their items of at most 64
+visibilities are gridded by the small-item kernel (one wave per item)
+instead of the segment walk. Parity of Phi and Phi^dagger and of ADMM
+iterations (whose gridding runs the ball projection and multiplier update in
+the same kernel) against the oracle, and bitwise repeatability.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import admm, measurement as ms, wavelets as wv
+from gpu_util import DEV, make_plan, purimi, rel_l2, say, to_dev
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-12}
+N, M = 512, 20000          # K = 1024: 4096 tiles of 16 (16384 of 8), about 5 (1) visibilities each
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return purimi()
+
+
+def sparse_problem(prec, seed):
+    rng = np.random.default_rng(seed)
+    x = W.gaussian_sky(N, W.n_sources_for(N), rng)
+    dt = np.float32 if prec == "f32" else np.float64
+    uv = rng.uniform(-3.1, 3.1, (M, 2)).astype(dt)   # uniform over the grid
+    return x, uv
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("J", [2, 4])
+def test_phi_parity_with_small_items(P, prec, J):
+    say(f"small items phi prec={prec} J={J}")
+    x, uv = sparse_problem(prec, 11 + J)
+    spec = ms.PhiSpec(N, 2 * N, J, 2000)
+    plan, perm = make_plan(P, N, uv, None, J, 2000, prec)
+    rdt = torch.float32 if prec == "f32" else torch.float64
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    uv64 = uv.astype(np.float64)
+    y_gpu = plan.apply(to_dev(x, rdt)).cpu().numpy()
+    y_ref = ms.phi(x, uv64, None, spec)[perm]
+    assert rel_l2(y_gpu, y_ref) <= TOL[prec]
+    rng = np.random.default_rng(J)
+    yy = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    xa = plan.adjoint(to_dev(yy[perm], cdt)).cpu().numpy()
+    xa_ref = ms.phi_adjoint(yy, uv64, None, spec)
+    assert rel_l2(xa, xa_ref) <= TOL[prec]
+    # bitwise repeatable
+    xb = plan.adjoint(to_dev(yy[perm], cdt)).cpu().numpy()
+    assert np.array_equal(xa, xb)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_admm_parity_with_small_items(P, prec, tol):
+    """Three ADMM iterations with the same operator scale (the oracle's power
+    method, 20 steps) and gamma on both sides: the small-item kernel's ADMM
+    prologue."""
+    say(f"small items admm prec={prec}")
+    x_true, uv = sparse_problem(prec, 5)
+    spec = ms.PhiSpec(N, 2 * N, 4, 2000)
+    uv64 = uv.astype(np.float64)
+    rng = np.random.default_rng(6)
+    y0 = ms.phi(x_true, uv64, None, spec)
+    y, sigma, eps = W.add_noise(y0, W.unit_complex_noise(M, rng), 30.0)
+    nrm = ms.power_method(uv64, None, spec, iters=20)
+    gamma, iters, levels = 1e-3, 3, 3
+    phi = lambda v: ms.phi(v, uv64, None, spec) / nrm
+    phi_adj = lambda v: ms.phi_adjoint(v, uv64, None, spec) / nrm
+    S = wv.Sara(N, levels)
+    x_ref, _, _, rep_ref = admm.admm(y, phi, phi_adj, S.forward, S.adjoint, eps,
+                                     admm.AdmmParams(gamma=gamma, iters=iters), np.zeros((N, N)))
+    plan, perm = make_plan(P, N, uv, None, 4, 2000, prec)
+    pprec = P.PR_F32 if prec == "f32" else P.PR_F64
+    psi = P.PsiPlan(N, levels, 0x1FF, pprec, DEV)
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    prm = P.admm_params(eps, gamma, iters=iters, op_norm=nrm)
+    x, rep = P.admm_solve(plan, psi, to_dev(y[perm], cdt), prm)
+    assert rep.iters_done == iters and rep.nonfinite == 0
+    assert rel_l2(x.cpu().numpy(), x_ref) <= tol
+    x2, _ = P.admm_solve(plan, psi, to_dev(y[perm], cdt), prm)
+    assert torch.equal(x, x2)
