@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import admm, measurement as ms, wavelets as wv
+from oracle import admm, measurement as ms, primal_dual as pd, wavelets as wv
 from gpu_util import DEV, make_plan, purimi, rel_l2, say, to_dev
 import workloads as W
 
@@ -85,3 +85,66 @@ def test_admm_parity_with_small_items(P, prec, tol):
     assert rel_l2(x.cpu().numpy(), x_ref) <= tol
     x2, _ = P.admm_solve(plan, psi, to_dev(y[perm], cdt), prm)
     assert torch.equal(x, x2)
+
+
+@pytest.fixture(scope="module")
+def sparse_admm():
+    """The sparse problem with noise, the oracle's operator scale and gamma."""
+    x_true, uv = sparse_problem("f32", 8)      # FP32 baselines: both precisions see the same values
+    spec = ms.PhiSpec(N, 2 * N, 4, 2000)
+    uv64 = uv.astype(np.float64)
+    rng = np.random.default_rng(9)
+    y0 = ms.phi(x_true, uv64, None, spec)
+    y, sigma, eps = W.add_noise(y0, W.unit_complex_noise(M, rng), 30.0)
+    nrm = ms.power_method(uv64, None, spec, iters=20)
+    phi = lambda v: ms.phi(v, uv64, None, spec) / nrm
+    phi_adj = lambda v: ms.phi_adjoint(v, uv64, None, spec) / nrm
+    return dict(uv=uv, uv64=uv64, y=y, sigma=sigma, eps=eps, nrm=nrm, phi=phi, phi_adj=phi_adj,
+                S=wv.Sara(N, 3), gamma=1e-3)
+
+
+def _gpu(P, d, prec):
+    uv = d["uv"] if prec == "f32" else d["uv64"]
+    plan, perm = make_plan(P, N, uv, None, 4, 2000, prec)
+    psi = P.PsiPlan(N, 3, 0x1FF, P.PR_F32 if prec == "f32" else P.PR_F64, DEV)
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    return plan, perm, psi, to_dev(d["y"][perm], cdt)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_local_balls_with_small_items(P, sparse_admm, prec, tol):
+    """Four baseline-length sections: the small-item kernel's section-ball
+    prologue."""
+    say(f"small items local balls prec={prec}")
+    d = sparse_admm
+    nsec, iters = 4, 3
+    order = np.argsort(np.hypot(d["uv64"][:, 0], d["uv64"][:, 1]), kind="stable")
+    sec = np.empty(M, dtype=np.int32)
+    for j, part in enumerate(np.array_split(order, nsec)):
+        sec[part] = j
+    m = np.bincount(sec, minlength=nsec).astype(np.float64)
+    eps_j = d["sigma"] * np.sqrt(m + 2.0 * np.sqrt(m))
+    x_ref, _, _, _ = admm.admm(d["y"], d["phi"], d["phi_adj"], d["S"].forward, d["S"].adjoint, eps_j,
+                               admm.AdmmParams(gamma=d["gamma"], iters=iters), np.zeros((N, N)), sections=sec)
+    plan, perm, psi, y_plan = _gpu(P, d, prec)
+    balls = P.Balls(plan, torch.as_tensor(sec[perm]).to(DEV), nsec)
+    x, rep = P.admm_local_solve(plan, psi, balls, y_plan,
+                                P.admm_params(0.0, d["gamma"], iters=iters, op_norm=d["nrm"]), eps_j)
+    assert rep.iters_done == iters and rep.nonfinite == 0
+    assert rel_l2(x.cpu().numpy(), x_ref) <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_primal_dual_with_small_items(P, sparse_admm, prec, tol):
+    """Primal-Dual with the ball: the gridding prologue without the
+    multiplier term."""
+    say(f"small items primal-dual prec={prec}")
+    d = sparse_admm
+    iters, tau, sigma, theta = 3, 0.5, 1.0, 1.0
+    x_ref, _, _, _ = pd.primal_dual(d["y"], d["phi"], d["phi_adj"], d["S"].forward, d["S"].adjoint, d["gamma"],
+                                    tau, sigma, theta, iters, np.zeros((N, N)), misfit="ball", eps=d["eps"])
+    plan, perm, psi, y_plan = _gpu(P, d, prec)
+    x, rep = P.pd_solve(plan, psi, y_plan, P.pd_params(d["gamma"], tau, sigma, theta, iters=iters,
+                                                       misfit=P.PR_PD_BALL, eps=d["eps"], op_norm=d["nrm"]))
+    assert rep.iters_done == iters and rep.nonfinite == 0
+    assert rel_l2(x.cpu().numpy(), x_ref) <= tol
