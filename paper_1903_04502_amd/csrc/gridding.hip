@@ -131,6 +131,8 @@ struct GwArgs {
   // carries the member (tile | m << kMemberShift); the table, D and kappa of
   // the launch are shared (every member has the same kernel).
   const GwArgs* mtab;
+  const int4* small;         // the small items (not in the schedule), one wave each after the block's items
+  int nsmall;
 };
 
 constexpr int kDegridPer = 4;   // visibilities per thread per chunk
@@ -165,6 +167,20 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   };
   double sum_t = 0.0, sum_r = 0.0;
   double sacc[MODE == 2 ? kSecAcc : 1] = {};   // MODE 2: ||t||^2 per section
+  // ADMM epilogue of one visibility: t = v + s - y and the FP64 partials
+  auto admm_out = [&](int64_t k, C yk, C yo, C sk, int sj) {
+    const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
+    a.t_out[k] = t;
+    const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
+    const double t2 = tr * tr + ti * ti;
+    sum_t += t2;
+    sum_r += dr * dr + di * di;
+    if (MODE == 2) {
+#pragma unroll
+      for (int jj = 0; jj < (MODE == 2 ? kSecAcc : 1); ++jj) sacc[jj] += sj == jj ? t2 : 0.0;
+    }
+    (void)sj;
+  };
   // inputs of this thread's visibilities for the current and the next chunk
   R cu_[kDegridPer], cv_[kDegridPer], cw_[kDegridPer], nu_[kDegridPer], nv_[kDegridPer], nw_[kDegridPer];
   auto load = [&](const R* uvp, int64_t c0, int64_t cend, R* u, R* v, R* w) {
@@ -258,17 +274,7 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
         } else {
           const C yo = MODE == 2 ? yo_[MODE == 2 ? j : 0] : a.y_obs[k];
           const C sk = MODE == 2 ? sk_[MODE == 2 ? j : 0] : (a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0)));
-          const C t = cmk<C>(yk.x + sk.x - yo.x, yk.y + sk.y - yo.y);
-          a.t_out[k] = t;
-          const double tr = t.x, ti = t.y, dr = static_cast<double>(yk.x) - yo.x, di = static_cast<double>(yk.y) - yo.y;
-          const double t2 = tr * tr + ti * ti;
-          sum_t += t2;
-          sum_r += dr * dr + di * di;
-          if (MODE == 2) {
-            const int sj = sj_[MODE == 2 ? j : 0];
-#pragma unroll
-            for (int jj = 0; jj < (MODE == 2 ? kSecAcc : 1); ++jj) sacc[jj] += sj == jj ? t2 : 0.0;
-          }
+          admm_out(k, yk, yo, sk, MODE == 2 ? sj_[MODE == 2 ? j : 0] : 0);
         }
       }
 #pragma unroll
@@ -276,6 +282,60 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
         cu_[j] = nu_[j];
         cv_[j] = nv_[j];
         cw_[j] = nw_[j];
+      }
+    }
+  }
+  // The small items (plans whose gridding splits them off): one wave per
+  // item, lane l computes visibility l from the grid directly (the J^2 cells
+  // it reads are the patch values the item's block would have loaded; the
+  // same sums in the same order), with no block barrier: the waves run their
+  // items independently.
+  if (a.nsmall > 0) {
+    constexpr int kWaves = kThreads / 64;
+    const int lane = tid & 63;
+    for (int idx = static_cast<int>(blockIdx.x) * kWaves + (tid >> 6); idx < a.nsmall;
+         idx += kWaves * static_cast<int>(gridDim.x)) {
+      const int4 it = a.small[idx];
+      if (lane >= it.z - it.y) continue;
+      const GwArgs<R> m = mem(it);
+      const int K = m.K;
+      const int tile = item_tile(it);
+      const int tv = tile >> m.lognT, tu = tile & (m.nT - 1);
+      const int64_t k = static_cast<int64_t>(it.y) + lane;
+      R u, v, w;
+      vis_load<TW>(m.uv, k, u, v, w);
+      AxisTaps xu, xv;
+      int lu, lv;
+      vis_taps<TW>(u, v, m.kappa, J, a.D, K, T, tu, tv, xu, xv, lu, lv);
+      if (static_cast<unsigned>(lu) >= static_cast<unsigned>(T) || static_cast<unsigned>(lv) >= static_cast<unsigned>(T)) {
+        const R nan = R(NAN);
+        if (MODE == 0) m.y_out[k] = cmk<C>(nan, nan);
+        else a.t_out[k] = cmk<C>(nan, nan);
+        continue;
+      }
+      R wu[J], wv[J];
+      axis_weights<LIN, J>(tab, xu, a.D, a.tlen, wu);
+      axis_weights<LIN, J>(tab, xv, a.D, a.tlen, wv);
+      R accr = 0, acci = 0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        const C* row = m.grid + static_cast<int64_t>((tv * T + lv + b) & (K - 1)) * K;
+        R rr = 0, ri = 0;
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+          const C g = row[(tu * T + lu + q) & (K - 1)];
+          rr += wu[q] * g.x;
+          ri += wu[q] * g.y;
+        }
+        accr += wv[b] * rr;
+        acci += wv[b] * ri;
+      }
+      const R ws = w * (FUSED ? m.scale : scale);
+      const C yk = cmk<C>(accr * ws, acci * ws);
+      if (MODE == 0) {
+        m.y_out[k] = yk;
+      } else {
+        admm_out(k, yk, a.y_obs[k], a.s_in ? a.s_in[k] : cmk<C>(R(0), R(0)), MODE == 2 ? a.sec[k] : 0);
       }
     }
   }
@@ -1369,7 +1429,10 @@ __global__ void section_kappa_partials_kernel(const double* partials, int nblock
   }
 }
 
+// Degridding blocks: with small items every block also takes some after its
+// scheduled items (their offsets run to kDegridBlocks).
 int degrid_blocks(const pr_phi_plan_t* p) {
+  if (p->nSmall > 0) return kDegridBlocks;
   return static_cast<int>(p->nItems < kDegridBlocks ? p->nItems : kDegridBlocks);
 }
 
@@ -1612,6 +1675,8 @@ GwArgs<R> gw_args(pr_phi_plan_t* p, double scale) {
   }
   a.kappa = p->kappa;
   a.scale = static_cast<R>(scale);
+  a.small = p->small;
+  a.nsmall = static_cast<int>(p->nSmall);
   return a;
 }
 
@@ -1773,14 +1838,17 @@ int fused_vis_build_t(FusedStages* f, Carver& c, hipStream_t s) {
   }
   const int64_t nbig = static_cast<int64_t>(big.size());
   f->nSmall = static_cast<int64_t>(smallv.size());
-  f->Gd = static_cast<int>(total < kDegridBlocks ? total : kDegridBlocks);
+  // the degridding schedules the same items as the walk; every block then
+  // takes small items after its own (offsets for all kDegridBlocks)
+  f->Gd = f->nSmall > 0 ? kDegridBlocks : static_cast<int>(nbig < kDegridBlocks ? nbig : kDegridBlocks);
   f->Gg = static_cast<int>(nbig < kGridBlocks ? nbig : kGridBlocks);
   std::vector<int4> sd, sg;
   std::vector<int32_t> sdo, sgo;
   if (total > 0) {
-    lpt_schedule(all, f->Gd, P2 / 2, sd, sdo);
-    for (int4& e : sd) e.w = local[e.w];
-    PR_TRY_HIP(hipMemcpyAsync(f->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    lpt_schedule(big, static_cast<int>(nbig < kDegridBlocks ? nbig : kDegridBlocks), P2 / 2, sd, sdo);
+    if (f->nSmall > 0) sdo.resize(kDegridBlocks + 1, sdo.back());
+    if (!sd.empty())
+      PR_TRY_HIP(hipMemcpyAsync(f->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
     PR_TRY_HIP(hipMemcpyAsync(f->sched_d_off, sdo.data(), sdo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   }
   if (nbig > 0) {
@@ -1828,7 +1896,7 @@ int upload_args(std::vector<char>& h, std::vector<const void*>& up, void* dev, V
 
 template <typename R>
 int fused_gw_t(FusedStages* f, void* const* y, hipStream_t s) {
-  if (f->Gd == 0) return PR_OK;
+  if (f->Gd == 0) return PR_OK;   // no items at all
   using C = cx_t<R>;
   PR_TRY((upload_args<GwArgs<R>, C>(f->h_dg, f->up_dg, f->d_dg, reinterpret_cast<C* const*>(y), &GwArgs<R>::y_out, s)));
   pr_phi_plan_t* p0 = f->plans[0];
@@ -1836,6 +1904,8 @@ int fused_gw_t(FusedStages* f, void* const* y, hipStream_t s) {
   a.items = f->sched_d;
   a.sched_off = f->sched_d_off;
   a.mtab = static_cast<const GwArgs<R>*>(f->d_dg);
+  a.small = f->small;
+  a.nsmall = static_cast<int>(f->nSmall);
   return with_j(p0->J, [&](auto jj) {
     return with_lk<R>(p0, [&](auto lk) {
       return launch_degrid<R, decltype(jj)::value, 0, decltype(lk)::value, true>(p0, a, s, f->Gd);

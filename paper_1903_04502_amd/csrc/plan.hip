@@ -506,12 +506,11 @@ static int build_schedules(pr_phi_plan_t* p, hipStream_t s) {
   const int64_t P2 = static_cast<int64_t>(p->P) * p->P;
   std::vector<int4> sd, sg, big, small;
   std::vector<int32_t> sdo, sgo, bigi;
-  const int Gd = static_cast<int>(n < kDegridBlocks ? n : kDegridBlocks);
-  lpt_schedule(items, Gd, P2 / 2, sd, sdo);     // per item: the patch load
-  // gridding: with the walk, items of at most kSmallItem visibilities go to
-  // the small-item kernel (item order, own index in .w) when there are
-  // enough of them to pay for its launch; a few hundred ride along in the
-  // walk's schedule, hidden among its blocks
+  // With the walk, items of at most kSmallItem visibilities go to the
+  // small-item gridding kernel (item order, own index in .w) when there are
+  // enough of them to pay for its launch (a few hundred ride along in the
+  // walk's schedule, hidden among its blocks); the degridding then also
+  // takes them one wave per item after each block's scheduled items.
   int64_t nsmall_items = 0;
   for (const int4& e : items) nsmall_items += e.z - e.y <= kSmallItem ? 1 : 0;
   const bool split = phi_walk_fits(p) && nsmall_items >= kSmallSplitMin;
@@ -526,12 +525,15 @@ static int build_schedules(pr_phi_plan_t* p, hipStream_t s) {
     }
   }
   const int64_t nb = static_cast<int64_t>(big.size());
+  const int Gd = static_cast<int>(nb < kDegridBlocks ? nb : kDegridBlocks);
+  lpt_schedule(big, Gd, P2 / 2, sd, sdo);       // per item: the patch load
+  if (!small.empty()) sdo.resize(kDegridBlocks + 1, sdo.back());
   const int Gg = static_cast<int>(nb < kGridBlocks ? nb : kGridBlocks);
   lpt_schedule(big, Gg, P2, sg, sgo);           // per item: clearing, assembly, patch store
   for (int4& e : sg) e.w = bigi[static_cast<size_t>(e.w)];
   p->nGrid = nb;
   p->nSmall = static_cast<int64_t>(small.size());
-  PR_TRY_HIP(hipMemcpyAsync(p->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  if (!sd.empty()) PR_TRY_HIP(hipMemcpyAsync(p->sched_d, sd.data(), sd.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   PR_TRY_HIP(hipMemcpyAsync(p->sched_d_off, sdo.data(), sdo.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   if (nb > 0) {
     PR_TRY_HIP(hipMemcpyAsync(p->sched_g, sg.data(), sg.size() * sizeof(int4), hipMemcpyHostToDevice, s));
