@@ -1313,12 +1313,12 @@ size_t small_lds_bytes() {
   return static_cast<size_t>(kThreads) * sizeof(EntrySize);
 }
 
-// Columns of the moments held per gridding thread (JA): FP32 keeps at most 8
-// complex accumulators per thread for J <= 4 (two threads per segment), FP64
-// at most 8.
-template <typename R, int J> struct GridSplit;
-template <int J> struct GridSplit<float, J> { static constexpr int JA = J <= 2 ? J : (J == 6 ? 3 : 2); };
-template <int J> struct GridSplit<double, J> { static constexpr int JA = J <= 2 ? J : 2; };
+// Columns of the moments held per gridding thread (JA): all of them for
+// J <= 2, else two (2 J complex accumulators plus their parked copies). Three
+// columns at J = 6 took about 300 registers in FP32, one wave per SIMD, and
+// gridded at half the rate of two columns with a quarter of the threads idle
+// in the walk (J / 2 = 3 threads per segment, rounded up to 4).
+template <typename R, int J> struct GridSplit { static constexpr int JA = J <= 2 ? J : 2; };
 
 // Grid cell = sum of the patches of the (up to four) tiles whose patch covers
 // it, neighbour tiles first, items of a tile in order. One block per output
@@ -1576,13 +1576,17 @@ int launch_grid(pr_phi_plan_t* p, GwAdjArgs<R> a, hipStream_t s, int parts = 3) 
       return PR_EUNSUPPORTED;
     }
     a.B = B;
-    if (tab_lds) {
-      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true, LK>, bytes));
-      grid_kernel<R, J, JA, MODE, true, LK><<<G, kThreads, bytes, s>>>(a);
-    } else {
-      PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false, LK>, bytes));
-      grid_kernel<R, J, JA, MODE, false, LK><<<G, kThreads, bytes, s>>>(a);
+    if (G > 0) {
+      if (tab_lds) {
+        PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, true, LK>, bytes));
+        grid_kernel<R, J, JA, MODE, true, LK><<<G, kThreads, bytes, s>>>(a);
+      } else {
+        PR_TRY(allow_lds(grid_kernel<R, J, JA, MODE, false, LK>, bytes));
+        grid_kernel<R, J, JA, MODE, false, LK><<<G, kThreads, bytes, s>>>(a);
+      }
     }
+    if (MODE == 1 && a.sec) PR_TRY((launch_small<R, J, MODE == 1 ? 3 : MODE, LK>(a, p->small, p->nSmall, s)));
+    else PR_TRY((launch_small<R, J, MODE, LK>(a, p->small, p->nSmall, s)));
   }
   PR_TRY_LAUNCH();
   if (parts & 2) {
@@ -1605,8 +1609,6 @@ int setup_mode() {
     PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], false, LK, 0>, kLdsHard)));
     PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], true, LK, 0>, kLdsHard)));
     PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], false, LK, 0>, kLdsHard)));
-    PR_TRY((allow_lds(grid_small_kernel<R, J, WM[0], LK>, kLdsHard)));
-    PR_TRY((allow_lds(grid_small_kernel<R, J, WM[1], LK>, kLdsHard)));
     if constexpr (LK == kLkWords) {
       PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], true, LK, 16>, kLdsHard)));
       PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[0], false, LK, 16>, kLdsHard)));
@@ -1614,6 +1616,8 @@ int setup_mode() {
       PR_TRY((allow_lds(grid_walk_kernel<R, J, WM[1], false, LK, 16>, kLdsHard)));
     }
   }
+  PR_TRY((allow_lds(grid_small_kernel<R, J, MODE, LK>, kLdsHard)));
+  PR_TRY((allow_lds(grid_small_kernel<R, J, MODE == 1 ? 3 : MODE, LK>, kLdsHard)));
   PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, true, LK>, kLdsHard)));
   PR_TRY((allow_lds(grid_kernel<R, J, JA, MODE, false, LK>, kLdsHard)));
   return PR_OK;

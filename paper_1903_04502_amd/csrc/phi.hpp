@@ -68,7 +68,8 @@ constexpr int kPartialsMax = 4096;     // per-block partials, per quantity slot
 constexpr int kDegridBlocks = 2048;    // persistent degridding blocks (8 per CU); <= kPartialsMax
 constexpr int kGridBlocks = 512;       // persistent gridding blocks (2 per CU, bound by LDS)
 constexpr int kSmallItem = 64;         // items of at most this many visibilities: the small-item gridding
-constexpr int kSmallSplitMin = 2048;   // ... when a plan has at least this many of them
+constexpr int kSmallSplitMin = 2048;   // ... when a plan has at least this many of them (segment walk)
+constexpr int kSmallSplitMinLanes = 512;   // the same with the J-lane gridding (J > 4)
 constexpr int kSecAcc = 8;           // local balls: sections summed in the degridding epilogue
 constexpr int kSlotSec0 = 4;         // their per-block partials: slots kSlotSec0 .. kSlotSec0 + kSecAcc - 1
 constexpr int kPartialSlots = kSlotSec0 + kSecAcc;

@@ -362,9 +362,7 @@ static int default_tile(int J, int prec, int64_t M, int K) {
 // rounded up to a power of two, JA = moment columns per thread).
 static size_t grid_lds_min(int T, int J, int prec) {
   const size_t sr = prec == PR_F32 ? 4 : 8, sc = 2 * sr;
-  int ja;
-  if (prec == PR_F32) ja = J <= 2 ? J : (J == 6 ? 3 : 2);
-  else ja = J <= 2 ? J : 2;
+  const int ja = J <= 2 ? J : 2;
   int tpc = (J + ja - 1) / ja;
   if (tpc == 3) tpc = 4;
   const size_t ns = 256 / tpc;
@@ -506,14 +504,15 @@ static int build_schedules(pr_phi_plan_t* p, hipStream_t s) {
   const int64_t P2 = static_cast<int64_t>(p->P) * p->P;
   std::vector<int4> sd, sg, big, small;
   std::vector<int32_t> sdo, sgo, bigi;
-  // With the walk, items of at most kSmallItem visibilities go to the
-  // small-item gridding kernel (item order, own index in .w) when there are
-  // enough of them to pay for its launch (a few hundred ride along in the
-  // walk's schedule, hidden among its blocks); the degridding then also
-  // takes them one wave per item after each block's scheduled items.
+  // Items of at most kSmallItem visibilities go to the small-item gridding
+  // kernel (item order, own index in .w) when there are enough of them to pay
+  // for its launch (with the walk a few hundred ride along in its schedule,
+  // hidden among its blocks; the J-lane kernel pays more per item); the
+  // degridding then also takes them one wave per item after each block's
+  // scheduled items.
   int64_t nsmall_items = 0;
   for (const int4& e : items) nsmall_items += e.z - e.y <= kSmallItem ? 1 : 0;
-  const bool split = phi_walk_fits(p) && nsmall_items >= kSmallSplitMin;
+  const bool split = nsmall_items >= (phi_walk_fits(p) ? kSmallSplitMin : kSmallSplitMinLanes);
   for (int64_t i = 0; i < n; ++i) {
     int4 e = items[static_cast<size_t>(i)];
     if (split && e.z - e.y <= kSmallItem) {

@@ -1,7 +1,8 @@
 """Plans with many small gridding items: a large grid sparsely covered, so
 that most tiles hold a few visibilities. Their items of at most 64
 visibilities are gridded by the small-item kernel (one wave per item)
-instead of the segment walk. Parity of Phi and Phi^dagger and of ADMM
+instead of the segment walk (J <= 4) or the J-lane gridding (J = 6).
+Parity of Phi and Phi^dagger and of ADMM
 iterations (whose gridding runs the ball projection and multiplier update in
 the same kernel) against the oracle, and bitwise repeatability.
 """
@@ -34,7 +35,7 @@ def sparse_problem(prec, seed):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("J", [2, 4])
+@pytest.mark.parametrize("J", [2, 4, 6])
 def test_phi_parity_with_small_items(P, prec, J):
     say(f"small items phi prec={prec} J={J}")
     x, uv = sparse_problem(prec, 11 + J)
@@ -56,14 +57,14 @@ def test_phi_parity_with_small_items(P, prec, J):
     assert np.array_equal(xa, xb)
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
-def test_admm_parity_with_small_items(P, prec, tol):
+@pytest.mark.parametrize("prec,tol,J", [("f64", 1e-10, 4), ("f32", 1e-4, 4), ("f64", 1e-10, 6)])
+def test_admm_parity_with_small_items(P, prec, tol, J):
     """Three ADMM iterations with the same operator scale (the oracle's power
     method, 20 steps) and gamma on both sides: the small-item kernel's ADMM
     prologue."""
-    say(f"small items admm prec={prec}")
+    say(f"small items admm prec={prec} J={J}")
     x_true, uv = sparse_problem(prec, 5)
-    spec = ms.PhiSpec(N, 2 * N, 4, 2000)
+    spec = ms.PhiSpec(N, 2 * N, J, 2000)
     uv64 = uv.astype(np.float64)
     rng = np.random.default_rng(6)
     y0 = ms.phi(x_true, uv64, None, spec)
@@ -75,7 +76,7 @@ def test_admm_parity_with_small_items(P, prec, tol):
     S = wv.Sara(N, levels)
     x_ref, _, _, rep_ref = admm.admm(y, phi, phi_adj, S.forward, S.adjoint, eps,
                                      admm.AdmmParams(gamma=gamma, iters=iters), np.zeros((N, N)))
-    plan, perm = make_plan(P, N, uv, None, 4, 2000, prec)
+    plan, perm = make_plan(P, N, uv, None, J, 2000, prec)
     pprec = P.PR_F32 if prec == "f32" else P.PR_F64
     psi = P.PsiPlan(N, levels, 0x1FF, pprec, DEV)
     cdt = torch.complex64 if prec == "f32" else torch.complex128
