@@ -291,6 +291,9 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(GwArgs<R> a) {
   // same sums in the same order), with no block barrier: the waves run their
   // items independently.
   if (a.nsmall > 0) {
+    // a block without scheduled items has passed no barrier since the table
+    // copy: every wave's part of the table must be in LDS before any is read
+    if (TAB_LDS) __syncthreads();
     constexpr int kWaves = kThreads / 64;
     const int lane = tid & 63;
     for (int idx = static_cast<int>(blockIdx.x) * kWaves + (tid >> 6); idx < a.nsmall;

@@ -160,16 +160,19 @@ int setup_job(pr_server_t* s, pr_server_t::Job* j) {
   void* x = base + j->lay.o_x;
   const int64_t n2 = static_cast<int64_t>(d.n) * d.n;
   const int G = grid_for(d.M, 256, 8192);
+  // the caller's y is read here, on the admission stream, and waited for: the
+  // caller may release it once the job is running
   if (d.prec == PR_F32) {
-    gather_cx_kernel<float><<<G, 256, 0, js>>>(static_cast<const float2*>(d.y), j->phi->perm, d.M,
-                                               static_cast<float2*>(yplan));
+    gather_cx_kernel<float><<<G, 256, 0, s->adm>>>(static_cast<const float2*>(d.y), j->phi->perm, d.M,
+                                                   static_cast<float2*>(yplan));
     zero_real_kernel<float><<<grid_for(n2, 256, 4096), 256, 0, js>>>(static_cast<float*>(x), n2);
   } else {
-    gather_cx_kernel<double><<<G, 256, 0, js>>>(static_cast<const double2*>(d.y), j->phi->perm, d.M,
-                                                static_cast<double2*>(yplan));
+    gather_cx_kernel<double><<<G, 256, 0, s->adm>>>(static_cast<const double2*>(d.y), j->phi->perm, d.M,
+                                                    static_cast<double2*>(yplan));
     zero_real_kernel<double><<<grid_for(n2, 256, 4096), 256, 0, js>>>(static_cast<double*>(x), n2);
   }
   PR_TRY_LAUNCH();
+  PR_TRY_HIP(hipStreamSynchronize(s->adm));
   PR_TRY(admm_job_init(&j->job, j->phi, j->psi, yplan, x, base + j->lay.o_admm, d.params, js));
   PR_TRY(admm_device_setup(&j->job, js));
   PR_TRY_HIP(hipEventCreateWithFlags(&j->ready, hipEventDisableTiming));

@@ -179,3 +179,25 @@ def test_fused_batch_with_small_item_members(P):
     for ch, yb, xb in zip(chs, ys, xs):
         assert torch.equal(yb, ch["plan"].apply(ch["x"])), (ch["n"], ch["M"])
         assert torch.equal(xb, ch["plan"].adjoint(yb)), (ch["n"], ch["M"])
+
+
+def test_degridding_blocks_without_scheduled_items(P):
+    """One dense tile among thousands of sparse ones: the plan has a single
+    item of more than 64 visibilities, so all degridding blocks but one
+    have no scheduled item and go straight to the small items after copying
+    the kernel table into LDS (which they must wait for). Phi against the
+    oracle, then repeated applications bitwise equal."""
+    say("degridding blocks without scheduled items")
+    n, m_sparse, m_dense = 512, 12000, 100
+    rng = np.random.default_rng(77)
+    x = W.gaussian_sky(n, W.n_sources_for(n), rng)
+    cell = 2 * np.pi / (2 * n)                       # one grid cell in radians per pixel
+    dense = 1.0 + rng.uniform(0.0, 4 * cell, (m_dense, 2))
+    uv = np.concatenate([rng.uniform(-3.1, 3.1, (m_sparse, 2)), dense]).astype(np.float32)
+    spec = ms.PhiSpec(n, 2 * n, 4, 2000)
+    plan, perm = make_plan(P, n, uv, None, 4, 2000, "f32")
+    xd = to_dev(x, torch.float32)
+    y = plan.apply(xd)
+    assert rel_l2(y.cpu().numpy(), ms.phi(x, uv.astype(np.float64), None, spec)[perm]) <= TOL["f32"]
+    for _ in range(20):
+        assert torch.equal(plan.apply(xd), y)
