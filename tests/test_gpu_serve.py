@@ -217,3 +217,27 @@ def test_nonfinite_data_is_flagged(P, bad):
     y_bad[1234] = complex(bad, 0.0)
     _, rep = P.admm_solve(plan, psi, y_bad, prm)
     assert rep.nonfinite != 0
+
+
+def test_data_may_change_once_the_job_runs(P):
+    """uv, w and y must stay valid only until the job is running: the server
+    has read them by then. Overwriting y right after admission leaves the
+    served image unchanged."""
+    say("serve: y overwritten once running")
+    a = request(P, *JOBS[0])
+    srv = P.Server(1 << 30, max_active=8, nstreams=4)
+    ja = srv.submit(a["desc"], keep=(a["uv_d"], a["y_d"]))
+    drain(srv, [ja])
+    x_ref, _ = srv.fetch(ja, a["n"])
+    y_tmp = a["y_d"].clone()
+    uv_tmp = a["uv_d"].clone()
+    desc = P.job_desc(a["n"], uv_tmp, y_tmp, a["prm"], levels=3)
+    jb = srv.submit(desc, keep=(uv_tmp, y_tmp))
+    while srv.state(jb) < 1:
+        srv.tick()
+    y_tmp.fill_(float("nan"))
+    uv_tmp.fill_(float("nan"))
+    drain(srv, [jb])
+    x_b, rep_b = srv.fetch(jb, a["n"])
+    assert rep_b.nonfinite == 0
+    assert torch.equal(x_b, x_ref)
