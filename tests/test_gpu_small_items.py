@@ -6,6 +6,8 @@ Parity of Phi and Phi^dagger and of ADMM
 iterations (whose gridding runs the ball projection and multiplier update in
 the same kernel) against the oracle, and bitwise repeatability.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -88,11 +90,11 @@ def test_admm_parity_with_small_items(P, prec, tol, J):
     assert torch.equal(x, x2)
 
 
-@pytest.fixture(scope="module")
-def sparse_admm():
+@functools.lru_cache(maxsize=None)
+def _sparse_admm(J):
     """The sparse problem with noise, the oracle's operator scale and gamma."""
     x_true, uv = sparse_problem("f32", 8)      # FP32 baselines: both precisions see the same values
-    spec = ms.PhiSpec(N, 2 * N, 4, 2000)
+    spec = ms.PhiSpec(N, 2 * N, J, 2000)
     uv64 = uv.astype(np.float64)
     rng = np.random.default_rng(9)
     y0 = ms.phi(x_true, uv64, None, spec)
@@ -101,23 +103,29 @@ def sparse_admm():
     phi = lambda v: ms.phi(v, uv64, None, spec) / nrm
     phi_adj = lambda v: ms.phi_adjoint(v, uv64, None, spec) / nrm
     return dict(uv=uv, uv64=uv64, y=y, sigma=sigma, eps=eps, nrm=nrm, phi=phi, phi_adj=phi_adj,
-                S=wv.Sara(N, 3), gamma=1e-3)
+                S=wv.Sara(N, 3), gamma=1e-3, J=J)
+
+
+@pytest.fixture(scope="module")
+def sparse_admm():
+    return _sparse_admm(4)
 
 
 def _gpu(P, d, prec):
     uv = d["uv"] if prec == "f32" else d["uv64"]
-    plan, perm = make_plan(P, N, uv, None, 4, 2000, prec)
+    plan, perm = make_plan(P, N, uv, None, d["J"], 2000, prec)
     psi = P.PsiPlan(N, 3, 0x1FF, P.PR_F32 if prec == "f32" else P.PR_F64, DEV)
     cdt = torch.complex64 if prec == "f32" else torch.complex128
     return plan, perm, psi, to_dev(d["y"][perm], cdt)
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
-def test_local_balls_with_small_items(P, sparse_admm, prec, tol):
+@pytest.mark.parametrize("prec,tol,J", [("f64", 1e-10, 4), ("f32", 1e-4, 4), ("f64", 1e-10, 6)])
+def test_local_balls_with_small_items(P, prec, tol, J):
     """Four baseline-length sections: the small-item kernel's section-ball
-    prologue."""
-    say(f"small items local balls prec={prec}")
-    d = sparse_admm
+    prologue (after the segment walk at J = 4, after the J-lane gridding at
+    J = 6)."""
+    say(f"small items local balls prec={prec} J={J}")
+    d = _sparse_admm(J)
     nsec, iters = 4, 3
     order = np.argsort(np.hypot(d["uv64"][:, 0], d["uv64"][:, 1]), kind="stable")
     sec = np.empty(M, dtype=np.int32)
