@@ -44,11 +44,11 @@ __global__ void dwt_rows_kernel(const R* __restrict__ src, int64_t src_basis_str
   const Filt<R>& f = filt[bi];
   const R* in = src + bi * src_basis_stride;
   R* out = rows + bi * n2;
-  const int half = L >> 1;
-  const int64_t total = static_cast<int64_t>(L) * half;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const int r = static_cast<int>(i / half), m = static_cast<int>(i - static_cast<int64_t>(r) * half);
+  // L is a power of two and L^2 < 2^31: 32-bit positions, shifts and masks
+  const int half = L >> 1, lgh = __builtin_ctz(half);
+  const int total = L * half;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
+    const int r = i >> lgh, m = i & (half - 1);
     const R* row = in + static_cast<int64_t>(r) * ld_src;
     R lo = 0, hi = 0;
 #pragma unroll
@@ -76,11 +76,10 @@ __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, i
   R* cb = coef + bi * n2;
   const R* wb = wts ? wts + bi * n2 : nullptr;   // per-coefficient l1 weights (MODE 1)
   R* llb = ll_out ? ll_out + bi * (n2 / 4) : nullptr;
-  const int half = L >> 1;
-  const int64_t total = static_cast<int64_t>(half) * L;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const int m = static_cast<int>(i / L), c = static_cast<int>(i - static_cast<int64_t>(m) * L);
+  const int half = L >> 1, lgL = __builtin_ctz(L);
+  const int total = half * L;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
+    const int m = i >> lgL, c = i & (L - 1);
     R lo = 0, hi = 0;
 #pragma unroll
     for (int q = 0; q < kTapsMax; ++q) {
@@ -126,11 +125,10 @@ __global__ void idwt_cols_kernel(const R* __restrict__ coef, int64_t n2, int n, 
   const R* cb = coef + bi * n2;
   const R* ll = ll_src + bi * ll_basis_stride;
   R* out = rows + bi * n2;
-  const int half = L >> 1;
-  const int64_t total = static_cast<int64_t>(L) * L;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const int r = static_cast<int>(i / L), c = static_cast<int>(i - static_cast<int64_t>(r) * L);
+  const int half = L >> 1, lgL = __builtin_ctz(L);
+  const int total = L * L;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
+    const int r = i >> lgL, c = i & (L - 1);
     R acc = 0;
 #pragma unroll
     for (int q = 0; q < kTapsMax; ++q) {
@@ -152,11 +150,10 @@ __global__ void idwt_rows_kernel(const R* __restrict__ rows, int64_t n2, int L, 
   const Filt<R>& f = filt[bi];
   const R* in = rows + bi * n2;
   R* out = dst + bi * dst_basis_stride;
-  const int half = L >> 1;
-  const int64_t total = static_cast<int64_t>(L) * L;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const int r = static_cast<int>(i / L), c = static_cast<int>(i - static_cast<int64_t>(r) * L);
+  const int half = L >> 1, lgL = __builtin_ctz(L);
+  const int total = L * L;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
+    const int r = i >> lgL, c = i & (L - 1);
     const R* row = in + static_cast<int64_t>(r) * L;
     R acc = 0;
 #pragma unroll
