@@ -76,30 +76,39 @@ __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, i
   R* cb = coef + bi * n2;
   const R* wb = wts ? wts + bi * n2 : nullptr;   // per-coefficient l1 weights (MODE 1)
   R* llb = ll_out ? ll_out + bi * (n2 / 4) : nullptr;
+  // two output rows per thread, m and m + 1: their input windows share all
+  // but two rows, loaded once (each output is the same sum in the same order)
   const int half = L >> 1, lgL = __builtin_ctz(L);
-  const int total = half * L;
+  const int total = (half >> 1) * L;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
-    const int m = i >> lgL, c = i & (L - 1);
-    R lo = 0, hi = 0;
+    const int m0 = (i >> lgL) * 2, c = i & (L - 1);
+    R v[kTapsMax + 2];
 #pragma unroll
-    for (int q = 0; q < kTapsMax; ++q) {
-      if (q < f.taps) {
-        const R v = in[static_cast<int64_t>((2 * m + q) & (L - 1)) * L + c];
-        lo += f.h[q] * v;
-        hi += f.g[q] * v;
+    for (int q = 0; q < kTapsMax + 2; ++q)
+      v[q] = q < f.taps + 2 ? in[static_cast<int64_t>((2 * m0 + q) & (L - 1)) * L + c] : R(0);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int m = m0 + k;
+      R lo = 0, hi = 0;
+#pragma unroll
+      for (int q = 0; q < kTapsMax; ++q) {
+        if (q < f.taps) {
+          lo += f.h[q] * v[q + 2 * k];
+          hi += f.g[q] * v[q + 2 * k];
+        }
       }
+      // low-low band goes down the chain unless this is the last level
+      if (c < half && !last) {
+        llb[static_cast<int64_t>(m) * half + c] = lo;
+      } else {
+        const int64_t o = static_cast<int64_t>(m) * n + c;
+        if (MODE == 0) cb[o] = lo * scale;
+        else cb[o] = dual_clip(cb[o], lo * scale, wb ? gamma * wb[o] : gamma, eta);
+      }
+      const int64_t o = static_cast<int64_t>(half + m) * n + c;
+      if (MODE == 0) cb[o] = hi * scale;
+      else cb[o] = dual_clip(cb[o], hi * scale, wb ? gamma * wb[o] : gamma, eta);
     }
-    // low-low band goes down the chain unless this is the last level
-    if (c < half && !last) {
-      llb[static_cast<int64_t>(m) * half + c] = lo;
-    } else {
-      const int64_t o = static_cast<int64_t>(m) * n + c;
-      if (MODE == 0) cb[o] = lo * scale;
-      else cb[o] = dual_clip(cb[o], lo * scale, wb ? gamma * wb[o] : gamma, eta);
-    }
-    const int64_t o = static_cast<int64_t>(half + m) * n + c;
-    if (MODE == 0) cb[o] = hi * scale;
-    else cb[o] = dual_clip(cb[o], hi * scale, wb ? gamma * wb[o] : gamma, eta);
   }
 }
 
@@ -412,15 +421,16 @@ int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma,
     }
     const int64_t work = static_cast<int64_t>(L) * (L / 2);
     const dim3 grid(grid_for(work, kThreads, 2048), p->ndb);
+    const dim3 grid_cols(grid_for(work / 2, kThreads, 2048), p->ndb);   // two outputs per thread
     dwt_rows_kernel<R><<<grid, kThreads, 0, s>>>(src, sstride, ld, L, rows, n2, f);
     PR_TRY_LAUNCH();
     const int last = lev == p->levels;
     R* llout = last ? nullptr : (lev & 1 ? lla : llb);
     if (mode == 0)
-      dwt_cols_kernel<R, 0><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
+      dwt_cols_kernel<R, 0><<<grid_cols, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
                                                       R(eta), nullptr);
     else
-      dwt_cols_kernel<R, 1><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
+      dwt_cols_kernel<R, 1><<<grid_cols, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
                                                       R(eta), wwave);
     PR_TRY_LAUNCH();
   }
