@@ -134,21 +134,27 @@ __global__ void idwt_cols_kernel(const R* __restrict__ coef, int64_t n2, int n, 
   const R* cb = coef + bi * n2;
   const R* ll = ll_src + bi * ll_basis_stride;
   R* out = rows + bi * n2;
+  // output rows 2p (even taps) and 2p + 1 (odd taps) read the same band
+  // rows m = p - j: one thread forms both from one load of each (each
+  // output is the same sum in the same order)
   const int half = L >> 1, lgL = __builtin_ctz(L);
-  const int total = L * L;
+  const int total = half * L;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
-    const int r = i >> lgL, c = i & (L - 1);
-    R acc = 0;
+    const int p = i >> lgL, c = i & (L - 1);
+    R acc0 = 0, acc1 = 0;
 #pragma unroll
-    for (int q = 0; q < kTapsMax; ++q) {
-      if (q < f.taps && ((q ^ r) & 1) == 0) {
-        const int m = ((r - q) & (L - 1)) >> 1;
+    for (int j = 0; j < kTapsMax / 2; ++j) {
+      const int q = 2 * j;
+      if (q < f.taps) {
+        const int m = (p - j) & (half - 1);
         const R lo = c < half ? ll[static_cast<int64_t>(m) * ld_ll + c] : cb[static_cast<int64_t>(m) * n + c];
         const R hi = cb[static_cast<int64_t>(half + m) * n + c];
-        acc += f.h[q] * lo + f.g[q] * hi;
+        acc0 += f.h[q] * lo + f.g[q] * hi;
+        if (q + 1 < f.taps) acc1 += f.h[q + 1] * lo + f.g[q + 1] * hi;
       }
     }
-    out[i] = acc;
+    out[static_cast<int64_t>(2 * p) * L + c] = acc0;
+    out[static_cast<int64_t>(2 * p + 1) * L + c] = acc1;
   }
 }
 
@@ -466,7 +472,8 @@ int synthesis_bases(pr_psi_plan_t* p, const R* coef, hipStream_t s) {
     const int64_t llstride = lev == p->levels ? n2 : n2 / 4;
     const int64_t work = static_cast<int64_t>(L) * L;
     const dim3 grid(grid_for(work, kThreads, 2048), p->ndb);
-    idwt_cols_kernel<R><<<grid, kThreads, 0, s>>>(wave, n2, n, llsrc, ldll, llstride, L, rows, f);
+    const dim3 grid_cols(grid_for(work / 2, kThreads, 2048), p->ndb);   // two output rows per thread
+    idwt_cols_kernel<R><<<grid_cols, kThreads, 0, s>>>(wave, n2, n, llsrc, ldll, llstride, L, rows, f);
     PR_TRY_LAUNCH();
     R* dst = lev == 1 ? recon : (lev & 1 ? lla : llb);
     const int64_t dstride = lev == 1 ? n2 : n2 / 4;
