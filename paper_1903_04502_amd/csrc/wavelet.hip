@@ -165,20 +165,26 @@ __global__ void idwt_rows_kernel(const R* __restrict__ rows, int64_t n2, int L, 
   const Filt<R>& f = filt[bi];
   const R* in = rows + bi * n2;
   R* out = dst + bi * dst_basis_stride;
-  const int half = L >> 1, lgL = __builtin_ctz(L);
-  const int total = L * L;
+  // outputs 2p and 2p + 1 of a row from one load of their shared band
+  // entries m = p - j (as in the column pass)
+  const int half = L >> 1, lgh = __builtin_ctz(half);
+  const int total = L * half;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
-    const int r = i >> lgL, c = i & (L - 1);
+    const int r = i >> lgh, p = i & (half - 1);
     const R* row = in + static_cast<int64_t>(r) * L;
-    R acc = 0;
+    R acc0 = 0, acc1 = 0;
 #pragma unroll
-    for (int q = 0; q < kTapsMax; ++q) {
-      if (q < f.taps && ((q ^ c) & 1) == 0) {
-        const int m = ((c - q) & (L - 1)) >> 1;
-        acc += f.h[q] * row[m] + f.g[q] * row[half + m];
+    for (int j = 0; j < kTapsMax / 2; ++j) {
+      const int q = 2 * j;
+      if (q < f.taps) {
+        const int m = (p - j) & (half - 1);
+        const R lo = row[m], hi = row[half + m];
+        acc0 += f.h[q] * lo + f.g[q] * hi;
+        if (q + 1 < f.taps) acc1 += f.h[q + 1] * lo + f.g[q + 1] * hi;
       }
     }
-    out[i] = acc;
+    out[static_cast<int64_t>(r) * L + 2 * p] = acc0;
+    out[static_cast<int64_t>(r) * L + 2 * p + 1] = acc1;
   }
 }
 
@@ -470,10 +476,9 @@ int synthesis_bases(pr_psi_plan_t* p, const R* coef, hipStream_t s) {
     const R* llsrc = lev == p->levels ? wave : ((lev + 1) & 1 ? lla : llb);
     const int ldll = lev == p->levels ? n : L / 2;
     const int64_t llstride = lev == p->levels ? n2 : n2 / 4;
-    const int64_t work = static_cast<int64_t>(L) * L;
-    const dim3 grid(grid_for(work, kThreads, 2048), p->ndb);
-    const dim3 grid_cols(grid_for(work / 2, kThreads, 2048), p->ndb);   // two output rows per thread
-    idwt_cols_kernel<R><<<grid_cols, kThreads, 0, s>>>(wave, n2, n, llsrc, ldll, llstride, L, rows, f);
+    // both passes form two outputs per thread: L^2 / 2 threads
+    const dim3 grid(grid_for(static_cast<int64_t>(L) * L / 2, kThreads, 2048), p->ndb);
+    idwt_cols_kernel<R><<<grid, kThreads, 0, s>>>(wave, n2, n, llsrc, ldll, llstride, L, rows, f);
     PR_TRY_LAUNCH();
     R* dst = lev == 1 ? recon : (lev & 1 ? lla : llb);
     const int64_t dstride = lev == 1 ? n2 : n2 / 4;
