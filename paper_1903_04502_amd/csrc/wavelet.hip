@@ -45,22 +45,29 @@ __global__ void dwt_rows_kernel(const R* __restrict__ src, int64_t src_basis_str
   const R* in = src + bi * src_basis_stride;
   R* out = rows + bi * n2;
   // L is a power of two and L^2 < 2^31: 32-bit positions, shifts and masks
-  const int half = L >> 1, lgh = __builtin_ctz(half);
-  const int total = L * half;
+  // Two outputs per thread, m and m + 1: their windows share all but two
+  // inputs, loaded once (each output is the same sum in the same order).
+  const int half = L >> 1, lgq = __builtin_ctz(half >> 1);
+  const int total = L * (half >> 1);
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
-    const int r = i >> lgh, m = i & (half - 1);
+    const int r = i >> lgq, m0 = (i & ((half >> 1) - 1)) * 2;
     const R* row = in + static_cast<int64_t>(r) * ld_src;
-    R lo = 0, hi = 0;
+    R v[kTapsMax + 2];
 #pragma unroll
-    for (int q = 0; q < kTapsMax; ++q) {
-      if (q < f.taps) {
-        const R v = row[(2 * m + q) & (L - 1)];
-        lo += f.h[q] * v;
-        hi += f.g[q] * v;
+    for (int q = 0; q < kTapsMax + 2; ++q) v[q] = q < f.taps + 2 ? row[(2 * m0 + q) & (L - 1)] : R(0);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      R lo = 0, hi = 0;
+#pragma unroll
+      for (int q = 0; q < kTapsMax; ++q) {
+        if (q < f.taps) {
+          lo += f.h[q] * v[q + 2 * k];
+          hi += f.g[q] * v[q + 2 * k];
+        }
       }
+      out[static_cast<int64_t>(r) * L + m0 + k] = lo;
+      out[static_cast<int64_t>(r) * L + half + m0 + k] = hi;
     }
-    out[static_cast<int64_t>(r) * L + m] = lo;
-    out[static_cast<int64_t>(r) * L + half + m] = hi;
   }
 }
 
@@ -431,18 +438,17 @@ int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma,
       PR_TRY_LAUNCH();
       break;
     }
-    const int64_t work = static_cast<int64_t>(L) * (L / 2);
-    const dim3 grid(grid_for(work, kThreads, 2048), p->ndb);
-    const dim3 grid_cols(grid_for(work / 2, kThreads, 2048), p->ndb);   // two outputs per thread
+    // both passes form two outputs per thread: L^2 / 4 threads
+    const dim3 grid(grid_for(static_cast<int64_t>(L) * (L / 4), kThreads, 2048), p->ndb);
     dwt_rows_kernel<R><<<grid, kThreads, 0, s>>>(src, sstride, ld, L, rows, n2, f);
     PR_TRY_LAUNCH();
     const int last = lev == p->levels;
     R* llout = last ? nullptr : (lev & 1 ? lla : llb);
     if (mode == 0)
-      dwt_cols_kernel<R, 0><<<grid_cols, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
+      dwt_cols_kernel<R, 0><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
                                                       R(eta), nullptr);
     else
-      dwt_cols_kernel<R, 1><<<grid_cols, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
+      dwt_cols_kernel<R, 1><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
                                                       R(eta), wwave);
     PR_TRY_LAUNCH();
   }
