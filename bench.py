@@ -106,6 +106,24 @@ def copy_bandwidth(dev, nbytes=1 << 31, reps=5):
     return 2.0 * nbytes / t / 1e9
 
 
+def side_pair_ms(P, plan, x, y, xg, K_steps, windows=3):
+    """ms per (Phi, Phi^dagger) pair of a side configuration: the median of a
+    few windows of K pairs, each between two events (one host stall inside a
+    single window would otherwise decide the figure)."""
+    import torch
+    ts = []
+    for _ in range(windows):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K_steps):
+            P.pr_phi_apply(plan.handle, x, y)
+            P.pr_phi_adjoint(plan.handle, y, xg)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / K_steps)
+    return float(np.median(ts))
+
+
 def run_linear(P, dev, n, J, D, uv32, x_true, K_steps, W_steps, with_oracle):
     """The same workload with first-order (linear) kernel lookup, FP32."""
     import torch
@@ -117,14 +135,7 @@ def run_linear(P, dev, n, J, D, uv32, x_true, K_steps, W_steps, with_oracle):
         P.pr_phi_apply(plan.handle, x, y)
         P.pr_phi_adjoint(plan.handle, y, xg)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(K_steps):
-        P.pr_phi_apply(plan.handle, x, y)
-        P.pr_phi_adjoint(plan.handle, y, xg)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / K_steps
+    t = side_pair_ms(P, plan, x, y, xg, K_steps)
     out = {"interp": "linear (first order)", "phi_pair_ms": t, "vis_per_s": plan.M / (t * 1e-3)}
     if with_oracle:
         from oracle import measurement as ms
@@ -197,14 +208,7 @@ def run_j6(P, dev, n, D, L, uv32, x_true, K_steps, W_steps, with_oracle):
         P.pr_phi_apply(plan.handle, x, y)
         P.pr_phi_adjoint(plan.handle, y, xg)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(K_steps):
-        P.pr_phi_apply(plan.handle, x, y)
-        P.pr_phi_adjoint(plan.handle, y, xg)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / K_steps
+    t = side_pair_ms(P, plan, x, y, xg, K_steps)
     op_norm = plan.norm(100)
     gamma = 1e-3 * float(psi.adjoint(plan.adjoint(y) / op_norm).abs().max().item())
     eps = 0.05 * float(torch.linalg.vector_norm(y).item()) / op_norm
@@ -214,6 +218,7 @@ def run_j6(P, dev, n, D, L, uv32, x_true, K_steps, W_steps, with_oracle):
                     want_report=False)
     xa.zero_()
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     P.pr_admm_solve(plan.handle, psi.handle, y, P.admm_params(eps, gamma, iters=K_steps, op_norm=op_norm), xa, ws,
                     want_report=False)
