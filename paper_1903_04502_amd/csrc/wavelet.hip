@@ -72,7 +72,7 @@ __global__ void dwt_rows_kernel(const R* __restrict__ src, int64_t src_basis_str
 }
 
 // MODE 0: write scaled coefficients to alpha. MODE 1: dual update of d in place.
-template <typename R, int MODE>
+template <typename R, int MODE, int NO>
 __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, int n, R* __restrict__ ll_out,
                                 int last, R* __restrict__ coef, const Filt<R>* __restrict__ filt, R scale,
                                 R gamma_h, const double* __restrict__ gamma_dev, R eta, const R* __restrict__ wts) {
@@ -83,18 +83,19 @@ __global__ void dwt_cols_kernel(const R* __restrict__ rows, int64_t n2, int L, i
   R* cb = coef + bi * n2;
   const R* wb = wts ? wts + bi * n2 : nullptr;   // per-coefficient l1 weights (MODE 1)
   R* llb = ll_out ? ll_out + bi * (n2 / 4) : nullptr;
-  // two output rows per thread, m and m + 1: their input windows share all
-  // but two rows, loaded once (each output is the same sum in the same order)
+  // NO output rows per thread, m0 .. m0 + NO - 1: consecutive input windows
+  // share all but two rows, so the thread loads taps + 2 (NO - 1) rows once
+  // (each output is the same sum in the same order)
   const int half = L >> 1, lgL = __builtin_ctz(L);
-  const int total = (half >> 1) * L;
+  const int total = (half / NO) * L;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
-    const int m0 = (i >> lgL) * 2, c = i & (L - 1);
-    R v[kTapsMax + 2];
+    const int m0 = (i >> lgL) * NO, c = i & (L - 1);
+    R v[kTapsMax + 2 * (NO - 1)];
 #pragma unroll
-    for (int q = 0; q < kTapsMax + 2; ++q)
-      v[q] = q < f.taps + 2 ? in[static_cast<int64_t>((2 * m0 + q) & (L - 1)) * L + c] : R(0);
+    for (int q = 0; q < kTapsMax + 2 * (NO - 1); ++q)
+      v[q] = q < f.taps + 2 * (NO - 1) ? in[static_cast<int64_t>((2 * m0 + q) & (L - 1)) * L + c] : R(0);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < NO; ++k) {
       const int m = m0 + k;
       R lo = 0, hi = 0;
 #pragma unroll
@@ -241,6 +242,7 @@ __global__ void combine_kernel(const R* __restrict__ dirac, const R* __restrict_
 // ADMM iteration 0.18 -> 0.22 ms with levels 2..4 fused).
 constexpr int kTailThreads = 1024;
 constexpr int kTailMaxL = 64;
+constexpr int kCols4MinL = 512;   // analysis column pass: four output rows per thread from this level size
 constexpr size_t kTailLds = 2 * kTailMaxL * kTailMaxL * sizeof(double);
 
 template <typename R>
@@ -444,12 +446,20 @@ int analysis_impl(pr_psi_plan_t* p, const R* x, R* coef, int mode, double gamma,
     PR_TRY_LAUNCH();
     const int last = lev == p->levels;
     R* llout = last ? nullptr : (lev & 1 ? lla : llb);
-    if (mode == 0)
-      dwt_cols_kernel<R, 0><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
-                                                      R(eta), nullptr);
+    // the column pass forms four output rows per thread on large levels
+    const dim3 grid4(grid_for(static_cast<int64_t>(L) * (L / 8), kThreads, 2048), p->ndb);
+    if (mode == 0 && L >= kCols4MinL)
+      dwt_cols_kernel<R, 0, 4><<<grid4, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma),
+                                                          gamma_dev, R(eta), nullptr);
+    else if (mode == 0)
+      dwt_cols_kernel<R, 0, 2><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma),
+                                                         gamma_dev, R(eta), nullptr);
+    else if (L >= kCols4MinL)
+      dwt_cols_kernel<R, 1, 4><<<grid4, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma),
+                                                          gamma_dev, R(eta), wwave);
     else
-      dwt_cols_kernel<R, 1><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma), gamma_dev,
-                                                      R(eta), wwave);
+      dwt_cols_kernel<R, 1, 2><<<grid, kThreads, 0, s>>>(rows, n2, L, n, llout, last, wave, f, scale, R(gamma),
+                                                         gamma_dev, R(eta), wwave);
     PR_TRY_LAUNCH();
   }
   return PR_OK;
